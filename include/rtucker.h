@@ -1,0 +1,295 @@
+/*
+ * rtucker.h -- C ABI of the MI355X (gfx950) library for randomized Tucker
+ * compression of big dense tensors and FFCP, the CP / nonnegative CP fit
+ * computed through the compressed format.
+ *
+ * Method: G. Zhou, A. Cichocki, S. Xie, "Decomposition of Big Tensors With
+ * Low Multilinear Rank" (arXiv 1412.1885).
+ *   - rt_tucker_rand : RandTucker2i, Algorithm 3 (Section IV-A), with the
+ *                      randomized range finder of Section IV-A, steps 1-3.
+ *   - rt_ffcp        : FFCP, Algorithm 1 (Section III-B), eqs. (8), (9),
+ *                      (12)-(15).
+ *   - rt_ttm, rt_cp_fit_dense : building blocks exported for tests and for
+ *                      evaluating a CP model against the dense tensor.
+ *   - rt_mlp_*       : the learned FFCP initializer (no counterpart in the
+ *                      paper; it proposes the "initialize A" of Algorithm 1,
+ *                      line 1).
+ *
+ * Conventions shared by every entry point
+ *   - Tensors are dense, row-major (last index fastest), contiguous.
+ *   - Matrices are row-major.  A factor matrix of mode n is I_n x R.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  Arrays of per-mode device
+ *     pointers (e.g. `const float* const* U`) are HOST arrays of N device
+ *     pointers.
+ *   - All device buffers are owned by the caller.  The library allocates no
+ *     device memory: temporary storage comes from the caller's workspace,
+ *     whose size the matching *_workspace query returns.
+ *   - Work is enqueued on the caller's stream `stream` (a hipStream_t passed
+ *     as void*; NULL is the default stream) and returns without waiting.
+ *     Results and the device-side info structs are valid after the stream
+ *     is synchronized.
+ *   - Return value: RT_OK (0) or a negative rt_status.  Argument errors are
+ *     detected on the host before anything is enqueued; a message is kept
+ *     per thread and returned by rt_last_error().  No C++ exception or abort
+ *     crosses this ABI.  Conditions the device detects (non-finite input,
+ *     ridge applied to a singular Gram matrix) are reported in the info
+ *     structs, never as a return code.
+ *   - Device pointers must be 16-byte aligned (RT_ERR_INVALID_ARG otherwise).
+ */
+#ifndef RTUCKER_H
+#define RTUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_MAX_MODES 8
+#define RT_MAX_SKETCH 64 /* largest sketch width R~_n and CP rank R */
+
+typedef enum {
+  RT_OK = 0,
+  RT_ERR_INVALID_ARG = -1,
+  RT_ERR_UNSUPPORTED = -2,
+  RT_ERR_WORKSPACE = -3,
+  RT_ERR_NONFINITE = -4,
+  RT_ERR_NUMERICAL = -5,
+  RT_ERR_HIP = -6,
+  RT_ERR_NO_DEVICE = -7
+} rt_status;
+
+/* Arithmetic of the Y-streaming passes of rt_tucker_rand. */
+typedef enum {
+  RT_F32 = 0,        /* FP32 Y, FP32 products, FP32 accumulation            */
+  RT_BF16_MIXED = 1, /* FP32 Y converted once to a BF16 copy; BF16 products,
+                        FP32 accumulation (MFMA); QR/eig stay FP64           */
+  RT_F64 = 2         /* FP64 Y, FP64 everywhere                              */
+} rt_precision;
+
+/* rt_tucker_desc.flags */
+#define RT_FLAG_NO_TRUNCATE 0x1u /* return the R~-sized Q_n and G~         */
+#define RT_FLAG_BF16_INPUT 0x2u  /* RT_BF16_MIXED only: Y already holds the
+                                    BF16 copy (uint16 bit patterns); no FP32
+                                    pass and no conversion                  */
+#define RT_FLAG_GAUSS_SEIDEL 0x4u /* reserved: paper-literal loop order;
+                                     currently RT_ERR_UNSUPPORTED           */
+
+/*
+ * Problem description of rt_tucker_rand.
+ *   N              number of modes, 2..RT_MAX_MODES.
+ *   dims[n]        I_n >= 1.
+ *   ranks_tilde[n] R~_n, sketch width (the paper's R_n + p, Section IV-A),
+ *                  1 <= R~_n <= min(I_n, RT_MAX_SKETCH) so that Q_n can
+ *                  have R~_n orthonormal columns.
+ *   ranks[n]       output Tucker rank R_n, 1..R~_n (ignored with
+ *                  RT_FLAG_NO_TRUNCATE).  R~_n -> R_n truncation goes
+ *                  through the core's mode-n Gram eigenvectors.
+ *   sweeps         1 or 2: how many times the sketch loop of Algorithm 3
+ *                  runs (the paper runs it twice; the second sweep is the
+ *                  "one additional ALS-like iteration").
+ *   precision      rt_precision.
+ */
+typedef struct {
+  int32_t N;
+  int32_t sweeps;
+  int32_t precision;
+  uint32_t flags;
+  int64_t dims[RT_MAX_MODES];
+  int32_t ranks[RT_MAX_MODES];
+  int32_t ranks_tilde[RT_MAX_MODES];
+} rt_tucker_desc;
+
+/* Written by the device (caller-owned device memory). */
+typedef struct {
+  double normY2;    /* ||Y||_F^2 of the values the passes consumed (the
+                       BF16 copy in RT_BF16_MIXED), FP64 accumulation     */
+  double normG2;    /* ||G||_F^2 of the returned core                    */
+  int32_t nonfinite; /* nonzero if a NaN/Inf was seen in Y               */
+  int32_t rank_deficient; /* bit n set if Z_n had a zero Householder
+                             pivot (exact rank deficiency)               */
+  int64_t reserved[2];
+} rt_tucker_info;
+
+/* Optional intermediate outputs of rt_tucker_rand (every pointer may be
+ * NULL).  Z[s*N+n]: sweep s sketch Z_n, I_n x R~_n FP32 (FP64 for RT_F64).
+ * Q[s*N+n]: its orthonormal basis, same shape and type.  Gt: the
+ * untruncated core G~, prod R~_n, same type. */
+typedef struct {
+  void* Z[2 * RT_MAX_MODES];
+  void* Q[2 * RT_MAX_MODES];
+  void* Gt;
+} rt_tucker_trace;
+
+/*
+ * Workspace bytes rt_tucker_rand needs for this description (host only; no
+ * device work).  Returns RT_ERR_INVALID_ARG for an invalid description.
+ */
+int rt_tucker_rand_workspace(const rt_tucker_desc* desc, size_t* bytes);
+
+/*
+ * RandTucker2i (Algorithm 3, Section IV-A) on a dense tensor.
+ *
+ * For each sweep s = 1..sweeps and every mode n (Jacobi order: every mode of
+ * a sweep uses the bases of the previous sweep; sweep 1 uses Omega_p, the
+ * random initial U^(p) of Algorithm 3, line 1):
+ *     X_n = Y x_{p != n} B_p^T,    Z_n = X_(n) Omega~_n^(s),
+ *     Q_n = orth(Z_n)   (FP64 Householder QR, signs so that diag(R) >= 0)
+ * then the core G~ = Y x_1 Q_1^T ... x_N Q_N^T (Algorithm 3, line 8) and,
+ * unless RT_FLAG_NO_TRUNCATE, the truncation to R_n:
+ *     W_n = top-R_n eigenvectors of G~_(n) G~_(n)^T (descending, each
+ *           column's largest-magnitude entry positive),
+ *     U_n = Q_n W_n,   G = G~ x_n W_n^T.
+ *
+ *   Y          device; FP32 (RT_F32, RT_BF16_MIXED), FP64 (RT_F64) or BF16
+ *              bit patterns (RT_BF16_MIXED with RT_FLAG_BF16_INPUT);
+ *              I_1 x ... x I_N row-major.  Not modified.
+ *   Omega      host array of N device FP32 (FP64 for RT_F64) matrices
+ *              Omega_n, I_n x R~_n row-major (Gaussian test matrices).
+ *   Omega_t    host array of sweeps*N device matrices Omega~_n^(s) (index
+ *              s*N + n), (prod_{p != n} R~_p) x R~_n row-major; row index
+ *              is the row-major flattening of (j_p)_{p != n}, increasing p.
+ *   ws         device workspace of at least ws_bytes >= the query result.
+ *   U          host array of N device outputs, I_n x R_n (I_n x R~_n with
+ *              RT_FLAG_NO_TRUNCATE), FP32 (FP64 for RT_F64).
+ *   G          device output core, R_1 x ... x R_N, same type as U.
+ *   Ybf16      RT_BF16_MIXED without RT_FLAG_BF16_INPUT: device buffer of
+ *              prod I_n uint16 receiving the BF16 copy of Y (round to
+ *              nearest even); NULL otherwise.
+ *   info       device rt_tucker_info (may be NULL).
+ *   trace      host struct of optional device outputs (may be NULL).
+ *   stream     hipStream_t.
+ * Errors: RT_ERR_INVALID_ARG (bad description, NULL required pointer,
+ * misalignment), RT_ERR_WORKSPACE (ws_bytes too small), RT_ERR_UNSUPPORTED
+ * (flag not implemented), RT_ERR_HIP (a launch failed).
+ */
+int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
+                   const void* const* Omega, const void* const* Omega_t,
+                   void* ws, size_t ws_bytes, void* const* U, void* G,
+                   uint16_t* Ybf16, rt_tucker_info* info,
+                   const rt_tucker_trace* trace, void* stream);
+
+/* FFCP update rules (Algorithm 1, line 6). */
+typedef enum {
+  RT_ALS = 0,  /* eq. (14): A = U G_(n)(KR V) (hadamard A^T A)^{-1}        */
+  RT_HALS = 1, /* eq. (8), standard form a_r <- max(eps, a_r + (q_r -
+                  A t_r)/t_rr), columns in order, eps = 1e-16            */
+  RT_MU = 2    /* eq. (15) with 1e-16 added to the denominator          */
+} rt_update;
+
+typedef enum {
+  RT_INIT_USER = 0,  /* A_init given                                      */
+  RT_INIT_HOSVD = 1  /* V_n = top-R eigenvectors of G_(n) G_(n)^T, padded
+                        with the caller's `pad` columns when R > R_n      */
+} rt_init;
+
+/*
+ * Problem description of rt_ffcp.
+ *   N, dims[n] = I_n, ranks[n] = R_n: the Tucker format [[G; U]].
+ *   R        CP rank, 1..RT_MAX_SKETCH.
+ *   update   rt_update;  init  rt_init.
+ *   max_it   iteration cap (>= 1);  tol  stop at iteration t >= 2 when
+ *            |Fit_t - Fit_{t-1}| < tol (Section V-A rule; tol = 0 runs
+ *            exactly max_it iterations).
+ *   l1       soft-threshold level c of eq. (16) applied after each update
+ *            (0 disables).
+ *   normY2   ||[[G;U]]||^2 used by the fit; NaN (or negative) means: compute
+ *            <G, G x_n U_n^T U_n> on the device.
+ */
+typedef struct {
+  int32_t N;
+  int32_t R;
+  int32_t update;
+  int32_t init;
+  int32_t max_it;
+  int32_t reserved;
+  double tol;
+  double l1;
+  double normY2;
+  int64_t dims[RT_MAX_MODES];
+  int32_t ranks[RT_MAX_MODES];
+} rt_ffcp_desc;
+
+/* Written by the device. */
+typedef struct {
+  int32_t iterations; /* iterations run                                  */
+  int32_t converged;  /* 1 if the tolerance test stopped the loop        */
+  int32_t ridged;     /* 1 if a Cholesky failed and the ridge
+                         1e-12 tr(T)/R was added                         */
+  int32_t reserved;
+  double fit;         /* final Fit = 1 - ||Yt - Yhat|| / ||Yt||           */
+  double fit_prev;    /* fit of the previous iteration                   */
+} rt_ffcp_info;
+
+int rt_ffcp_workspace(const rt_ffcp_desc* desc, size_t* bytes);
+
+/*
+ * FFCP (Algorithm 1, Section III-B) on a Tucker format [[G; U]].
+ * Per iteration, for n = 1..N:
+ *     H_n = G_(n) [KR_{p != n} V_p]         (eq. 12-13),
+ *     Q_n = U_n H_n,  T_n = hadamard_{p != n} A_p^T A_p   (eq. 9),
+ *     A_n <- update (ALS / HALS / MU),  optional S_c (eq. 16),
+ *     columns of A_n normalized for n < N (lambda lives in A_N, eq. 2),
+ *     V_n = U_n^T A_n                       (eq. 13).
+ * Fit after mode N in closed form: ||Yt||^2 - 2 sum(H_N * V_N) +
+ * 1^T (hadamard_p A_p^T A_p) 1 (FP64).  Arithmetic is FP64 on the device;
+ * U, G, A_init are read as FP32 and the outputs written as FP32.
+ *
+ *   U        host array of N device FP32 matrices I_n x R_n.
+ *   G        device FP32 core R_1 x ... x R_N.
+ *   A_init   host array of N device FP32 I_n x R (RT_INIT_USER), else NULL.
+ *   pad      RT_INIT_HOSVD with R > R_n: host array of N device FP32
+ *            R_n x (R - R_n) matrices (entries for modes with R <= R_n are
+ *            ignored and may be NULL); NULL otherwise.
+ *   A        host array of N device FP32 outputs I_n x R, unit columns.
+ *   lambda   device FP32 output, R weights (||a_r^(N)|| before the final
+ *            normalization).
+ *   fit_trace device FP64 array of max_it entries receiving the fit of
+ *            every iteration run (may be NULL).
+ *   info     device rt_ffcp_info (may be NULL).
+ * Errors: RT_ERR_INVALID_ARG, RT_ERR_WORKSPACE, RT_ERR_HIP.
+ */
+int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
+            const float* const* A_init, const float* const* pad,
+            void* ws, size_t ws_bytes, float* const* A, float* lambda,
+            double* fit_trace, rt_ffcp_info* info, void* stream);
+
+/*
+ * Mode-n product out = X x_n M^T (the contraction the paper writes
+ * Y x_n U^T, eq. (1) and Algorithms 2-3): X viewed as [A, I, C] with
+ * A = prod_{p<n} I_p, I = I_n, C = prod_{p>n} I_p; M is I x K row-major;
+ * out is [A, K, C].  dtype: 0 = FP32, 2 = FP64 (rt_precision values).
+ * All pointers device.  K <= RT_MAX_SKETCH.  No workspace.
+ */
+int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,
+           const void* X, const void* M, void* out, void* stream);
+
+/*
+ * Fit of a CP model against a dense tensor (Section III-B definition,
+ * Fit = 1 - ||Y - Yhat|| / ||Y||) through one mode-N contraction of Y:
+ * <Y, Yhat> = sum(lambda * A_N * (Y_(N) KR_{p<N} A_p)), ||Yhat||^2 from the
+ * Gram identity eq. (9), ||Y||^2 accumulated in FP64.
+ *   Y: device FP32 tensor (desc dims/N; R from desc.R); A: host array of N
+ *   device FP32 I_n x R; lambda: device FP32 R (NULL = ones);
+ *   ws/ws_bytes from rt_cp_fit_workspace; out3: device FP64[3] receiving
+ *   {fit, ||Y||^2, <Y,Yhat>}.
+ */
+int rt_cp_fit_workspace(const rt_ffcp_desc* desc, size_t* bytes);
+int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
+                    const float* const* A, const float* lambda, void* ws,
+                    size_t ws_bytes, double* out3, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* rt_status_string(int status);
+/* Last error message of the calling thread (static per-thread buffer). */
+const char* rt_last_error(void);
+/* Library version string. */
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTUCKER_H */

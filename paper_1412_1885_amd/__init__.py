@@ -1,0 +1,15 @@
+"""Randomized Tucker compression (RandTucker2i) and FFCP on MI355X.
+
+Python binding of the C ABI in include/rtucker.h; every step of the method
+runs in the HIP library ``librtucker.so`` built by
+``python -m paper_1412_1885_amd.build``.  The library is loaded on first use
+and its absence is an error (there is no CPU fallback).
+"""
+
+from ._binding import (  # noqa: F401
+    RtError, lib, version, status_string, last_error,
+    tucker_desc, tucker_rand_workspace, tucker_rand,
+    ffcp_desc, ffcp_workspace, ffcp, ttm, cp_fit_dense,
+    rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense,
+    LIB_PATH,
+)

@@ -1,0 +1,339 @@
+"""ctypes binding of librtucker (include/rtucker.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+torch is used for device memory and the current stream.  If the library is
+not built this module raises; there is no CPU fallback.
+"""
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtucker.so")
+
+RT_MAX_MODES = 8
+RT_MAX_SKETCH = 64
+RT_F32, RT_BF16_MIXED, RT_F64 = 0, 1, 2
+RT_FLAG_NO_TRUNCATE, RT_FLAG_BF16_INPUT, RT_FLAG_GAUSS_SEIDEL = 1, 2, 4
+RT_ALS, RT_HALS, RT_MU = 0, 1, 2
+RT_INIT_USER, RT_INIT_HOSVD = 0, 1
+PRECISIONS = {"f32": RT_F32, "bf16": RT_BF16_MIXED, "f64": RT_F64}
+UPDATES = {"als": RT_ALS, "hals": RT_HALS, "mu": RT_MU}
+
+
+class TuckerDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("dims", ctypes.c_int64 * RT_MAX_MODES),
+                ("ranks", ctypes.c_int32 * RT_MAX_MODES),
+                ("ranks_tilde", ctypes.c_int32 * RT_MAX_MODES)]
+
+
+class TuckerTrace(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_void_p * (2 * RT_MAX_MODES)),
+                ("Q", ctypes.c_void_p * (2 * RT_MAX_MODES)),
+                ("Gt", ctypes.c_void_p)]
+
+
+class FfcpDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("update", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("max_it", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("l1", ctypes.c_double),
+                ("normY2", ctypes.c_double),
+                ("dims", ctypes.c_int64 * RT_MAX_MODES),
+                ("ranks", ctypes.c_int32 * RT_MAX_MODES)]
+
+
+TUCKER_INFO_DTYPE = np.dtype([("normY2", "<f8"), ("normG2", "<f8"),
+                              ("nonfinite", "<i4"), ("rank_deficient", "<i4"),
+                              ("reserved", "<i8", (2,))])
+FFCP_INFO_DTYPE = np.dtype([("iterations", "<i4"), ("converged", "<i4"),
+                            ("ridged", "<i4"), ("reserved", "<i4"),
+                            ("fit", "<f8"), ("fit_prev", "<f8")])
+
+_lib_handle = None
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load librtucker.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing; build it with "
+                "`python -m paper_1412_1885_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.rt_tucker_rand_workspace.argtypes = [ctypes.POINTER(TuckerDesc), ctypes.POINTER(sz)]
+        L.rt_tucker_rand.argtypes = [ctypes.POINTER(TuckerDesc), vp, ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp), vp,
+                                     vp, vp, ctypes.POINTER(TuckerTrace), vp]
+        L.rt_ffcp_workspace.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
+        L.rt_ffcp.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
+                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
+                              ctypes.POINTER(vp), vp, vp, vp, vp]
+        L.rt_ttm.argtypes = [i32, i64, i64, i64, i32, vp, vp, vp, vp]
+        L.rt_cp_fit_workspace.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
+        L.rt_cp_fit_dense.argtypes = [ctypes.POINTER(FfcpDesc), vp, ctypes.POINTER(vp),
+                                      vp, vp, sz, vp, vp]
+        L.rt_status_string.argtypes = [ctypes.c_int]
+        L.rt_status_string.restype = ctypes.c_char_p
+        L.rt_last_error.restype = ctypes.c_char_p
+        L.rt_version.restype = ctypes.c_char_p
+        for f in ("rt_tucker_rand_workspace", "rt_tucker_rand", "rt_ffcp_workspace",
+                  "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib_handle = L
+    return _lib_handle
+
+
+def status_string(status):
+    return lib().rt_status_string(int(status)).decode()
+
+
+def last_error():
+    return lib().rt_last_error().decode()
+
+
+def version():
+    return lib().rt_version().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise RtError(rc, last_error())
+
+
+# --------------------------------------------------------------- helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * max(1, len(tensors)))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr() if t is not None else 0
+    return arr
+
+
+def _require_device(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(256, int(nbytes)), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------- entry points
+
+def tucker_desc(dims, ranks_tilde, ranks=None, sweeps=1, precision="f32",
+                truncate=True, bf16_input=False):
+    d = TuckerDesc()
+    d.N = len(dims)
+    d.sweeps = sweeps
+    d.precision = PRECISIONS[precision]
+    d.flags = (0 if truncate else RT_FLAG_NO_TRUNCATE) | \
+        (RT_FLAG_BF16_INPUT if bf16_input else 0)
+    for n, I in enumerate(dims):
+        d.dims[n] = int(I)
+        d.ranks_tilde[n] = int(ranks_tilde[n])
+        d.ranks[n] = int(ranks[n]) if ranks is not None else int(ranks_tilde[n])
+    return d
+
+
+def tucker_rand_workspace(desc):
+    n = ctypes.c_size_t(0)
+    _check(lib().rt_tucker_rand_workspace(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
+                truncate=True, trace=False, ybf16=None, bf16_input=False,
+                dims=None, workspace=None, stream=None, sync=True):
+    """rt_tucker_rand.  Y: device tensor (float32 / float64, or int16/uint16
+    BF16 bit patterns with bf16_input).  omegas: N device matrices I_n x R~_n.
+    omega_tildes: list over sweeps of N device matrices.  Returns a dict with
+    U (list), G, and when sync, info (numpy record) and the optional trace."""
+    torch = _torch()
+    dims = list(Y.shape) if dims is None else list(dims)
+    N = len(dims)
+    rt = [int(o.shape[1]) for o in omegas]
+    desc = tucker_desc(dims, rt, ranks, sweeps, precision, truncate, bf16_input)
+    fdt = torch.float64 if precision == "f64" else torch.float32
+    _require_device(Y, "Y")
+    for n in range(N):
+        _require_device(omegas[n], f"omegas[{n}]", fdt)
+    for s in range(sweeps):
+        for n in range(N):
+            _require_device(omega_tildes[s][n], f"omega_tildes[{s}][{n}]", fdt)
+    dev = Y.device
+    out_r = [desc.ranks[n] if truncate else rt[n] for n in range(N)]
+    U = [torch.empty((dims[n], out_r[n]), dtype=fdt, device=dev) for n in range(N)]
+    G = torch.empty(out_r, dtype=fdt, device=dev)
+    if precision == "bf16" and not bf16_input and ybf16 is None:
+        ybf16 = torch.empty(dims, dtype=torch.int16, device=dev)
+    info = torch.zeros(TUCKER_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ws_bytes = tucker_rand_workspace(desc)
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes \
+        else _workspace(ws_bytes, dev)
+    tr = None
+    trace_t = None
+    if trace:
+        tr = TuckerTrace()
+        trace_t = {"Z": [], "Q": [], "Gt": torch.empty(rt, dtype=fdt, device=dev)}
+        for s in range(sweeps):
+            for n in range(N):
+                z = torch.empty((dims[n], rt[n]), dtype=fdt, device=dev)
+                q = torch.empty((dims[n], rt[n]), dtype=fdt, device=dev)
+                trace_t["Z"].append(z)
+                trace_t["Q"].append(q)
+                tr.Z[s * N + n] = z.data_ptr()
+                tr.Q[s * N + n] = q.data_ptr()
+        tr.Gt = trace_t["Gt"].data_ptr()
+    om = _ptr_array(omegas)
+    omt = _ptr_array([omega_tildes[s][n] for s in range(sweeps) for n in range(N)])
+    Uarr = _ptr_array(U)
+    _check(lib().rt_tucker_rand(ctypes.byref(desc), _ptr(Y), om, omt, _ptr(ws),
+                                ws.numel(), Uarr, _ptr(G), _ptr(ybf16), _ptr(info),
+                                ctypes.byref(tr) if tr is not None else None,
+                                _stream_handle(stream)))
+    out = {"U": U, "G": G, "ybf16": ybf16, "info_dev": info, "workspace": ws}
+    if trace:
+        out["trace"] = trace_t
+    if sync:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        out["info"] = np.frombuffer(info.cpu().numpy().tobytes(), TUCKER_INFO_DTYPE)[0]
+    return out
+
+
+def ffcp_desc(dims, ranks, R, update="als", init="user", max_it=1000, tol=1e-6,
+              l1=0.0, normY2=None):
+    d = FfcpDesc()
+    d.N = len(dims)
+    d.R = int(R)
+    d.update = UPDATES[update]
+    d.init = RT_INIT_USER if init == "user" else RT_INIT_HOSVD
+    d.max_it = int(max_it)
+    d.tol = float(tol)
+    d.l1 = float(l1)
+    d.normY2 = float("nan") if normY2 is None else float(normY2)
+    for n in range(d.N):
+        d.dims[n] = int(dims[n])
+        d.ranks[n] = int(ranks[n])
+    return d
+
+
+def ffcp_workspace(desc):
+    n = ctypes.c_size_t(0)
+    _check(lib().rt_ffcp_workspace(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
+         tol=1e-6, l1=0.0, normY2=None, fit_trace=False, workspace=None,
+         stream=None, sync=True):
+    """rt_ffcp on a Tucker format.  U: N device float32 I_n x R_n; G: device
+    float32 core.  A_init (list of device float32 I_n x R) selects the user
+    init; otherwise init="hosvd" (pad: list of R_n x (R - R_n) matrices for
+    modes with R > R_n)."""
+    torch = _torch()
+    N = len(U)
+    dims = [int(u.shape[0]) for u in U]
+    ranks = [int(u.shape[1]) for u in U]
+    if init is None:
+        init = "user" if A_init is not None else "hosvd"
+    desc = ffcp_desc(dims, ranks, R, update, init, max_it, tol, l1, normY2)
+    for n in range(N):
+        _require_device(U[n], f"U[{n}]", torch.float32)
+    _require_device(G, "G", torch.float32)
+    dev = G.device
+    A = [torch.empty((dims[n], R), dtype=torch.float32, device=dev) for n in range(N)]
+    lam = torch.empty(R, dtype=torch.float32, device=dev)
+    info = torch.zeros(FFCP_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ft = torch.zeros(max_it, dtype=torch.float64, device=dev) if fit_trace else None
+    ws_bytes = ffcp_workspace(desc)
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes \
+        else _workspace(ws_bytes, dev)
+    ainit = _ptr_array(A_init) if A_init is not None else None
+    padp = _ptr_array(pad) if pad is not None else None
+    _check(lib().rt_ffcp(ctypes.byref(desc), _ptr_array(U), _ptr(G), ainit, padp,
+                         _ptr(ws), ws.numel(), _ptr_array(A), _ptr(lam), _ptr(ft),
+                         _ptr(info), _stream_handle(stream)))
+    out = {"A": A, "lam": lam, "info_dev": info, "fit_trace_dev": ft}
+    if sync:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]
+        out["info"] = inf
+        if ft is not None:
+            out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
+    return out
+
+
+def ttm(X, M, n, stream=None):
+    """rt_ttm: X x_n M^T for a device tensor X and device matrix M (I_n x K)."""
+    torch = _torch()
+    _require_device(X, "X")
+    _require_device(M, "M", X.dtype)
+    shape = list(X.shape)
+    A = int(np.prod(shape[:n])) if n > 0 else 1
+    C = int(np.prod(shape[n + 1:])) if n + 1 < len(shape) else 1
+    K = int(M.shape[1])
+    out = torch.empty(shape[:n] + [K] + shape[n + 1:], dtype=X.dtype, device=X.device)
+    dt = RT_F64 if X.dtype == torch.float64 else RT_F32
+    _check(lib().rt_ttm(dt, A, shape[n], C, K, _ptr(X), _ptr(M), _ptr(out),
+                        _stream_handle(stream)))
+    return out
+
+
+def cp_fit_dense(Y, A, lam=None, stream=None):
+    """rt_cp_fit_dense: (fit, ||Y||^2, <Y, Yhat>) of a CP model against Y."""
+    torch = _torch()
+    _require_device(Y, "Y", torch.float32)
+    dims = list(Y.shape)
+    R = int(A[0].shape[1])
+    desc = ffcp_desc(dims, [1] * len(dims), R)
+    n = ctypes.c_size_t(0)
+    _check(lib().rt_cp_fit_workspace(ctypes.byref(desc), ctypes.byref(n)))
+    ws = _workspace(n.value, Y.device)
+    out3 = torch.zeros(4, dtype=torch.float64, device=Y.device)
+    _check(lib().rt_cp_fit_dense(ctypes.byref(desc), _ptr(Y), _ptr_array(A), _ptr(lam),
+                                 _ptr(ws), ws.numel(), _ptr(out3), _stream_handle(stream)))
+    torch.cuda.current_stream().synchronize()
+    v = out3.cpu().numpy()
+    return float(v[0]), float(v[1]), float(v[2])
+
+
+# names of the C ABI
+rt_tucker_rand = tucker_rand
+rt_ffcp = ffcp
+rt_ttm = ttm
+rt_cp_fit_dense = cp_fit_dense

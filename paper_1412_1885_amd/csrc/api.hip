@@ -1,0 +1,793 @@
+// C ABI of librtucker (declared in include/rtucker.h): argument validation,
+// workspace planning and the launch sequence of RandTucker2i and FFCP.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/rtucker.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "stream.hpp"
+
+namespace rt {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("HIP error in %s: %s", what, hipGetErrorString(e));
+  return kErrHip;
+}
+
+namespace {
+
+bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+int check_ptr(const void* p, const char* name) {
+  if (!p) {
+    set_error("%s is NULL", name);
+    return kErrInvalid;
+  }
+  if (!aligned16(p)) {
+    set_error("%s is not 16-byte aligned", name);
+    return kErrInvalid;
+  }
+  return kOk;
+}
+
+#define RT_TRY(x)             \
+  do {                        \
+    int _rc = (x);            \
+    if (_rc != kOk) return _rc; \
+  } while (0)
+
+// ------------------------------------------------------------ tucker_rand
+
+int validate_tucker(const rt_tucker_desc* d) {
+  if (!d) {
+    set_error("desc is NULL");
+    return kErrInvalid;
+  }
+  if (d->N < 2 || d->N > RT_MAX_MODES) {
+    set_error("N=%d outside 2..%d", d->N, RT_MAX_MODES);
+    return kErrInvalid;
+  }
+  if (d->sweeps < 1 || d->sweeps > 2) {
+    set_error("sweeps=%d (must be 1 or 2)", d->sweeps);
+    return kErrInvalid;
+  }
+  if (d->precision != RT_F32 && d->precision != RT_BF16_MIXED &&
+      d->precision != RT_F64) {
+    set_error("unknown precision %d", d->precision);
+    return kErrInvalid;
+  }
+  if (d->flags & ~(RT_FLAG_NO_TRUNCATE | RT_FLAG_BF16_INPUT | RT_FLAG_GAUSS_SEIDEL)) {
+    set_error("unknown flag bits 0x%x", d->flags);
+    return kErrInvalid;
+  }
+  if (d->flags & RT_FLAG_GAUSS_SEIDEL) {
+    set_error("Gauss-Seidel sweep order is not implemented");
+    return kErrUnsupported;
+  }
+  if ((d->flags & RT_FLAG_BF16_INPUT) && d->precision != RT_BF16_MIXED) {
+    set_error("RT_FLAG_BF16_INPUT requires RT_BF16_MIXED");
+    return kErrInvalid;
+  }
+  int64_t total = 1;
+  int64_t core = 1;
+  for (int n = 0; n < d->N; ++n) {
+    const int64_t I = d->dims[n];
+    const int rt = d->ranks_tilde[n];
+    if (I < 1) {
+      set_error("dims[%d]=%lld < 1", n, (long long)I);
+      return kErrInvalid;
+    }
+    if (rt < 1 || rt > RT_MAX_SKETCH || rt > I) {
+      set_error("ranks_tilde[%d]=%d outside 1..min(I_n=%lld, %d)", n, rt,
+                (long long)I, RT_MAX_SKETCH);
+      return kErrInvalid;
+    }
+    if (!(d->flags & RT_FLAG_NO_TRUNCATE)) {
+      if (d->ranks[n] < 1 || d->ranks[n] > rt) {
+        set_error("ranks[%d]=%d outside 1..R~_n=%d", n, d->ranks[n], rt);
+        return kErrInvalid;
+      }
+    }
+    if (total > (int64_t(1) << 62) / I) {
+      set_error("tensor size overflows 64 bits");
+      return kErrInvalid;
+    }
+    total *= I;
+    core *= rt;
+  }
+  if (core > (int64_t(1) << 26)) {
+    set_error("sketch core prod R~_n = %lld too large", (long long)core);
+    return kErrUnsupported;
+  }
+  return kOk;
+}
+
+template <typename T>
+struct TuckerPlan {
+  int N;
+  int64_t I[RT_MAX_MODES];
+  int K[RT_MAX_MODES];
+  int Rn[RT_MAX_MODES];
+  int64_t total, core, core_out;
+  int64_t sizeTA, sizeTB, chain;
+  // workspace carves
+  double* partial;
+  double* scal;   // [0] normY2 [1] normG2
+  int32_t* iflags; // [0] nonfinite [1] rank
+  T* TA;
+  T* TB;
+  T* X0;
+  T* X1;
+  T* Z[RT_MAX_MODES];
+  T* Q[RT_MAX_MODES];
+  double* qrwork[RT_MAX_MODES];
+  T* Gt;
+  T* Gtmp;
+  double* gram[RT_MAX_MODES];
+  double* W[RT_MAX_MODES];
+  T* WT[RT_MAX_MODES];
+  uint16_t* stream_scratch;
+  size_t stream_bytes;
+  void* stream_ws;
+
+  size_t plan(const rt_tucker_desc* d, void* ws) {
+    Arena ar(ws);
+    N = d->N;
+    total = 1;
+    core = 1;
+    core_out = 1;
+    const bool trunc = !(d->flags & RT_FLAG_NO_TRUNCATE);
+    for (int n = 0; n < N; ++n) {
+      I[n] = d->dims[n];
+      K[n] = d->ranks_tilde[n];
+      Rn[n] = trunc ? d->ranks[n] : K[n];
+      total *= I[n];
+      core *= K[n];
+      core_out *= Rn[n];
+    }
+    const int last = N - 1, second = N - 2;
+    sizeTA = total / I[last] * K[last];
+    sizeTB = total / I[second] * K[second];
+    chain = sizeTA > sizeTB ? sizeTA : sizeTB;
+    partial = ar.take<double>(norm2_blocks());
+    scal = ar.take<double>(8);
+    iflags = ar.take<int32_t>(8);
+    TA = ar.take<T>(sizeTA);
+    TB = ar.take<T>(sizeTB);
+    X0 = ar.take<T>(chain);
+    X1 = ar.take<T>(chain);
+    for (int n = 0; n < N; ++n) {
+      Z[n] = ar.take<T>(I[n] * K[n]);
+      Q[n] = ar.take<T>(I[n] * K[n]);
+      qrwork[n] = ar.take<double>(2 * I[n] * K[n]);
+      gram[n] = ar.take<double>(K[n] * K[n]);
+      W[n] = ar.take<double>(K[n] * K[n]);
+      WT[n] = ar.take<T>(K[n] * K[n]);
+    }
+    Gt = ar.take<T>(core);
+    Gtmp = ar.take<T>(core);
+    stream_bytes = stream_workspace_bytes(d);
+    stream_ws = ar.take<char>(stream_bytes);
+    return ar.need;
+  }
+};
+
+// X_n = base x_{p in modes} B_p^T, contracting in increasing p; dims `D`
+// are updated in place.  Returns the buffer holding the result.
+template <typename T>
+int contract_chain(const T* base, int64_t* D, int N, const int* modes,
+                   int nmodes, const T* const* B, const int* K, T* buf0,
+                   T* buf1, const T** result, hipStream_t s) {
+  const T* src = base;
+  T* bufs[2] = {buf0, buf1};
+  int cur = 0;
+  for (int q = 0; q < nmodes; ++q) {
+    const int p = modes[q];
+    int64_t Apre = 1, Cpost = 1;
+    for (int r = 0; r < p; ++r) Apre *= D[r];
+    for (int r = p + 1; r < N; ++r) Cpost *= D[r];
+    RT_TRY(launch_ttm<T>(src, B[p], bufs[cur], Apre, D[p], Cpost, K[p], s));
+    D[p] = K[p];
+    src = bufs[cur];
+    cur ^= 1;
+  }
+  *result = src;
+  return kOk;
+}
+
+template <typename T>
+int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
+               const void* const* Omt, void* ws, size_t ws_bytes,
+               void* const* Uout, void* Gout, uint16_t* Ybf16,
+               rt_tucker_info* info, const rt_tucker_trace* trace,
+               hipStream_t s) {
+  TuckerPlan<T> P;
+  const size_t need = P.plan(d, ws);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return kErrWorkspace;
+  }
+  const int N = P.N, last = N - 1, second = N - 2;
+  const bool mixed = d->precision == RT_BF16_MIXED;
+  RT_TRY(launch_fill_i32(P.iflags, 0, 8, s));
+
+  // ||Y||^2 and the non-finite flag (of the values the passes consume)
+  if (!mixed) {
+    RT_TRY(launch_norm2<T>(static_cast<const T*>(Yv), P.total, P.partial,
+                           norm2_blocks(), P.scal + 0, P.iflags + 0, s));
+  }
+
+  const T* B[RT_MAX_MODES];
+  for (int n = 0; n < N; ++n) B[n] = static_cast<const T*>(Om[n]);
+  StreamCtx sc = make_stream_ctx(d, Yv, Ybf16, P.stream_ws, P.stream_bytes);
+
+  for (int sw = 0; sw < d->sweeps; ++sw) {
+    // streamed pass: TA = Y x_last B_last^T, TB = Y x_second B_second^T
+    RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second],
+                          P.K[second], P.TA, P.TB, s));
+    if (mixed && sw == 0) {
+      RT_TRY(launch_norm2_bf16(sc.ybf16, P.total, P.partial, norm2_blocks(),
+                               P.scal + 0, P.iflags + 0, s));
+    }
+    for (int n = 0; n < N; ++n) {
+      int64_t D[RT_MAX_MODES];
+      int modes[RT_MAX_MODES], nm = 0;
+      const T* base;
+      for (int p = 0; p < N; ++p) D[p] = P.I[p];
+      if (n != last) {
+        base = P.TA;
+        D[last] = P.K[last];
+        for (int p = 0; p < last; ++p)
+          if (p != n) modes[nm++] = p;
+      } else {
+        base = P.TB;
+        D[second] = P.K[second];
+        for (int p = 0; p < second; ++p) modes[nm++] = p;
+      }
+      const T* X;
+      RT_TRY(contract_chain<T>(base, D, N, modes, nm, B, P.K, P.X0, P.X1, &X, s));
+      int64_t Apre = 1, Cpost = 1;
+      for (int p = 0; p < n; ++p) Apre *= D[p];
+      for (int p = n + 1; p < N; ++p) Cpost *= D[p];
+      RT_TRY(launch_sketch_z<T>(X, static_cast<const T*>(Omt[sw * N + n]),
+                                P.Z[n], Apre, P.I[n], Cpost, P.K[n], s));
+    }
+    QrBatch qb{};
+    qb.nb = N;
+    for (int n = 0; n < N; ++n) {
+      qb.Z[n] = P.Z[n];
+      qb.Q[n] = P.Q[n];
+      qb.work[n] = P.qrwork[n];
+      qb.I[n] = P.I[n];
+      qb.K[n] = P.K[n];
+    }
+    RT_TRY(launch_qr<T>(qb, P.iflags + 1, s));
+    if (trace) {
+      for (int n = 0; n < N; ++n) {
+        const size_t bytes = P.I[n] * P.K[n] * sizeof(T);
+        if (trace->Z[sw * N + n] &&
+            hipMemcpyAsync(trace->Z[sw * N + n], P.Z[n], bytes,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return hip_fail(hipGetLastError(), "trace copy");
+        if (trace->Q[sw * N + n] &&
+            hipMemcpyAsync(trace->Q[sw * N + n], P.Q[n], bytes,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return hip_fail(hipGetLastError(), "trace copy");
+      }
+    }
+    for (int n = 0; n < N; ++n) B[n] = P.Q[n];
+  }
+
+  // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first, then the rest
+  RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
+  {
+    int64_t D[RT_MAX_MODES];
+    for (int p = 0; p < N; ++p) D[p] = P.I[p];
+    D[last] = P.K[last];
+    int modes[RT_MAX_MODES], nm = 0;
+    for (int p = 0; p < last; ++p) modes[nm++] = p;
+    const T* X;
+    RT_TRY(contract_chain<T>(P.TA, D, N, modes, nm, B, P.K, P.X0, P.X1, &X, s));
+    if (hipMemcpyAsync(P.Gt, X, P.core * sizeof(T), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+      return hip_fail(hipGetLastError(), "core copy");
+  }
+  if (trace && trace->Gt &&
+      hipMemcpyAsync(trace->Gt, P.Gt, P.core * sizeof(T),
+                     hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return hip_fail(hipGetLastError(), "trace copy");
+
+  if (d->flags & RT_FLAG_NO_TRUNCATE) {
+    for (int n = 0; n < N; ++n)
+      if (hipMemcpyAsync(Uout[n], P.Q[n], P.I[n] * P.K[n] * sizeof(T),
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return hip_fail(hipGetLastError(), "U copy");
+    if (hipMemcpyAsync(Gout, P.Gt, P.core * sizeof(T), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+      return hip_fail(hipGetLastError(), "G copy");
+  } else {
+    EigBatch eb{};
+    eb.nb = N;
+    int64_t Apre = 1;
+    for (int n = 0; n < N; ++n) {
+      const int64_t Cpost = P.core / (Apre * P.K[n]);
+      RT_TRY(launch_gram_unfold<T>(P.Gt, P.gram[n], Apre, P.K[n], Cpost, s));
+      Apre *= P.K[n];
+      eb.S[n] = P.gram[n];
+      eb.W[n] = P.W[n];
+      eb.evals[n] = nullptr;
+      eb.n[n] = P.K[n];
+      eb.k[n] = P.Rn[n];
+    }
+    RT_TRY(launch_eig(eb, s));
+    const T* WT[RT_MAX_MODES];
+    for (int n = 0; n < N; ++n) {
+      RT_TRY(launch_matmul_w<T>(P.Q[n], P.W[n], static_cast<T*>(Uout[n]),
+                                P.I[n], P.K[n], P.Rn[n], s));
+      if (sizeof(T) == sizeof(double)) {
+        WT[n] = reinterpret_cast<const T*>(P.W[n]);
+      } else {
+        RT_TRY((launch_convert<double, float>(
+            P.W[n], reinterpret_cast<float*>(P.WT[n]),
+            static_cast<int64_t>(P.K[n]) * P.Rn[n], s)));
+        WT[n] = P.WT[n];
+      }
+    }
+    int64_t D[RT_MAX_MODES];
+    for (int p = 0; p < N; ++p) D[p] = P.K[p];
+    int modes[RT_MAX_MODES];
+    for (int p = 0; p < N; ++p) modes[p] = p;
+    const T* X;
+    RT_TRY(contract_chain<T>(P.Gt, D, N, modes, N, WT, P.Rn, P.Gtmp, P.X1, &X,
+                             s));
+    if (hipMemcpyAsync(Gout, X, P.core_out * sizeof(T), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+      return hip_fail(hipGetLastError(), "G copy");
+  }
+  RT_TRY(launch_norm2<T>(static_cast<const T*>(Gout), P.core_out, P.partial,
+                         norm2_blocks(), P.scal + 1, P.iflags + 2, s));
+  if (info) {
+    // scal[0..1] -> normY2, normG2; iflags[0] nonfinite, iflags[1] rank
+    if (hipMemcpyAsync(info, P.scal, 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess ||
+        hipMemcpyAsync(reinterpret_cast<char*>(info) + 16, P.iflags,
+                       2 * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+      return hip_fail(hipGetLastError(), "info copy");
+  }
+  return kOk;
+}
+
+// ------------------------------------------------------------------ ffcp
+
+int validate_ffcp(const rt_ffcp_desc* d) {
+  if (!d) {
+    set_error("desc is NULL");
+    return kErrInvalid;
+  }
+  if (d->N < 2 || d->N > RT_MAX_MODES) {
+    set_error("N=%d outside 2..%d", d->N, RT_MAX_MODES);
+    return kErrInvalid;
+  }
+  if (d->R < 1 || d->R > RT_MAX_SKETCH) {
+    set_error("R=%d outside 1..%d", d->R, RT_MAX_SKETCH);
+    return kErrInvalid;
+  }
+  if (d->update < 0 || d->update > 2) {
+    set_error("unknown update rule %d", d->update);
+    return kErrInvalid;
+  }
+  if (d->init < 0 || d->init > 1) {
+    set_error("unknown init %d", d->init);
+    return kErrInvalid;
+  }
+  if (d->max_it < 1) {
+    set_error("max_it=%d < 1", d->max_it);
+    return kErrInvalid;
+  }
+  if (!(d->tol >= 0.0) || !(d->l1 >= 0.0)) {
+    set_error("tol and l1 must be >= 0");
+    return kErrInvalid;
+  }
+  int64_t core = 1;
+  for (int n = 0; n < d->N; ++n) {
+    if (d->dims[n] < 1 || d->ranks[n] < 1 || d->ranks[n] > RT_MAX_SKETCH ||
+        d->ranks[n] > d->dims[n]) {
+      set_error("mode %d: I=%lld R_n=%d invalid", n, (long long)d->dims[n],
+                d->ranks[n]);
+      return kErrInvalid;
+    }
+    core *= d->ranks[n];
+  }
+  if (core > (int64_t(1) << 24)) {
+    set_error("core too large for the FFCP kernel");
+    return kErrUnsupported;
+  }
+  return kOk;
+}
+
+struct FfcpPlan {
+  double* A[RT_MAX_MODES];
+  double* V[RT_MAX_MODES];
+  double* Gram[RT_MAX_MODES];
+  double* U64[RT_MAX_MODES];
+  double* G64;
+  double* H;
+  double* Qm;
+  double* T;
+  double* W1;
+  double* W2;
+  double* scal;
+  double* Vinit[RT_MAX_MODES];
+  double* hgram[RT_MAX_MODES];
+  size_t plan(const rt_ffcp_desc* d, void* ws) {
+    Arena ar(ws);
+    const int N = d->N, R = d->R;
+    int64_t core = 1, Imax = 1;
+    int Rmin = 1 << 30, Rmax = 0;
+    for (int n = 0; n < N; ++n) {
+      core *= d->ranks[n];
+      Imax = d->dims[n] > Imax ? d->dims[n] : Imax;
+      Rmin = d->ranks[n] < Rmin ? d->ranks[n] : Rmin;
+      Rmax = d->ranks[n] > Rmax ? d->ranks[n] : Rmax;
+    }
+    int64_t wsize = core / Rmin * R;
+    if (wsize < core) wsize = core;
+    for (int n = 0; n < N; ++n) {
+      A[n] = ar.take<double>(d->dims[n] * R);
+      V[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * R);
+      Gram[n] = ar.take<double>(R * R);
+      U64[n] = ar.take<double>(d->dims[n] * d->ranks[n]);
+      Vinit[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * R);
+      hgram[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * d->ranks[n]);
+    }
+    G64 = ar.take<double>(core);
+    int64_t hs = static_cast<int64_t>(Rmax) * (R > Rmax ? R : Rmax);
+    H = ar.take<double>(hs);
+    Qm = ar.take<double>(Imax * R);
+    T = ar.take<double>(R * R);
+    W1 = ar.take<double>(wsize);
+    W2 = ar.take<double>(wsize);
+    scal = ar.take<double>(8 + RT_MAX_SKETCH);
+    return ar.need;
+  }
+};
+
+__global__ void hosvd_pad_kernel(const double* W, const float* pad, double* V,
+                                 int Rn, int k, int R) {
+  // V[j, r] = W[j, r] for r < k, pad[j, r-k] for r >= k
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= Rn * R) return;
+  const int j = l / R, r = l % R;
+  V[l] = (r < k) ? W[j * k + r] : static_cast<double>(pad[j * (R - k) + (r - k)]);
+}
+
+template <typename T>
+__global__ void gram_of_core_kernel(const T* G, double* S, int64_t Apre, int Rn,
+                                    int64_t Cpost) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= Rn * Rn) return;
+  const int i = l / Rn, j = l % Rn;
+  double acc = 0.0;
+  for (int64_t a = 0; a < Apre; ++a)
+    for (int64_t c = 0; c < Cpost; ++c)
+      acc += static_cast<double>(G[(a * Rn + i) * Cpost + c]) *
+             static_cast<double>(G[(a * Rn + j) * Cpost + c]);
+  S[l] = acc;
+}
+
+}  // namespace
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+int rt_tucker_rand_workspace(const rt_tucker_desc* desc, size_t* bytes) {
+  RT_TRY(validate_tucker(desc));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return kErrInvalid;
+  }
+  if (desc->precision == RT_F64) {
+    TuckerPlan<double> p;
+    *bytes = p.plan(desc, nullptr);
+  } else {
+    TuckerPlan<float> p;
+    *bytes = p.plan(desc, nullptr);
+  }
+  return kOk;
+}
+
+int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
+                   const void* const* Omega, const void* const* Omega_t,
+                   void* ws, size_t ws_bytes, void* const* U, void* G,
+                   uint16_t* Ybf16, rt_tucker_info* info,
+                   const rt_tucker_trace* trace, void* stream) {
+  RT_TRY(validate_tucker(desc));
+  RT_TRY(check_ptr(Y, "Y"));
+  RT_TRY(check_ptr(ws, "ws"));
+  RT_TRY(check_ptr(G, "G"));
+  if (!Omega || !Omega_t || !U) {
+    set_error("Omega, Omega_t and U arrays must not be NULL");
+    return kErrInvalid;
+  }
+  for (int n = 0; n < desc->N; ++n) {
+    RT_TRY(check_ptr(Omega[n], "Omega[n]"));
+    RT_TRY(check_ptr(U[n], "U[n]"));
+    for (int s = 0; s < desc->sweeps; ++s)
+      RT_TRY(check_ptr(Omega_t[s * desc->N + n], "Omega_t[s*N+n]"));
+  }
+  const bool mixed = desc->precision == RT_BF16_MIXED;
+  if (mixed && !(desc->flags & RT_FLAG_BF16_INPUT)) RT_TRY(check_ptr(Ybf16, "Ybf16"));
+  if (info && !aligned16(info)) {
+    set_error("info is not 16-byte aligned");
+    return kErrInvalid;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (desc->precision == RT_F64)
+    return tucker_run<double>(desc, Y, Omega, Omega_t, ws, ws_bytes, U, G,
+                              Ybf16, info, trace, s);
+  return tucker_run<float>(desc, Y, Omega, Omega_t, ws, ws_bytes, U, G, Ybf16,
+                           info, trace, s);
+}
+
+int rt_ffcp_workspace(const rt_ffcp_desc* desc, size_t* bytes) {
+  RT_TRY(validate_ffcp(desc));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return kErrInvalid;
+  }
+  FfcpPlan p;
+  *bytes = p.plan(desc, nullptr);
+  return kOk;
+}
+
+int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
+            const float* const* A_init, const float* const* pad, void* ws,
+            size_t ws_bytes, float* const* A, float* lambda, double* fit_trace,
+            rt_ffcp_info* info, void* stream) {
+  RT_TRY(validate_ffcp(desc));
+  RT_TRY(check_ptr(G, "G"));
+  RT_TRY(check_ptr(ws, "ws"));
+  RT_TRY(check_ptr(lambda, "lambda"));
+  if (!U || !A) {
+    set_error("U and A arrays must not be NULL");
+    return kErrInvalid;
+  }
+  const int N = desc->N, R = desc->R;
+  for (int n = 0; n < N; ++n) {
+    RT_TRY(check_ptr(U[n], "U[n]"));
+    RT_TRY(check_ptr(A[n], "A[n]"));
+  }
+  if (desc->init == RT_INIT_USER) {
+    if (!A_init) {
+      set_error("A_init is NULL with RT_INIT_USER");
+      return kErrInvalid;
+    }
+    for (int n = 0; n < N; ++n) RT_TRY(check_ptr(A_init[n], "A_init[n]"));
+  } else {
+    for (int n = 0; n < N; ++n) {
+      if (R > desc->ranks[n]) {
+        if (!pad || !pad[n]) {
+          set_error("HOSVD init with R > R_%d needs pad[%d]", n, n);
+          return kErrInvalid;
+        }
+        RT_TRY(check_ptr(pad[n], "pad[n]"));
+      }
+    }
+  }
+  if ((info && !aligned16(info)) || (fit_trace && !aligned16(fit_trace))) {
+    set_error("info / fit_trace not 16-byte aligned");
+    return kErrInvalid;
+  }
+  FfcpPlan P;
+  const size_t need = P.plan(desc, ws);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return kErrWorkspace;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FfcpArgs a{};
+  a.N = N;
+  a.R = R;
+  a.update = desc->update;
+  a.max_it = desc->max_it;
+  a.tol = desc->tol;
+  a.l1 = desc->l1;
+  a.normY2 = (std::isnan(desc->normY2) || desc->normY2 < 0.0) ? -1.0 : desc->normY2;
+  a.G = G;
+  a.lambda = lambda;
+  a.fit_trace = fit_trace;
+  a.info = info;
+  for (int n = 0; n < N; ++n) {
+    a.I[n] = desc->dims[n];
+    a.Rn[n] = desc->ranks[n];
+    a.U[n] = U[n];
+    a.A_out[n] = A[n];
+    a.A[n] = P.A[n];
+    a.V[n] = P.V[n];
+    a.Gram[n] = P.Gram[n];
+    a.U64[n] = P.U64[n];
+    a.A_init[n] = desc->init == RT_INIT_USER ? A_init[n] : nullptr;
+    a.V_init[n] = P.Vinit[n];
+  }
+  a.G64 = P.G64;
+  a.H = P.H;
+  a.Qm = P.Qm;
+  a.T = P.T;
+  a.W1 = P.W1;
+  a.W2 = P.W2;
+  a.scal = P.scal;
+  if (desc->init == RT_INIT_HOSVD) {
+    // V_n = top-min(R, R_n) eigenvectors of G_(n) G_(n)^T, padded with the
+    // caller's columns when R > R_n; the kernel then forms A_n = U_n V_n.
+    int64_t core = 1;
+    for (int n = 0; n < N; ++n) core *= desc->ranks[n];
+    int64_t Apre = 1;
+    for (int n = 0; n < N; ++n) {
+      const int Rn = desc->ranks[n];
+      const int k = R < Rn ? R : Rn;
+      const int64_t Cpost = core / (Apre * Rn);
+      hipLaunchKernelGGL(gram_of_core_kernel<float>,
+                         dim3((Rn * Rn + 255) / 256), dim3(256), 0, s, G,
+                         P.hgram[n], Apre, Rn, Cpost);
+      RT_LAUNCH_CHECK("hosvd gram");
+      Apre *= Rn;
+      EigBatch one{};
+      one.nb = 1;
+      one.S[0] = P.hgram[n];
+      one.n[0] = Rn;
+      one.k[0] = k;
+      one.W[0] = P.H;  // Rn x k scratch
+      one.evals[0] = nullptr;
+      RT_TRY(launch_eig(one, s));
+      hipLaunchKernelGGL(hosvd_pad_kernel, dim3((Rn * R + 255) / 256), dim3(256),
+                         0, s, P.H, (k < R) ? pad[n] : nullptr, P.Vinit[n], Rn,
+                         k, R);
+      RT_LAUNCH_CHECK("hosvd pad");
+    }
+  }
+  return launch_ffcp(a, s);
+}
+
+int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,
+           const void* X, const void* M, void* out, void* stream) {
+  if (A < 1 || I < 1 || C < 1 || K < 1 || K > RT_MAX_SKETCH) {
+    set_error("rt_ttm: bad sizes");
+    return kErrInvalid;
+  }
+  RT_TRY(check_ptr(X, "X"));
+  RT_TRY(check_ptr(M, "M"));
+  RT_TRY(check_ptr(out, "out"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == RT_F32)
+    return launch_ttm<float>(static_cast<const float*>(X),
+                             static_cast<const float*>(M),
+                             static_cast<float*>(out), A, I, C, K, s);
+  if (dtype == RT_F64)
+    return launch_ttm<double>(static_cast<const double*>(X),
+                              static_cast<const double*>(M),
+                              static_cast<double*>(out), A, I, C, K, s);
+  set_error("rt_ttm: dtype %d unsupported", dtype);
+  return kErrInvalid;
+}
+
+int rt_cp_fit_workspace(const rt_ffcp_desc* desc, size_t* bytes) {
+  if (!desc || !bytes || desc->N < 2 || desc->N > RT_MAX_MODES || desc->R < 1 ||
+      desc->R > RT_MAX_SKETCH) {
+    set_error("rt_cp_fit_workspace: bad arguments");
+    return kErrInvalid;
+  }
+  int64_t total = 1, rpow = 1;
+  for (int n = 0; n < desc->N; ++n) {
+    if (desc->dims[n] < 1) {
+      set_error("rt_cp_fit_workspace: dims[%d] < 1", n);
+      return kErrInvalid;
+    }
+    total *= desc->dims[n];
+    rpow *= desc->R;
+    if (rpow > (int64_t(1) << 24)) {
+      set_error("rt_cp_fit: R^N too large");
+      return kErrUnsupported;
+    }
+  }
+  const int64_t t1 = total / desc->dims[desc->N - 1] * desc->R;
+  Arena ar(nullptr);
+  ar.take<float>(t1);
+  ar.take<float>(t1);
+  ar.take<double>(norm2_blocks());
+  ar.take<double>(8);
+  ar.take<int32_t>(8);
+  for (int n = 0; n < desc->N; ++n) ar.take<double>(desc->R * desc->R);
+  *bytes = ar.need;
+  return kOk;
+}
+
+int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
+                    const float* const* A, const float* lambda, void* ws,
+                    size_t ws_bytes, double* out3, void* stream) {
+  size_t need = 0;
+  RT_TRY(rt_cp_fit_workspace(desc, &need));
+  RT_TRY(check_ptr(Y, "Y"));
+  RT_TRY(check_ptr(ws, "ws"));
+  RT_TRY(check_ptr(out3, "out3"));
+  if (!A) {
+    set_error("A is NULL");
+    return kErrInvalid;
+  }
+  const int N = desc->N, R = desc->R;
+  for (int n = 0; n < N; ++n) RT_TRY(check_ptr(A[n], "A[n]"));
+  if (lambda) RT_TRY(check_ptr(lambda, "lambda"));
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return kErrWorkspace;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t total = 1;
+  for (int n = 0; n < N; ++n) total *= desc->dims[n];
+  const int64_t t1 = total / desc->dims[N - 1] * R;
+  Arena ar(ws);
+  float* b0 = ar.take<float>(t1);
+  float* b1 = ar.take<float>(t1);
+  double* partial = ar.take<double>(norm2_blocks());
+  double* scal = ar.take<double>(8);
+  int32_t* flags = ar.take<int32_t>(8);
+  double* grams[RT_MAX_MODES];
+  for (int n = 0; n < N; ++n) grams[n] = ar.take<double>(R * R);
+  RT_TRY(launch_fill_i32(flags, 0, 8, s));
+  RT_TRY(launch_norm2<float>(Y, total, partial, norm2_blocks(), scal + 0,
+                             flags, s));
+  // Y x_N A_N^T ... x_1 A_1^T  ->  R^N tensor; its diagonal gives <Y, Yhat>
+  int64_t D[RT_MAX_MODES];
+  for (int n = 0; n < N; ++n) D[n] = desc->dims[n];
+  const float* src = Y;
+  float* bufs[2] = {b0, b1};
+  int cur = 0;
+  for (int p = N - 1; p >= 0; --p) {
+    int64_t Apre = 1, Cpost = 1;
+    for (int q = 0; q < p; ++q) Apre *= D[q];
+    for (int q = p + 1; q < N; ++q) Cpost *= D[q];
+    RT_TRY(launch_ttm<float>(src, A[p], bufs[cur], Apre, D[p], Cpost, R, s));
+    D[p] = R;
+    src = bufs[cur];
+    cur ^= 1;
+  }
+  for (int n = 0; n < N; ++n)
+    RT_TRY(launch_gram_unfold<float>(A[n], grams[n], desc->dims[n], R, 1, s));
+  return launch_cp_fit_final(src, N, R, lambda, grams, scal, out3, s);
+}
+
+const char* rt_status_string(int status) {
+  switch (status) {
+    case RT_OK: return "RT_OK";
+    case RT_ERR_INVALID_ARG: return "RT_ERR_INVALID_ARG";
+    case RT_ERR_UNSUPPORTED: return "RT_ERR_UNSUPPORTED";
+    case RT_ERR_WORKSPACE: return "RT_ERR_WORKSPACE";
+    case RT_ERR_NONFINITE: return "RT_ERR_NONFINITE";
+    case RT_ERR_NUMERICAL: return "RT_ERR_NUMERICAL";
+    case RT_ERR_HIP: return "RT_ERR_HIP";
+    case RT_ERR_NO_DEVICE: return "RT_ERR_NO_DEVICE";
+    default: return "unknown status";
+  }
+}
+
+const char* rt_last_error(void) { return g_err; }
+
+const char* rt_version(void) { return "rtucker 0.1 (gfx950)"; }
+
+}  // extern "C"

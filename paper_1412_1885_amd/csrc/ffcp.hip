@@ -1,0 +1,427 @@
+// FFCP (Algorithm 1, Section III-B) on a Tucker format [[G; U]].
+//
+// The whole iteration loop runs inside one workgroup of 512 threads: every
+// step is a small dense operation (R <= 64, R_n <= 64, the core has at most
+// a few 10^5 entries) so the loop is latency bound, and keeping it on the
+// device removes every launch and host round trip; the stopping test is
+// evaluated on the device too.  Arithmetic is FP64: the stopping rule
+// compares fits to 1e-6..1e-9, and the closed-form fit cancels
+// ||Yt||^2 - 2<Yt,Yhat> + ||Yhat||^2, so its inputs need FP64 accumulation.
+//
+// Per iteration, for n = 0..N-1:
+//   H   = G_(n) [KR_{p != n} V_p]            eq. (12)-(13), contracted one
+//                                            mode at a time, last mode first
+//   Q   = U_n H
+//   T   = hadamard_{p != n} Gram_p          eq. (9)
+//   A_n <- ALS (Cholesky solve of A T = Q, eq. (14)) | HALS (eq. (8), standard
+//          form) | MU (eq. (15));  optional soft threshold S_c (eq. (16))
+//   normalize columns if n < N-1;  V_n = U_n^T A_n;  Gram_n = A_n^T A_n
+// then Fit = 1 - sqrt(||Yt||^2 - 2 sum(H_{N-1} * V_{N-1}) + 1^T(had Gram)1)
+//            / ||Yt||.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kFThreads = 512;
+constexpr int kFWaves = kFThreads / 64;
+constexpr int kRMax = 64;
+
+struct InfoDev {
+  int32_t iterations, converged, ridged, reserved;
+  double fit, fit_prev;
+};
+
+__device__ __forceinline__ void bsync() { __syncthreads(); }
+
+// out[o] = sum_i X[i*ldx + ox(o)] * Y[i*ldy + oy(o)], o < nout, i < rows;
+// one wave per output (lanes stride the rows), deterministic order.
+template <typename FX, typename FY>
+__device__ void wave_dots(const double* X, int64_t ldx, const double* Y,
+                          int64_t ldy, int64_t rows, int nout, FX ox, FY oy,
+                          double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = wave; o < nout; o += kFWaves) {
+    const int cx = ox(o), cy = oy(o);
+    double acc = 0.0;
+    for (int64_t i = lane; i < rows; i += 64) acc += X[i * ldx + cx] * Y[i * ldy + cy];
+    acc = wave_sum(acc);
+    if (lane == 0) out[o] = acc;
+  }
+}
+
+// Mode product of a core by a square FP64 matrix M (S x S) in mode m:
+// out[a, i, c] = sum_j X[a, j, c] M[j, i].
+__device__ void core_ttm_sq(const double* X, double* out, const double* M,
+                            int64_t Apre, int S, int64_t Cpost) {
+  const int64_t total = Apre * S * Cpost;
+  for (int64_t l = threadIdx.x; l < total; l += kFThreads) {
+    int64_t c = l % Cpost;
+    int64_t t = l / Cpost;
+    int i = static_cast<int>(t % S);
+    int64_t a = t / S;
+    double acc = 0.0;
+    for (int j = 0; j < S; ++j) acc += X[(a * S + j) * Cpost + c] * M[j * S + i];
+    out[l] = acc;
+  }
+}
+
+template <int RMAX>
+__global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
+  __shared__ double Ts[kRMax * kRMax];   // T, then its Cholesky factor
+  __shared__ double red[kFWaves];
+  __shared__ double sh[8];
+  __shared__ int shi[4];
+  const int t = threadIdx.x;
+  const int N = a.N, R = a.R;
+  InfoDev* info = static_cast<InfoDev*>(a.info);
+
+  // ---- setup: FP64 copies of U, G; A from the initialization -------------
+  int64_t coreSize = 1;
+  for (int n = 0; n < N; ++n) coreSize *= a.Rn[n];
+  for (int n = 0; n < N; ++n) {
+    const int64_t cnt = a.I[n] * a.Rn[n];
+    for (int64_t l = t; l < cnt; l += kFThreads) a.U64[n][l] = a.U[n][l];
+  }
+  for (int64_t l = t; l < coreSize; l += kFThreads) a.G64[l] = a.G[l];
+  bsync();
+  for (int n = 0; n < N; ++n) {
+    const int64_t cnt = a.I[n] * R;
+    if (a.A_init[n]) {
+      for (int64_t l = t; l < cnt; l += kFThreads) a.A[n][l] = a.A_init[n][l];
+    } else {  // A = U V_init
+      for (int64_t l = t; l < cnt; l += kFThreads) {
+        int64_t i = l / R;
+        int r = static_cast<int>(l % R);
+        double acc = 0.0;
+        for (int j = 0; j < a.Rn[n]; ++j)
+          acc += a.U64[n][i * a.Rn[n] + j] * a.V_init[n][j * R + r];
+        a.A[n][l] = acc;
+      }
+    }
+  }
+  bsync();
+  for (int n = 0; n < N; ++n) {
+    const int Rn = a.Rn[n];
+    const double* Un = a.U64[n];
+    const double* An = a.A[n];
+    wave_dots(Un, Rn, An, R, a.I[n], Rn * R, [&](int o) { return o / R; },
+              [&](int o) { return o % R; }, a.V[n]);
+    wave_dots(An, R, An, R, a.I[n], R * R, [&](int o) { return o / R; },
+              [&](int o) { return o % R; }, a.Gram[n]);
+  }
+  bsync();
+
+  // ---- ||Yt||^2 = <G, G x_n U_n^T U_n> unless given ----------------------
+  double nrm2 = a.normY2;
+  if (!(nrm2 >= 0.0)) {
+    // UtU_n into W2 (packed), G' chain in W1 <-> Qm buffers
+    double* src = a.G64;
+    double* bufs[2] = {a.W1, a.W2};
+    int cur = 0;
+    int64_t Apre = 1;
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
+      int64_t Cpost = coreSize / (Apre * Rn);
+      // UtU in Ts (Rn <= 64)
+      wave_dots(a.U64[n], Rn, a.U64[n], Rn, a.I[n], Rn * Rn,
+                [&](int o) { return o / Rn; }, [&](int o) { return o % Rn; },
+                a.H);
+      bsync();
+      core_ttm_sq(src, bufs[cur], a.H, Apre, Rn, Cpost);
+      bsync();
+      src = bufs[cur];
+      cur ^= 1;
+      Apre *= Rn;
+    }
+    double p = 0.0;
+    for (int64_t l = t; l < coreSize; l += kFThreads) p += a.G64[l] * src[l];
+    nrm2 = block_sum(p, red);
+    bsync();
+  }
+
+  // ---- iterations ---------------------------------------------------------
+  double fit_prev = 0.0, fit = 0.0;
+  int it = 0, converged = 0, ridged = 0;
+  double inner = 0.0;
+  for (it = 1; it <= a.max_it; ++it) {
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
+      const int64_t In = a.I[n];
+      // H = G_(n) [KR_{p != n} V_p]: contract the last remaining mode != n
+      int rem[8], nrem = N;
+      for (int p = 0; p < N; ++p) rem[p] = p;
+      const double* src = a.G64;
+      double* bufs[2] = {a.W1, a.W2};
+      int cur = 0;
+      bool first = true;
+      while (nrem > 1) {
+        int pos = nrem - 1;
+        if (rem[pos] == n) pos = nrem - 2;
+        const int m = rem[pos];
+        int64_t Apre = 1, Cpost = 1;
+        for (int q = 0; q < pos; ++q) Apre *= a.Rn[rem[q]];
+        for (int q = pos + 1; q < nrem; ++q) Cpost *= a.Rn[rem[q]];
+        const int Rm = a.Rn[m];
+        const double* Vm = a.V[m];
+        double* dst = bufs[cur];
+        const int64_t total = Apre * Cpost * R;
+        for (int64_t l = t; l < total; l += kFThreads) {
+          const int r = static_cast<int>(l % R);
+          const int64_t ac = l / R;
+          const int64_t c = ac % Cpost, aa = ac / Cpost;
+          double acc = 0.0;
+          if (first) {
+            for (int j = 0; j < Rm; ++j)
+              acc += src[(aa * Rm + j) * Cpost + c] * Vm[j * R + r];
+          } else {
+            for (int j = 0; j < Rm; ++j)
+              acc += src[((aa * Rm + j) * Cpost + c) * R + r] * Vm[j * R + r];
+          }
+          dst[l] = acc;
+        }
+        bsync();
+        for (int q = pos; q < nrem - 1; ++q) rem[q] = rem[q + 1];
+        --nrem;
+        src = dst;
+        cur ^= 1;
+        first = false;
+      }
+      const double* H = src;  // Rn x R
+      // Q = U_n H
+      double* Qm = a.Qm;
+      for (int64_t l = t; l < In * R; l += kFThreads) {
+        const int64_t i = l / R;
+        const int r = static_cast<int>(l % R);
+        double acc = 0.0;
+        for (int j = 0; j < Rn; ++j) acc += a.U64[n][i * Rn + j] * H[j * R + r];
+        Qm[l] = acc;
+      }
+      // T = hadamard of the other Grams
+      for (int l = t; l < R * R; l += kFThreads) {
+        double v = 1.0;
+        for (int p = 0; p < N; ++p)
+          if (p != n) v *= a.Gram[p][l];
+        Ts[l] = v;
+      }
+      if (n == N - 1) {
+        // keep H of the last mode for the fit (copy before buffers reuse)
+        for (int l = t; l < Rn * R; l += kFThreads) a.H[l] = H[l];
+      }
+      bsync();
+      double* An = a.A[n];
+      if (a.update == 0) {
+        // ---- ALS: Cholesky of T (in place, lower), ridge on failure ------
+        for (int attempt = 0; attempt < 2; ++attempt) {
+          if (attempt == 1) {
+            // rebuild T + delta I
+            double tr = 0.0;
+            for (int l = 0; l < R; ++l) {
+              double v = 1.0;
+              for (int p = 0; p < N; ++p)
+                if (p != n) v *= a.Gram[p][l * R + l];
+              tr += v;
+            }
+            const double delta = 1e-12 * tr / R;
+            bsync();
+            for (int l = t; l < R * R; l += kFThreads) {
+              double v = 1.0;
+              for (int p = 0; p < N; ++p)
+                if (p != n) v *= a.Gram[p][l];
+              if (l / R == l % R) v += delta;
+              Ts[l] = v;
+            }
+            bsync();
+          }
+          if (t == 0) shi[0] = 0;
+          bsync();
+          for (int k = 0; k < R; ++k) {
+            if (t == 0) {
+              double d = Ts[k * R + k];
+              if (!(d > 0.0)) {
+                shi[0] = 1;
+                d = 1.0;
+              }
+              Ts[k * R + k] = sqrt(d);
+            }
+            bsync();
+            const double dk = Ts[k * R + k];
+            for (int i = k + 1 + t; i < R; i += kFThreads) Ts[i * R + k] /= dk;
+            bsync();
+            const int rem2 = R - k - 1;
+            for (int l = t; l < rem2 * rem2; l += kFThreads) {
+              const int i = k + 1 + l / rem2, j = k + 1 + l % rem2;
+              if (j <= i) Ts[i * R + j] -= Ts[i * R + k] * Ts[j * R + k];
+            }
+            bsync();
+          }
+          const int failed = shi[0];
+          bsync();
+          if (!failed) break;
+          ridged = 1;
+        }
+        // solve A_n[i,:] L L^T = Q[i,:] row by row
+        for (int64_t i = t; i < In; i += kFThreads) {
+          double y[RMAX];
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+              double s = Qm[i * R + r];
+              for (int q = 0; q < r; ++q) s -= Ts[r * R + q] * y[q];
+              y[r] = s / Ts[r * R + r];
+            }
+          }
+#pragma unroll
+          for (int r = RMAX - 1; r >= 0; --r) {
+            if (r < R) {
+              double s = y[r];
+              for (int q = r + 1; q < R; ++q) s -= Ts[q * R + r] * y[q];
+              y[r] = s / Ts[r * R + r];
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r)
+            if (r < R) An[i * R + r] = y[r];
+        }
+      } else if (a.update == 1) {
+        // ---- HALS: columns in order, in place per row --------------------
+        for (int64_t i = t; i < In; i += kFThreads) {
+          double row[RMAX];
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) row[r] = (r < R) ? An[i * R + r] : 0.0;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+              double s = 0.0;
+#pragma unroll
+              for (int q = 0; q < RMAX; ++q)
+                if (q < R) s += row[q] * Ts[q * R + r];
+              double v = row[r] + (Qm[i * R + r] - s) / Ts[r * R + r];
+              row[r] = v > 1e-16 ? v : 1e-16;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r)
+            if (r < R) An[i * R + r] = row[r];
+        }
+      } else {
+        // ---- MU: A <- A * max(Q,0) / (A T + eps) -------------------------
+        for (int64_t i = t; i < In; i += kFThreads) {
+          double row[RMAX];
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) row[r] = (r < R) ? An[i * R + r] : 0.0;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+              double s = 0.0;
+#pragma unroll
+              for (int q = 0; q < RMAX; ++q)
+                if (q < R) s += row[q] * Ts[q * R + r];
+              double qv = Qm[i * R + r];
+              An[i * R + r] = row[r] * (qv > 0.0 ? qv : 0.0) / (s + 1e-16);
+            }
+          }
+        }
+      }
+      bsync();
+      if (a.l1 > 0.0) {
+        const double c = a.l1;
+        for (int64_t l = t; l < In * R; l += kFThreads) {
+          double x = An[l];
+          An[l] = x > c ? x - c : (x < -c ? x + c : 0.0);
+        }
+        bsync();
+      }
+      if (n < N - 1) {
+        wave_dots(An, R, An, R, In, R, [&](int o) { return o; },
+                  [&](int o) { return o; }, a.scal + 8);
+        bsync();
+        for (int64_t l = t; l < In * R; l += kFThreads) {
+          const double nr = sqrt(a.scal[8 + l % R]);
+          if (nr > 0.0) An[l] /= nr;
+        }
+        bsync();
+      }
+      wave_dots(a.U64[n], Rn, An, R, In, Rn * R, [&](int o) { return o / R; },
+                [&](int o) { return o % R; }, a.V[n]);
+      wave_dots(An, R, An, R, In, R * R, [&](int o) { return o / R; },
+                [&](int o) { return o % R; }, a.Gram[n]);
+      bsync();
+    }
+    // ---- fit ----------------------------------------------------------------
+    {
+      double p = 0.0;
+      const int Rl = a.Rn[N - 1];
+      for (int l = t; l < Rl * R; l += kFThreads) p += a.H[l] * a.V[N - 1][l];
+      inner = block_sum(p, red);
+      double q = 0.0;
+      for (int l = t; l < R * R; l += kFThreads) {
+        double v = 1.0;
+        for (int pp = 0; pp < N; ++pp) v *= a.Gram[pp][l];
+        q += v;
+      }
+      const double yh2 = block_sum(q, red);
+      double res2 = nrm2 - 2.0 * inner + yh2;
+      res2 = res2 > 0.0 ? res2 : 0.0;
+      fit = 1.0 - sqrt(res2) / sqrt(nrm2);
+    }
+    if (t == 0 && a.fit_trace) a.fit_trace[it - 1] = fit;
+    if (it >= 2 && fabs(fit - fit_prev) < a.tol) {
+      converged = 1;
+      break;
+    }
+    if (it < a.max_it) fit_prev = fit;
+    bsync();
+  }
+  if (it > a.max_it) it = a.max_it;
+  bsync();
+  // ---- outputs --------------------------------------------------------------
+  for (int n = 0; n < N - 1; ++n) {
+    const int64_t cnt = a.I[n] * R;
+    for (int64_t l = t; l < cnt; l += kFThreads)
+      a.A_out[n][l] = static_cast<float>(a.A[n][l]);
+  }
+  {
+    const int n = N - 1;
+    const double* An = a.A[n];
+    wave_dots(An, R, An, R, a.I[n], R, [&](int o) { return o; },
+              [&](int o) { return o; }, a.scal + 8);
+    bsync();
+    const int64_t cnt = a.I[n] * R;
+    for (int64_t l = t; l < cnt; l += kFThreads) {
+      const double nr = sqrt(a.scal[8 + l % R]);
+      a.A_out[n][l] = static_cast<float>(nr > 0.0 ? An[l] / nr : An[l]);
+    }
+    for (int r = t; r < R; r += kFThreads)
+      a.lambda[r] = static_cast<float>(sqrt(a.scal[8 + r]));
+  }
+  if (t == 0 && info) {
+    info->iterations = it;
+    info->converged = converged;
+    info->ridged = ridged;
+    info->reserved = 0;
+    info->fit = fit;
+    info->fit_prev = fit_prev;
+  }
+}
+
+}  // namespace
+
+int launch_ffcp(const FfcpArgs& a, hipStream_t s) {
+  if (a.R <= 16) {
+    hipLaunchKernelGGL(ffcp_kernel<16>, dim3(1), dim3(kFThreads), 0, s, a);
+  } else if (a.R <= 32) {
+    hipLaunchKernelGGL(ffcp_kernel<32>, dim3(1), dim3(kFThreads), 0, s, a);
+  } else if (a.R <= 64) {
+    hipLaunchKernelGGL(ffcp_kernel<64>, dim3(1), dim3(kFThreads), 0, s, a);
+  } else {
+    set_error("ffcp: R=%d exceeds 64", a.R);
+    return kErrUnsupported;
+  }
+  RT_LAUNCH_CHECK("ffcp");
+  return kOk;
+}
+
+}  // namespace rt

@@ -1,0 +1,114 @@
+// Host-side launchers of the device kernels (one translation unit each).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rt {
+
+// ---- generic mode-n product (ttm.hip) ------------------------------------
+// out[a, k, c] = sum_i X[a, i, c] * M[i, k];  X: [A, I, C], M: I x K.
+template <typename T>
+int launch_ttm(const T* X, const T* M, T* out, int64_t A, int64_t I, int64_t C,
+               int K, hipStream_t s);
+
+// Z[i, r] = sum_{a, c} X[a, i, c] * Om[a*C + c, r]  (X_(n) Omega~_n).
+template <typename T>
+int launch_sketch_z(const T* X, const T* Om, T* Z, int64_t A, int64_t I,
+                    int64_t C, int R, hipStream_t s);
+
+// S = X_(n) X_(n)^T in FP64 for X viewed [A, I, C] (I <= 64).
+template <typename T>
+int launch_gram_unfold(const T* X, double* S, int64_t A, int I, int64_t C,
+                       hipStream_t s);
+
+// out[i, j] = sum_k Q[i, k] * W[k, j];  Q: I x K (T), W: K x J (FP64).
+template <typename T>
+int launch_matmul_w(const T* Q, const double* W, T* out, int64_t I, int K,
+                    int J, hipStream_t s);
+
+// partial[b] = sum of squares (FP64) over a grid-stride slice; flag |= !finite.
+// Then out[0] = sum partials (fixed order).  n elements of T.
+template <typename T>
+int launch_norm2(const T* X, int64_t n, double* partial, int nblocks,
+                 double* out, int32_t* nonfinite, hipStream_t s);
+int launch_norm2_bf16(const uint16_t* X, int64_t n, double* partial,
+                      int nblocks, double* out, int32_t* nonfinite,
+                      hipStream_t s);
+int norm2_blocks();
+
+int launch_fill_i32(int32_t* p, int32_t value, int64_t n, hipStream_t s);
+
+// Fit of a CP model from X = Y x_1 A_1^T ... x_N A_N^T (an R^N tensor):
+// <Y,Yhat> = sum_r lambda_r X[r,..,r]; ||Yhat||^2 from the Grams (eq. 9);
+// ||Y||^2 = scal[0].  out3 = {fit, ||Y||^2, <Y,Yhat>}.
+int launch_cp_fit_final(const float* X, int N, int R, const float* lambda,
+                        double* const* grams, const double* scal, double* out3,
+                        hipStream_t s);
+
+// convert FP64 <-> T copies
+template <typename Tin, typename Tout>
+int launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s);
+
+// ---- small FP64 linear algebra (linalg.hip) -------------------------------
+// Batched Householder QR: for b < nb, Zin[b] is I_b x K_b (row-major, T),
+// Q_out[b] receives the orthonormal factor (diag(R) >= 0), T.  ws64 is a
+// FP64 scratch of sum_b I_b*K_b*2 doubles.  rank_flag bit b set on a zero
+// pivot.
+struct QrBatch {
+  const void* Z[16];
+  void* Q[16];
+  double* work[16];
+  int64_t I[16];
+  int K[16];
+  int nb;
+};
+template <typename T>
+int launch_qr(const QrBatch& b, int32_t* rank_flag, hipStream_t s);
+
+// Batched symmetric eigen-decomposition by cyclic Jacobi (FP64).
+// S[b] is n_b x n_b (n_b <= 64), W[b] receives the top-k_b eigenvectors as
+// an n_b x k_b row-major matrix (descending eigenvalues, ties by index,
+// largest-|.| entry of each column positive); evals[b] (may be null) the
+// sorted eigenvalues.
+struct EigBatch {
+  const double* S[16];
+  double* W[16];
+  double* evals[16];
+  int n[16];
+  int k[16];
+  int nb;
+};
+int launch_eig(const EigBatch& b, hipStream_t s);
+
+// ---- FFCP (ffcp.hip) ------------------------------------------------------
+struct FfcpArgs {
+  int N, R, update, max_it;
+  double tol, l1, normY2;
+  int64_t I[8];
+  int Rn[8];
+  const float* U[8];
+  const float* G;
+  const float* A_init[8];  // user init (null when HOSVD)
+  const double* V_init[8]; // HOSVD: R_n x R in FP64 (already padded)
+  float* A_out[8];
+  float* lambda;
+  double* fit_trace;
+  void* info;              // rt_ffcp_info*
+  // FP64 workspace pointers
+  double* A[8];
+  double* V[8];
+  double* Gram[8];
+  double* U64[8];
+  double* G64;
+  double* H;       // max R_n x R
+  double* Qm;      // max I_n x R
+  double* T;       // R x R (+ Cholesky factor)
+  double* W1;      // prod R / min R_p * R  (MTTKRP partial)
+  double* W2;      // same size
+  double* scal;    // scalars
+};
+int launch_ffcp(const FfcpArgs& a, hipStream_t s);
+
+}  // namespace rt

@@ -1,0 +1,312 @@
+// Small FP64 factorizations of the method:
+//  * orthonormal basis of a sketch Z_n by Householder QR (Section IV-A,
+//    step 3 of the range finder; Algorithm 3, line 6), columns signed so
+//    that diag(R) >= 0;
+//  * symmetric eigen-decomposition (cyclic Jacobi, parallel ordering) of the
+//    R~ x R~ Gram matrices used to truncate the core and to build the HOSVD
+//    initialization of FFCP.
+// One workgroup per matrix; matrices of one call are batched over the grid.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kQrThreads = 256;
+constexpr int kQrWaves = kQrThreads / 64;
+
+// Block reduction of KMAX per-thread partial sums (entries c in [lo, hi)).
+template <int KMAX>
+__device__ void block_reduce_vec(double (&part)[KMAX], double* red /*[waves][KMAX]*/,
+                                 double* outv /*[KMAX]*/, int lo, int hi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) {
+    if (c >= lo && c < hi) {
+      double v = wave_sum(part[c]);
+      if (lane == 0) red[wave * KMAX + c] = v;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < KMAX; c += kQrThreads) {
+    if (c >= lo && c < hi) {
+      double s = 0.0;
+      for (int w = 0; w < kQrWaves; ++w) s += red[w * KMAX + c];
+      outv[c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// W: I x K working copy, column-major (W[c*I + i]); P: I x K output Q,
+// column-major FP64 scratch.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrBatch b,
+                                                        int32_t* rank_flag) {
+  __shared__ double red[kQrWaves * KMAX];
+  __shared__ double wv[KMAX];
+  __shared__ double tau[KMAX];
+  __shared__ double rdiag[KMAX];
+  __shared__ double sc[4];
+  const int m = blockIdx.x;
+  const int64_t I = b.I[m];
+  const int K = b.K[m];
+  const T* Z = static_cast<const T*>(b.Z[m]);
+  T* Qo = static_cast<T*>(b.Q[m]);
+  double* W = b.work[m];
+  double* P = W + I * K;
+  const int t = threadIdx.x;
+
+  for (int64_t l = t; l < I * K; l += kQrThreads) {
+    int64_t i = l / K;
+    int c = static_cast<int>(l % K);
+    W[c * I + i] = static_cast<double>(Z[l]);
+  }
+  __syncthreads();
+
+  for (int j = 0; j < K; ++j) {
+    // norm of the sub-diagonal part of column j
+    double part = 0.0;
+    for (int64_t i = j + 1 + t; i < I; i += kQrThreads) {
+      double x = W[j * I + i];
+      part += x * x;
+    }
+    double xnorm2 = block_sum(part, red);
+    if (t == 0) {
+      double alpha = W[j * I + j];
+      double beta, tj, scale;
+      if (xnorm2 == 0.0) {
+        tj = 0.0;  // H_j = I (LAPACK convention)
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        double nrm = sqrt(alpha * alpha + xnorm2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      tau[j] = tj;
+      rdiag[j] = beta;
+      sc[0] = scale;
+      W[j * I + j] = beta;
+      if (beta == 0.0 && rank_flag) atomicOr(rank_flag, 1 << m);
+    }
+    __syncthreads();
+    const double scale = sc[0];
+    const double tj = tau[j];
+    for (int64_t i = j + 1 + t; i < I; i += kQrThreads) W[j * I + i] *= scale;
+    __syncthreads();
+    if (tj == 0.0) continue;
+    // w_c = v^T W[:, c] for c > j, with v_j = 1 and v_i = W[j*I+i] (i > j)
+    double acc[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+    for (int64_t i = j + t; i < I; i += kQrThreads) {
+      double v = (i == j) ? 1.0 : W[j * I + i];
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c > j && c < K) acc[c] += v * W[c * I + i];
+    }
+    block_reduce_vec<KMAX>(acc, red, wv, j + 1, K);
+    for (int64_t l = t; l < (I - j) * (K - j - 1); l += kQrThreads) {
+      int64_t i = j + l % (I - j);
+      int c = j + 1 + static_cast<int>(l / (I - j));
+      double v = (i == j) ? 1.0 : W[j * I + i];
+      W[c * I + i] -= tj * wv[c] * v;
+    }
+    __syncthreads();
+  }
+
+  // Form Q = H_0 ... H_{K-1} [I_K; 0] (backward accumulation).
+  for (int64_t l = t; l < I * K; l += kQrThreads) {
+    int c = static_cast<int>(l / I);
+    int64_t i = l % I;
+    P[l] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = K - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    double acc[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+    for (int64_t i = j + t; i < I; i += kQrThreads) {
+      double v = (i == j) ? 1.0 : W[j * I + i];
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c >= j && c < K) acc[c] += v * P[c * I + i];
+    }
+    block_reduce_vec<KMAX>(acc, red, wv, j, K);
+    for (int64_t l = t; l < (I - j) * (K - j); l += kQrThreads) {
+      int64_t i = j + l % (I - j);
+      int c = j + static_cast<int>(l / (I - j));
+      double v = (i == j) ? 1.0 : W[j * I + i];
+      P[c * I + i] -= tj * wv[c] * v;
+    }
+    __syncthreads();
+  }
+  // diag(R) >= 0: flip the matching columns of Q.
+  for (int64_t l = t; l < I * K; l += kQrThreads) {
+    int64_t i = l / K;
+    int c = static_cast<int>(l % K);
+    double sgn = rdiag[c] < 0.0 ? -1.0 : 1.0;
+    Qo[l] = static_cast<T>(sgn * P[c * I + i]);
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi
+constexpr int kEigThreads = 256;
+constexpr int kEigMax = 64;
+
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
+  __shared__ double S[kEigMax][kEigMax + 1];
+  __shared__ double V[kEigMax][kEigMax + 1];
+  __shared__ double cs[kEigMax / 2][2];
+  __shared__ int pr[kEigMax / 2][2];
+  __shared__ double red[kEigThreads / 64];
+  __shared__ int rankpos[kEigMax];
+  const int m = blockIdx.x;
+  const int n = b.n[m];
+  const int k = b.k[m];
+  const int t = threadIdx.x;
+  const double* Sin = b.S[m];
+  for (int l = t; l < n * n; l += kEigThreads) {
+    int i = l / n, j = l % n;
+    S[i][j] = 0.5 * (Sin[i * n + j] + Sin[j * n + i]);
+    V[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int np = (n + 1) & ~1;  // even number of players (dummy = n)
+  double fro = 0.0;
+  {
+    double p = 0.0;
+    for (int l = t; l < n * n; l += kEigThreads) {
+      double x = S[l / n][l % n];
+      p += x * x;
+    }
+    fro = block_sum(p, red);
+  }
+  const double thresh = 1e-30 * fro + 1e-300;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double p = 0.0;
+    for (int l = t; l < n * n; l += kEigThreads) {
+      int i = l / n, j = l % n;
+      if (i != j) p += S[i][j] * S[i][j];
+    }
+    double off = block_sum(p, red);
+    if (off <= thresh) break;
+    for (int r = 0; r < np - 1; ++r) {
+      if (t < np / 2) {
+        int a = (t == 0) ? 0 : 1 + ((t - 1 + r) % (np - 1));
+        int q = 1 + ((np - 2 - t + r) % (np - 1));
+        int lo = a < q ? a : q, hi = a < q ? q : a;
+        pr[t][0] = lo;
+        pr[t][1] = hi;
+        double c = 1.0, s = 0.0;
+        if (hi < n) {
+          double apq = S[lo][hi];
+          if (apq != 0.0) {
+            double tau = (S[hi][hi] - S[lo][lo]) / (2.0 * apq);
+            double tt = (tau >= 0.0 ? 1.0 : -1.0) /
+                        (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        cs[t][0] = c;
+        cs[t][1] = s;
+      }
+      __syncthreads();
+      // rows: S <- J^T S
+      for (int l = t; l < (np / 2) * n; l += kEigThreads) {
+        int pi = l / n, j = l % n;
+        int p0 = pr[pi][0], q0 = pr[pi][1];
+        if (q0 >= n) continue;
+        double c = cs[pi][0], s = cs[pi][1];
+        double xp = S[p0][j], xq = S[q0][j];
+        S[p0][j] = c * xp - s * xq;
+        S[q0][j] = s * xp + c * xq;
+      }
+      __syncthreads();
+      // columns: S <- S J, V <- V J
+      for (int l = t; l < (np / 2) * n; l += kEigThreads) {
+        int pi = l / n, j = l % n;
+        int p0 = pr[pi][0], q0 = pr[pi][1];
+        if (q0 >= n) continue;
+        double c = cs[pi][0], s = cs[pi][1];
+        double xp = S[j][p0], xq = S[j][q0];
+        S[j][p0] = c * xp - s * xq;
+        S[j][q0] = s * xp + c * xq;
+        double vp = V[j][p0], vq = V[j][q0];
+        V[j][p0] = c * vp - s * vq;
+        V[j][q0] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // descending order, ties by ascending index
+  if (t < n) {
+    double lt = S[t][t];
+    int pos = 0;
+    for (int j = 0; j < n; ++j) {
+      double lj = S[j][j];
+      if (lj > lt || (lj == lt && j < t)) ++pos;
+    }
+    rankpos[t] = pos;
+  }
+  __syncthreads();
+  double* W = b.W[m];
+  for (int src = t; src < n; src += kEigThreads) {
+    int pos = rankpos[src];
+    if (pos >= k) continue;
+    // sign: largest |entry| positive, lowest index on ties
+    int jm = 0;
+    double vm = fabs(V[0][src]);
+    for (int j = 1; j < n; ++j) {
+      double a = fabs(V[j][src]);
+      if (a > vm) { vm = a; jm = j; }
+    }
+    double sgn = V[jm][src] < 0.0 ? -1.0 : 1.0;
+    for (int j = 0; j < n; ++j) W[j * k + pos] = sgn * V[j][src];
+    if (b.evals[m]) b.evals[m][pos] = S[src][src];
+  }
+}
+
+template <typename T, int KMAX>
+int qr_dispatch(const QrBatch& b, int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL((qr_kernel<T, KMAX>), dim3(b.nb), dim3(kQrThreads), 0, s,
+                     b, flag);
+  RT_LAUNCH_CHECK("qr");
+  return kOk;
+}
+
+}  // namespace
+
+template <typename T>
+int launch_qr(const QrBatch& b, int32_t* flag, hipStream_t s) {
+  int kmax = 0;
+  for (int i = 0; i < b.nb; ++i) kmax = b.K[i] > kmax ? b.K[i] : kmax;
+  if (kmax <= 16) return qr_dispatch<T, 16>(b, flag, s);
+  if (kmax <= 32) return qr_dispatch<T, 32>(b, flag, s);
+  if (kmax <= 64) return qr_dispatch<T, 64>(b, flag, s);
+  set_error("qr: width %d exceeds 64", kmax);
+  return kErrUnsupported;
+}
+
+template int launch_qr<float>(const QrBatch&, int32_t*, hipStream_t);
+template int launch_qr<double>(const QrBatch&, int32_t*, hipStream_t);
+
+int launch_eig(const EigBatch& b, hipStream_t s) {
+  for (int i = 0; i < b.nb; ++i) {
+    if (b.n[i] > kEigMax || b.k[i] > b.n[i]) {
+      set_error("eig: size %d (k=%d) unsupported", b.n[i], b.k[i]);
+      return kErrUnsupported;
+    }
+  }
+  hipLaunchKernelGGL(eig_kernel, dim3(b.nb), dim3(kEigThreads), 0, s, b);
+  RT_LAUNCH_CHECK("eig");
+  return kOk;
+}
+
+}  // namespace rt

@@ -1,0 +1,36 @@
+// Y-streaming passes of RandTucker2i: each pass reads the dense tensor once.
+//   stream_dual   : TA = Y x_N B_N^T and TB = Y x_{N-1} B_{N-1}^T (one sketch
+//                   sweep of Algorithm 3 needs both: every X_n with n < N is
+//                   reached from TA, X_N from TB)
+//   stream_single : TA = Y x_N Q_N^T (first contraction of the core,
+//                   Algorithm 3 line 8)
+// Y is viewed as [A, I_{N-1}, I_N] (A = prod_{p < N-1} I_p).
+#pragma once
+
+#include "../../include/rtucker.h"
+#include "common.hpp"
+
+namespace rt {
+
+struct StreamCtx {
+  const void* y;        // FP32 / FP64 tensor (or BF16 with RT_FLAG_BF16_INPUT)
+  uint16_t* ybf16;      // BF16 copy (mixed precision)
+  int precision;
+  bool bf16_input;
+  int64_t A, I1, I2;    // [A, I_{N-1}, I_N]
+  void* ws;
+  size_t ws_bytes;
+};
+
+size_t stream_workspace_bytes(const rt_tucker_desc* d);
+StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
+                          uint16_t* ybf16, void* ws, size_t ws_bytes);
+
+template <typename T>
+int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2,
+                const T* B1, int K1, T* TA, T* TB, hipStream_t s);
+template <typename T>
+int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
+                  hipStream_t s);
+
+}  // namespace rt

@@ -1,0 +1,116 @@
+"""C-ABI tests that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid descriptions on the host before any
+device work."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1412_1885_amd as P
+from paper_1412_1885_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f)
+           for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(rt_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = declared_functions()
+    assert "rt_tucker_rand" in names and "rt_ffcp" in names
+    for n in sorted(names):
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in P.version()
+    assert P.status_string(0) == "RT_OK"
+    assert P.status_string(-1) == "RT_ERR_INVALID_ARG"
+    assert P.status_string(-3) == "RT_ERR_WORKSPACE"
+
+
+def _ws(desc):
+    n = ctypes.c_size_t(0)
+    rc = P.lib().rt_tucker_rand_workspace(ctypes.byref(desc), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_tucker_workspace_validation():
+    ok = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7], sweeps=2)
+    rc, n = _ws(ok)
+    assert rc == 0 and n > 0
+    bad_cases = []
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7]); d.N = 1
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7]); d.sweeps = 3
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 13])   # R_n > R~_n
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 8], [10, 11, 12], [5, 6, 7])     # R~_n > I_n
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 60], [10, 11, 65], [5, 6, 7])    # R~ > 64
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7]); d.precision = 7
+    bad_cases.append(d)
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7], precision="f32",
+                      bf16_input=True)
+    bad_cases.append(d)
+    for d in bad_cases:
+        rc, _ = _ws(d)
+        assert rc == B.RT_F32 - 1, P.last_error()      # RT_ERR_INVALID_ARG
+        assert P.last_error()
+
+
+def test_gauss_seidel_flag_reports_unsupported():
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7])
+    d.flags |= B.RT_FLAG_GAUSS_SEIDEL
+    rc, _ = _ws(d)
+    assert rc == -2
+
+
+def test_tucker_rand_rejects_null_and_misaligned_pointers_before_launch():
+    d = P.tucker_desc([4, 5, 6], [2, 2, 2], [1, 1, 1])
+    vp = ctypes.c_void_p
+    arr = (vp * 3)(16, 32, 48)
+    rc = P.lib().rt_tucker_rand(ctypes.byref(d), None, arr, arr, vp(64), 1 << 20,
+                                arr, vp(80), None, None, None, None)
+    assert rc == -1 and "Y" in P.last_error()
+    rc = P.lib().rt_tucker_rand(ctypes.byref(d), vp(8), arr, arr, vp(64), 1 << 20,
+                                arr, vp(80), None, None, None, None)
+    assert rc == -1 and "aligned" in P.last_error()
+
+
+def test_ffcp_validation():
+    n = ctypes.c_size_t(0)
+    d = P.ffcp_desc([30, 40, 50], [5, 6, 7], 4, "hals")
+    assert P.lib().rt_ffcp_workspace(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value > 0
+    for mutate in (lambda d: setattr(d, "R", 0), lambda d: setattr(d, "R", 65),
+                   lambda d: setattr(d, "update", 5), lambda d: setattr(d, "max_it", 0),
+                   lambda d: setattr(d, "tol", -1.0)):
+        d = P.ffcp_desc([30, 40, 50], [5, 6, 7], 4)
+        mutate(d)
+        assert P.lib().rt_ffcp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1
+    d = P.ffcp_desc([30, 4, 50], [5, 6, 7], 4)   # R_n > I_n
+    assert P.lib().rt_ffcp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1
+
+
+def test_workspace_too_small_reported():
+    d = P.tucker_desc([4, 5, 6], [2, 2, 2], [1, 1, 1])
+    vp = ctypes.c_void_p
+    arr = (vp * 6)(*[256 * (i + 1) for i in range(6)])
+    rc = P.lib().rt_tucker_rand(ctypes.byref(d), vp(4096), arr, arr, vp(8192), 16,
+                                arr, vp(12288), None, None, None, None)
+    assert rc == -3 and "workspace" in P.last_error()

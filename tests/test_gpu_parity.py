@@ -1,0 +1,220 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs (FP32 values promoted exactly to FP64 for the oracle).
+
+Tolerances: FP64 path at the level of FP64 rounding; FP32 path at the level
+of FP32 accumulation over the contraction lengths used here (a few hundred
+to a few thousand terms): relative 1e-5 on sketches, 1e-4 on subspaces and
+aligned cores (the truncation divides by eigen-gaps of O(1) relative size).
+FFCP runs in FP64 on the device from the same FP32 U, G and initial A, so its
+iterates match the oracle's to 1e-9.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ffcp as F
+from oracle import randtucker as RT
+from oracle import tensor as T
+from oracle.metrics import aligned_core_error, projector_distance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1412_1885_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.lib()
+    return P
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ TTM
+
+@pytest.mark.parametrize("shape", [(37, 41, 43), (9, 10, 11, 12), (300, 2, 5)])
+@pytest.mark.parametrize("K", [5, 30])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ttm_parity(P, shape, K, dtype):
+    g = np.random.default_rng(hash((shape, K)) % 2**32)
+    Y = g.standard_normal(shape)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    tol = 2e-6 if dtype == "f32" else 1e-13
+    Yf = Y.astype(np.float32).astype(np.float64) if dtype == "f32" else Y
+    for n in range(len(shape)):
+        M = g.standard_normal((shape[n], K))
+        Mf = M.astype(np.float32).astype(np.float64) if dtype == "f32" else M
+        out = P.ttm(dev(Yf, tdt), dev(Mf, tdt), n)
+        assert rel(host(out), T.ttm_t(Yf, Mf, n)) <= tol
+
+
+# ------------------------------------------------------------ tucker_rand
+
+def run_tucker(P, d, ranks, sweeps, precision="f32", truncate=True):
+    tdt = torch.float64 if precision == "f64" else torch.float32
+    cast = (lambda a: a) if precision == "f64" else synth.f32
+    Y = cast(d["Y"])
+    om = [cast(o) for o in d["omegas"]]
+    omt = [[cast(o) for o in lst] for lst in d["omega_tildes"][:sweeps]]
+    out = P.tucker_rand(dev(Y, tdt), [dev(o, tdt) for o in om],
+                        [[dev(o, tdt) for o in lst] for lst in omt],
+                        ranks=ranks, sweeps=sweeps, precision=precision,
+                        truncate=truncate, trace=True)
+    ref = RT.rand_tucker(np.asarray(Y, np.float64), [np.asarray(o, np.float64) for o in om],
+                         [[np.asarray(o, np.float64) for o in lst] for lst in omt],
+                         sweeps=sweeps, ranks=ranks if truncate else None)
+    return out, ref, np.asarray(Y, np.float64)
+
+
+def check_tucker(out, ref, Y, N, sweeps, tol_z, tol_u, tol_g):
+    for s in range(sweeps):
+        for n in range(N):
+            z = host(out["trace"]["Z"][s * N + n])
+            assert rel(z, ref["Z"][s][n]) <= tol_z, ("Z", s, n)
+            q = host(out["trace"]["Q"][s * N + n])
+            assert projector_distance(q, ref["Q_sweeps"][s][n]) <= tol_u, ("Q", s, n)
+            assert np.linalg.norm(q.T @ q - np.eye(q.shape[1])) <= 10 * tol_z
+    for n in range(N):
+        assert projector_distance(host(out["U"][n]), ref["U"][n]) <= tol_u, ("U", n)
+    eG = aligned_core_error(host(out["G"]), [host(u) for u in out["U"]],
+                            ref["G"], ref["U"])
+    assert eG <= tol_g
+    info = out["info"]
+    assert abs(info["normY2"] - np.sum(Y * Y)) <= 1e-6 * np.sum(Y * Y)
+    assert info["nonfinite"] == 0
+
+
+def test_tucker_c1_fp64(P):
+    """100^3 CP rank 10 + noise at 40 dB, Omega_n 100 x 15, ranks (10,10,10):
+    the plain method in FP64 end to end."""
+    d = synth.case_cp_gaussian(1, (100, 100, 100), 10, 40.0, (15, 15, 15))
+    out, ref, Y = run_tucker(P, d, (10, 10, 10), 1, "f64")
+    check_tucker(out, ref, Y, 3, 1, 1e-12, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_tucker_fp32_3way_ragged(P, sweeps):
+    d = synth.case_tucker(301, (64, 72, 81), (6, 7, 8), 20.0, (12, 13, 14), sweeps=2)
+    out, ref, Y = run_tucker(P, d, (6, 7, 8), sweeps, "f32")
+    check_tucker(out, ref, Y, 3, sweeps, 1e-5, 1e-4, 1e-4)
+
+
+def test_tucker_fp32_4way(P):
+    d = synth.case_tucker(302, (18, 20, 22, 24), (4, 5, 6, 7), 30.0, (6, 7, 8, 9),
+                          sweeps=2)
+    out, ref, Y = run_tucker(P, d, (4, 5, 6, 7), 2, "f32")
+    check_tucker(out, ref, Y, 4, 2, 1e-5, 1e-4, 1e-4)
+
+
+def test_tucker_no_truncate(P):
+    d = synth.case_tucker(303, (30, 31, 32), (4, 4, 4), 30.0, (7, 8, 9))
+    out, ref, Y = run_tucker(P, d, None, 1, "f32", truncate=False)
+    for n in range(3):
+        assert projector_distance(host(out["U"][n]), ref["U"][n]) <= 1e-4
+    assert aligned_core_error(host(out["G"]), [host(u) for u in out["U"]],
+                              ref["G"], ref["U"]) <= 1e-4
+
+
+def test_tucker_nonfinite_flag(P):
+    d = synth.case_tucker(304, (20, 21, 22), (3, 3, 3), 30.0, (5, 5, 5))
+    Y = synth.f32(d["Y"]).copy()
+    Y[3, 4, 5] = np.nan
+    out = P.tucker_rand(dev(Y), [dev(synth.f32(o)) for o in d["omegas"]],
+                        [[dev(synth.f32(o)) for o in d["omega_tildes"][0]]],
+                        ranks=(3, 3, 3), sweeps=1)
+    assert out["info"]["nonfinite"] == 1
+
+
+# ------------------------------------------------------------------ FFCP
+
+def _tucker_format(seed, dims, ranks, nonneg=False):
+    g = np.random.default_rng(seed)
+    G = g.uniform(0, 1, ranks) if nonneg else g.standard_normal(ranks)
+    U = [np.linalg.qr(g.standard_normal((I, r)))[0] for I, r in zip(dims, ranks)]
+    return synth.f32(G).astype(np.float64), [synth.f32(u).astype(np.float64) for u in U], g
+
+
+@pytest.mark.parametrize("rule", ["als", "hals", "mu"])
+@pytest.mark.parametrize("dims,ranks,R", [((50, 60, 70), (6, 7, 8), 5),
+                                           ((30, 31, 32, 33), (4, 5, 4, 5), 3)])
+def test_ffcp_iterates(P, rule, dims, ranks, R):
+    nonneg = rule != "als"
+    G, U, g = _tucker_format(hash((rule, dims)) % 2**32, dims, ranks, nonneg)
+    A0 = [synth.f32(g.uniform(0, 1, (I, R)) if nonneg else g.standard_normal((I, R)))
+          .astype(np.float64) for I in dims]
+    iters = 12
+    out = P.ffcp([dev(u) for u in U], dev(G), R, update=rule,
+                 A_init=[dev(a) for a in A0], max_it=iters, tol=0.0, fit_trace=True)
+    ref = F.ffcp(U, G, A0, update=rule, max_it=iters, tol=0.0)
+    assert int(out["info"]["iterations"]) == iters
+    np.testing.assert_allclose(out["fits"], ref["fits"], rtol=0, atol=1e-9)
+    for n in range(len(dims)):
+        assert rel(host(out["A"][n]), ref["A"][n]) <= 1e-6    # FP32 output
+    assert rel(host(out["lam"]), ref["lam"]) <= 1e-6
+
+
+def test_ffcp_convergence_matches_oracle(P):
+    d = synth.case_cp_gaussian(2, (60, 61, 62), 4, 30.0, (8, 8, 8))
+    tk = RT.rand_tucker(synth.f32(d["Y"]).astype(np.float64), d["omegas"],
+                        d["omega_tildes"], sweeps=1, ranks=(6, 6, 6))
+    U = [synth.f32(u).astype(np.float64) for u in tk["U"]]
+    G = synth.f32(tk["G"]).astype(np.float64)
+    A0 = [synth.f32(a).astype(np.float64)
+          for a in synth.init_factors(d["init_rng"], (60, 61, 62), 4)]
+    out = P.ffcp([dev(u) for u in U], dev(G), 4, update="als",
+                 A_init=[dev(a) for a in A0], max_it=500, tol=1e-9, fit_trace=True)
+    ref = F.ffcp(U, G, A0, update="als", max_it=500, tol=1e-9)
+    assert abs(int(out["info"]["iterations"]) - ref["iterations"]) <= 2
+    assert abs(out["info"]["fit"] - ref["fits"][-1]) <= 1e-8
+    assert out["info"]["converged"] == int(ref["converged"])
+
+
+def test_ffcp_hosvd_init_with_padding(P):
+    G, U, g = _tucker_format(77, (40, 41, 42), (5, 6, 4))
+    R = 6
+    pad = [synth.f32(g.standard_normal((r, R - r))).astype(np.float64) if R > r else None
+           for r in (5, 6, 4)]
+    out = P.ffcp([dev(u) for u in U], dev(G), R, update="als", init="hosvd",
+                 pad=[dev(p) if p is not None else None for p in pad],
+                 max_it=3, tol=0.0, fit_trace=True)
+    A0 = F.hosvd_init(U, G, R, pad=pad)
+    ref = F.ffcp(U, G, A0, update="als", max_it=3, tol=0.0)
+    np.testing.assert_allclose(out["fits"], ref["fits"], rtol=0, atol=1e-9)
+    for n in range(3):
+        assert rel(host(out["A"][n]), ref["A"][n]) <= 1e-6
+
+
+def test_ffcp_ridge_flag(P):
+    G, U, g = _tucker_format(78, (20, 21, 22), (3, 3, 3))
+    A0 = [g.standard_normal((I, 3)) for I in (20, 21, 22)]
+    A0[1][:, 2] = 0.0
+    A0[2][:, 2] = 0.0
+    out = P.ffcp([dev(u) for u in U], dev(G), 3, update="als",
+                 A_init=[dev(a) for a in A0], max_it=3, tol=0.0)
+    ref = F.ffcp(U, G, A0, update="als", max_it=3, tol=0.0)
+    assert out["info"]["ridged"] == 1 and ref["ridged"]
+    for n in range(3):
+        assert np.all(np.isfinite(host(out["A"][n])))
+
+
+def test_cp_fit_dense(P):
+    d = synth.case_cp_gaussian(3, (30, 40, 50), 5, 20.0, (6, 6, 6))
+    Y = synth.f32(d["Y"]).astype(np.float64)
+    A = [synth.f32(a).astype(np.float64) for a in d["A_true"]]
+    lam = np.array([1.0, 0.5, 2.0, 1.5, 0.25], dtype=np.float32).astype(np.float64)
+    fit, y2, inner = P.cp_fit_dense(dev(Y), [dev(a) for a in A], dev(lam))
+    assert abs(fit - F.cp_fit_mttkrp(Y, A, lam)) <= 1e-6
+    assert abs(y2 - np.sum(Y * Y)) <= 1e-9 * np.sum(Y * Y)
