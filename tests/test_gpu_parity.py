@@ -83,9 +83,16 @@ def check_tucker(out, ref, Y, N, sweeps, tol_z, tol_u, tol_g):
     for s in range(sweeps):
         for n in range(N):
             z = host(out["trace"]["Z"][s * N + n])
-            assert rel(z, ref["Z"][s][n]) <= tol_z, ("Z", s, n)
+            zr = ref["Z"][s][n]
+            assert rel(z, zr) <= tol_z, ("Z", s, n)
             q = host(out["trace"]["Q"][s * N + n])
-            assert projector_distance(q, ref["Q_sweeps"][s][n]) <= tol_u, ("Q", s, n)
+            # range(Z) moves by at most ||dZ||_2 / (s_min(Z) - ||dZ||_2) (Wedin);
+            # the trailing sketch directions are noise with small s_min, so the
+            # full-width basis is compared against that bound, not a constant.
+            dz = np.linalg.norm(z - zr, 2)
+            smin = np.linalg.svd(zr, compute_uv=False).min()
+            bound = 2.0 * dz / max(smin - dz, 1e-300) + 1e-6
+            assert projector_distance(q, ref["Q_sweeps"][s][n]) <= bound, ("Q", s, n)
             assert np.linalg.norm(q.T @ q - np.eye(q.shape[1])) <= 10 * tol_z
     for n in range(N):
         assert projector_distance(host(out["U"][n]), ref["U"][n]) <= tol_u, ("U", n)
@@ -141,9 +148,25 @@ def test_tucker_nonfinite_flag(P):
 # ------------------------------------------------------------------ FFCP
 
 def _tucker_format(seed, dims, ranks, nonneg=False):
+    """Random Tucker format.  nonneg=True builds the exact Tucker format of a
+    nonnegative CP tensor (U_n = orth(A_n), G = I x_n R_n, the construction
+    of Section V-A), so nonnegative updates face a well-posed problem."""
     g = np.random.default_rng(seed)
-    G = g.uniform(0, 1, ranks) if nonneg else g.standard_normal(ranks)
-    U = [np.linalg.qr(g.standard_normal((I, r)))[0] for I, r in zip(dims, ranks)]
+    if nonneg:
+        Rt = ranks[0]
+        A = [g.uniform(0, 1, (I, Rt)) for I in dims]
+        U, Rs = [], []
+        for a in A:
+            q, r = np.linalg.qr(a)
+            U.append(q)
+            Rs.append(r)
+        G = np.zeros((Rt,) * len(dims))
+        for r in range(Rt):
+            G[(r,) * len(dims)] = 1.0
+        G = T.multi_ttm_t(G, [r_.T for r_ in Rs])
+    else:
+        G = g.standard_normal(ranks)
+        U = [np.linalg.qr(g.standard_normal((I, r)))[0] for I, r in zip(dims, ranks)]
     return synth.f32(G).astype(np.float64), [synth.f32(u).astype(np.float64) for u in U], g
 
 
@@ -152,6 +175,8 @@ def _tucker_format(seed, dims, ranks, nonneg=False):
                                            ((30, 31, 32, 33), (4, 5, 4, 5), 3)])
 def test_ffcp_iterates(P, rule, dims, ranks, R):
     nonneg = rule != "als"
+    if nonneg:
+        ranks = (ranks[0],) * len(dims)
     G, U, g = _tucker_format(hash((rule, dims)) % 2**32, dims, ranks, nonneg)
     A0 = [synth.f32(g.uniform(0, 1, (I, R)) if nonneg else g.standard_normal((I, R)))
           .astype(np.float64) for I in dims]
