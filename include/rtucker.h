@@ -267,6 +267,21 @@ int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,
            const void* X, const void* M, void* out, void* stream);
 
 /*
+ * One streamed pass over a dense tensor viewed as A slabs of I1 x I2 (the
+ * two contractions one Algorithm 3 sweep needs from Y, see rt_tucker_rand):
+ *     TA[a, i1, k] = sum_{i2} Y[a, i1, i2] B2[i2, k]     (A x I1 x K2)
+ *     TB[a, j, i2] = sum_{i1} B1[i1, j] Y[a, i1, i2]     (A x K1 x I2)
+ * TB and B1 may be NULL (core pass: TA only).  norm_out (device FP64[1],
+ * may be NULL) receives ||Y||_F^2.  dtype: RT_F32 or RT_F64 (same for all
+ * arrays).  All pointers device; K1, K2 <= RT_MAX_SKETCH.  Exported for
+ * kernel-level tests; ws: device scratch of >= 8192 bytes.
+ */
+int rt_stream_pass(int32_t dtype, int64_t A, int64_t I1, int64_t I2,
+                   const void* Y, const void* B2, int32_t K2, const void* B1,
+                   int32_t K1, void* TA, void* TB, double* norm_out,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Fit of a CP model against a dense tensor (Section III-B definition,
  * Fit = 1 - ||Y - Yhat|| / ||Y||) through one mode-N contraction of Y:
  * <Y, Yhat> = sum(lambda * A_N * (Y_(N) KR_{p<N} A_p)), ||Yhat||^2 from the
@@ -280,6 +295,27 @@ int rt_cp_fit_workspace(const rt_ffcp_desc* desc, size_t* bytes);
 int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
                     const float* const* A, const float* lambda, void* ws,
                     size_t ws_bytes, double* out3, void* stream);
+
+/*
+ * Stage timing (tracing).  When enabled, the library brackets each stage it
+ * enqueues with HIP events on the caller's stream; rt_profile_read waits for
+ * the recorded events and returns per-stage totals.  Host-side only; the
+ * events are created by the library (no device memory).
+ * Stages: 0 = first streamed pass over Y (sweep with conversion/norm),
+ * 1 = later sweep passes, 2 = core pass, 3 = intermediate contractions and
+ * sketch products, 4 = QR, 5 = truncation (Gram, eig, rotation), 6 = FFCP.
+ */
+#define RT_PROFILE_STAGES 8
+typedef struct {
+  double ms[RT_PROFILE_STAGES];   /* summed event time per stage          */
+  int64_t count[RT_PROFILE_STAGES]; /* number of bracketed launches        */
+} rt_profile;
+
+/* Turn stage timing on (1) or off (0); turning it on clears the totals. */
+int rt_profile_enable(int on);
+/* Synchronize the recorded events and fill *out; returns RT_ERR_HIP if an
+ * event query fails. */
+int rt_profile_read(rt_profile* out);
 
 /* Human-readable name of a status code (static string). */
 const char* rt_status_string(int status);

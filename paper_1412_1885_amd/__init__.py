@@ -10,6 +10,7 @@ from ._binding import (  # noqa: F401
     RtError, lib, version, status_string, last_error,
     tucker_desc, tucker_rand_workspace, tucker_rand,
     ffcp_desc, ffcp_workspace, ffcp, ttm, cp_fit_dense,
-    rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense,
+    rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense, rt_stream_pass,
+    stream_pass, profile_enable, profile_read,
     LIB_PATH,
 )

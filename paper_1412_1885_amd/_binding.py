@@ -83,6 +83,8 @@ def lib():
                               ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
                               ctypes.POINTER(vp), vp, vp, vp, vp]
         L.rt_ttm.argtypes = [i32, i64, i64, i64, i32, vp, vp, vp, vp]
+        L.rt_stream_pass.argtypes = [i32, i64, i64, i64, vp, vp, i32, vp, i32, vp, vp,
+                                     vp, vp, sz, vp]
         L.rt_cp_fit_workspace.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
         L.rt_cp_fit_dense.argtypes = [ctypes.POINTER(FfcpDesc), vp, ctypes.POINTER(vp),
                                       vp, vp, sz, vp, vp]
@@ -91,7 +93,8 @@ def lib():
         L.rt_last_error.restype = ctypes.c_char_p
         L.rt_version.restype = ctypes.c_char_p
         for f in ("rt_tucker_rand_workspace", "rt_tucker_rand", "rt_ffcp_workspace",
-                  "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense"):
+                  "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
+                  "rt_stream_pass", "rt_profile_enable", "rt_profile_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -314,6 +317,48 @@ def ttm(X, M, n, stream=None):
     return out
 
 
+def stream_pass(Y3, B2, B1=None, stream=None):
+    """rt_stream_pass on a device tensor viewed [A, I1, I2]: returns
+    (TA, TB or None, ||Y||^2)."""
+    torch = _torch()
+    _require_device(Y3, "Y")
+    A, I1, I2 = (int(x) for x in Y3.shape)
+    K2 = int(B2.shape[1])
+    TA = torch.empty((A, I1, K2), dtype=Y3.dtype, device=Y3.device)
+    TB = None
+    K1 = 0
+    if B1 is not None:
+        K1 = int(B1.shape[1])
+        TB = torch.empty((A, K1, I2), dtype=Y3.dtype, device=Y3.device)
+    nrm = torch.zeros(2, dtype=torch.float64, device=Y3.device)
+    ws = _workspace(8192, Y3.device)
+    dt = RT_F64 if Y3.dtype == torch.float64 else RT_F32
+    _check(lib().rt_stream_pass(dt, A, I1, I2, _ptr(Y3), _ptr(B2), K2, _ptr(B1), K1,
+                                _ptr(TA), _ptr(TB), _ptr(nrm), _ptr(ws), ws.numel(),
+                                _stream_handle(stream)))
+    torch.cuda.current_stream().synchronize()
+    return TA, TB, float(nrm[0].item())
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8)]
+
+
+PROFILE_STAGES = ("first_pass", "sweep_pass", "core_pass", "contract", "qr",
+                  "truncate", "ffcp", "reserved")
+
+
+def profile_enable(on=True):
+    _check(lib().rt_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """Per-stage {name: (total_ms, launches)} of the bracketed stages."""
+    p = Profile()
+    _check(lib().rt_profile_read(ctypes.byref(p)))
+    return {PROFILE_STAGES[i]: (p.ms[i], int(p.count[i])) for i in range(8)}
+
+
 def cp_fit_dense(Y, A, lam=None, stream=None):
     """rt_cp_fit_dense: (fit, ||Y||^2, <Y, Yhat>) of a CP model against Y."""
     torch = _torch()
@@ -337,3 +382,4 @@ rt_tucker_rand = tucker_rand
 rt_ffcp = ffcp
 rt_ttm = ttm
 rt_cp_fit_dense = cp_fit_dense
+rt_stream_pass = stream_pass

@@ -8,6 +8,7 @@
 #include "../../include/rtucker.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 #include "stream.hpp"
 
 namespace rt {
@@ -222,27 +223,22 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     return kErrWorkspace;
   }
   const int N = P.N, last = N - 1, second = N - 2;
-  const bool mixed = d->precision == RT_BF16_MIXED;
   RT_TRY(launch_fill_i32(P.iflags, 0, 8, s));
 
-  // ||Y||^2 and the non-finite flag (of the values the passes consume)
-  if (!mixed) {
-    RT_TRY(launch_norm2<T>(static_cast<const T*>(Yv), P.total, P.partial,
-                           norm2_blocks(), P.scal + 0, P.iflags + 0, s));
-  }
-
+  // ||Y||^2 and the non-finite flag come from the first streamed pass.
   const T* B[RT_MAX_MODES];
   for (int n = 0; n < N; ++n) B[n] = static_cast<const T*>(Om[n]);
-  StreamCtx sc = make_stream_ctx(d, Yv, Ybf16, P.stream_ws, P.stream_bytes);
+  StreamCtx sc = make_stream_ctx(d, Yv, Ybf16, P.stream_ws, P.stream_bytes,
+                                 P.scal + 0, P.iflags + 0);
 
   for (int sw = 0; sw < d->sweeps; ++sw) {
     // streamed pass: TA = Y x_last B_last^T, TB = Y x_second B_second^T
-    RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second],
-                          P.K[second], P.TA, P.TB, s));
-    if (mixed && sw == 0) {
-      RT_TRY(launch_norm2_bf16(sc.ybf16, P.total, P.partial, norm2_blocks(),
-                               P.scal + 0, P.iflags + 0, s));
+    {
+      ProfScope ps(sw == 0 ? kStageFirstPass : kStageSweepPass, s);
+      RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second],
+                            P.K[second], P.TA, P.TB, s));
     }
+    ProfScope ps_contract(kStageContract, s);
     for (int n = 0; n < N; ++n) {
       int64_t D[RT_MAX_MODES];
       int modes[RT_MAX_MODES], nm = 0;
@@ -266,6 +262,8 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       RT_TRY(launch_sketch_z<T>(X, static_cast<const T*>(Omt[sw * N + n]),
                                 P.Z[n], Apre, P.I[n], Cpost, P.K[n], s));
     }
+    ps_contract.~ProfScope();
+    new (&ps_contract) ProfScope(kStageQr, s);
     QrBatch qb{};
     qb.nb = N;
     for (int n = 0; n < N; ++n) {
@@ -684,6 +682,61 @@ int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,
                               static_cast<const double*>(M),
                               static_cast<double*>(out), A, I, C, K, s);
   set_error("rt_ttm: dtype %d unsupported", dtype);
+  return kErrInvalid;
+}
+
+int rt_stream_pass(int32_t dtype, int64_t A, int64_t I1, int64_t I2,
+                   const void* Y, const void* B2, int32_t K2, const void* B1,
+                   int32_t K1, void* TA, void* TB, double* norm_out, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (A < 1 || I1 < 1 || I2 < 1 || K2 < 1 || K2 > RT_MAX_SKETCH ||
+      (TB && (K1 < 1 || K1 > RT_MAX_SKETCH))) {
+    set_error("rt_stream_pass: bad sizes");
+    return kErrInvalid;
+  }
+  RT_TRY(check_ptr(Y, "Y"));
+  RT_TRY(check_ptr(B2, "B2"));
+  RT_TRY(check_ptr(TA, "TA"));
+  RT_TRY(check_ptr(ws, "ws"));
+  if (TB) {
+    RT_TRY(check_ptr(B1, "B1"));
+    RT_TRY(check_ptr(TB, "TB"));
+  }
+  if (ws_bytes < 8192) {
+    set_error("rt_stream_pass: workspace too small");
+    return kErrWorkspace;
+  }
+  rt_tucker_desc d{};
+  d.N = 3;
+  d.sweeps = 1;
+  d.precision = dtype;
+  d.dims[0] = A;
+  d.dims[1] = I1;
+  d.dims[2] = I2;
+  Arena ar(ws);
+  double* nout = ar.take<double>(1);
+  int32_t* flag = ar.take<int32_t>(4);
+  void* sws = ar.take<char>(8192 - 512);
+  StreamCtx sc = make_stream_ctx(&d, Y, nullptr, sws, 8192 - 512,
+                                 norm_out ? norm_out : nout, flag);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == RT_F32) {
+    if (TB)
+      return stream_dual<float>(sc, 0, static_cast<const float*>(B2), K2,
+                                static_cast<const float*>(B1), K1,
+                                static_cast<float*>(TA), static_cast<float*>(TB), s);
+    return stream_single<float>(sc, 0, static_cast<const float*>(B2), K2,
+                                static_cast<float*>(TA), s);
+  }
+  if (dtype == RT_F64) {
+    if (TB)
+      return stream_dual<double>(sc, 0, static_cast<const double*>(B2), K2,
+                                 static_cast<const double*>(B1), K1,
+                                 static_cast<double*>(TA), static_cast<double*>(TB), s);
+    return stream_single<double>(sc, 0, static_cast<const double*>(B2), K2,
+                                 static_cast<double*>(TA), s);
+  }
+  set_error("rt_stream_pass: dtype %d unsupported", dtype);
   return kErrInvalid;
 }
 

@@ -38,6 +38,10 @@ int launch_norm2_bf16(const uint16_t* X, int64_t n, double* partial,
                       hipStream_t s);
 int norm2_blocks();
 
+// out[0] = sum of nb partials (fixed order); flag |= 1 if it is not finite.
+int launch_sum_partials(const double* partial, int nb, double* out,
+                        int32_t* nonfinite, hipStream_t s);
+
 int launch_fill_i32(int32_t* p, int32_t value, int64_t n, hipStream_t s);
 
 // Fit of a CP model from X = Y x_1 A_1^T ... x_N A_N^T (an R^N tensor):

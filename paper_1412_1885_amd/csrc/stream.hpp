@@ -4,7 +4,8 @@
 //                   reached from TA, X_N from TB)
 //   stream_single : TA = Y x_N Q_N^T (first contraction of the core,
 //                   Algorithm 3 line 8)
-// Y is viewed as [A, I_{N-1}, I_N] (A = prod_{p < N-1} I_p).
+// Y is viewed as [A, I_{N-1}, I_N] (A = prod_{p < N-1} I_p).  The first
+// pass of a call also produces ||Y||^2 and the non-finite flag.
 #pragma once
 
 #include "../../include/rtucker.h"
@@ -20,11 +21,15 @@ struct StreamCtx {
   int64_t A, I1, I2;    // [A, I_{N-1}, I_N]
   void* ws;
   size_t ws_bytes;
+  double* norm_partial;  // per-workgroup partial sums of ||Y||^2 (in ws)
+  double* norm_out;      // ||Y||^2 (FP64), written by the first pass
+  int32_t* nonfinite;    // set to 1 if ||Y||^2 is not finite
 };
 
 size_t stream_workspace_bytes(const rt_tucker_desc* d);
 StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
-                          uint16_t* ybf16, void* ws, size_t ws_bytes);
+                          uint16_t* ybf16, void* ws, size_t ws_bytes,
+                          double* norm_out, int32_t* nonfinite);
 
 template <typename T>
 int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2,

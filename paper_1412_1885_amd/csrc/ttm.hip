@@ -222,6 +222,19 @@ __global__ __launch_bounds__(kThreads) void convert_kernel(
   if (i < n) out[i] = static_cast<Tout>(in[i]);
 }
 
+__global__ void sum_partials_checked_kernel(const double* __restrict__ partial,
+                                            int nb, double* __restrict__ out,
+                                            int32_t* __restrict__ nonfinite) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) acc += partial[i];
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    out[0] = s;
+    if (!isfinite(s) && nonfinite) nonfinite[0] = 1;
+  }
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (i < n) p[i] = v;
@@ -266,6 +279,14 @@ __global__ void cp_fit_final_kernel(const float* __restrict__ X, int N, int R,
 }
 
 }  // namespace
+
+int launch_sum_partials(const double* partial, int nb, double* out,
+                        int32_t* nonfinite, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_checked_kernel, dim3(1), dim3(kThreads), 0, s,
+                     partial, nb, out, nonfinite);
+  RT_LAUNCH_CHECK("sum_partials");
+  return kOk;
+}
 
 int launch_fill_i32(int32_t* p, int32_t value, int64_t n, hipStream_t s) {
   if (n <= 0) return kOk;

@@ -119,6 +119,19 @@ def test_tucker_fp32_3way_ragged(P, sweeps):
     check_tucker(out, ref, Y, 3, sweeps, 1e-5, 1e-4, 1e-4)
 
 
+@pytest.mark.parametrize("dims", [(9, 70, 260), (5, 50, 1000), (12, 61, 200),
+                                  (20, 33, 100), (7, 3, 36)])
+def test_tucker_fp32_mfma_streaming_shapes(P, dims):
+    """Shapes that exercise the MFMA streaming pass: last dimension a
+    multiple of 4 but not of 32 (ragged column tile), I_{N-1} not a multiple
+    of 32 (ragged row chunk), and 1, 2, 4 or 8 wavefronts sharing a slab."""
+    rt = tuple(min(12, d) for d in dims)
+    ranks = tuple(min(3, r) for r in rt)   # truncate to the signal's ranks
+    d = synth.case_tucker(305 + dims[2], dims, ranks, 30.0, rt, sweeps=2)
+    out, ref, Y = run_tucker(P, d, ranks, 2, "f32")
+    check_tucker(out, ref, Y, 3, 2, 1e-5, 2e-4, 2e-4)
+
+
 def test_tucker_fp32_4way(P):
     d = synth.case_tucker(302, (18, 20, 22, 24), (4, 5, 6, 7), 30.0, (6, 7, 8, 9),
                           sweeps=2)
@@ -243,3 +256,23 @@ def test_cp_fit_dense(P):
     fit, y2, inner = P.cp_fit_dense(dev(Y), [dev(a) for a in A], dev(lam))
     assert abs(fit - F.cp_fit_mttkrp(Y, A, lam)) <= 1e-6
     assert abs(y2 - np.sum(Y * Y)) <= 1e-9 * np.sum(Y * Y)
+
+
+# ----------------------------------------------------- streamed pass itself
+
+@pytest.mark.parametrize("shape", [(1, 32, 32), (3, 70, 260), (2, 50, 1000), (5, 61, 200),
+                                   (4, 33, 100), (6, 3, 36), (2, 40, 96), (3, 17, 44)])
+@pytest.mark.parametrize("K", [(30, 30), (12, 7), (25, 32)])
+def test_stream_pass_parity(P, shape, K):
+    g = np.random.default_rng(sum(shape) + K[0])
+    Y = synth.f32(g.standard_normal(shape)).astype(np.float64)
+    B2 = synth.f32(g.standard_normal((shape[2], K[0]))).astype(np.float64)
+    B1 = synth.f32(g.standard_normal((shape[1], K[1]))).astype(np.float64)
+    TA, TB, n2 = P.stream_pass(dev(Y), dev(B2), dev(B1))
+    assert rel(host(TA), T.ttm_t(Y, B2, 2)) <= 2e-6
+    assert rel(host(TB), T.ttm_t(Y, B1, 1)) <= 2e-6
+    # squares are summed in FP32 per 16-element tile, then in FP64
+    assert abs(n2 - np.sum(Y * Y)) <= 1e-6 * np.sum(Y * Y)
+    TA2, TB2, _ = P.stream_pass(dev(Y), dev(B2))
+    assert TB2 is None
+    assert rel(host(TA2), T.ttm_t(Y, B2, 2)) <= 2e-6
