@@ -138,6 +138,9 @@ struct TuckerPlan {
   double* qrwork[RT_MAX_MODES];
   T* Gt;
   T* Gtmp;
+  T* W0;
+  T* W1;
+  T* zpart;
   double* gram[RT_MAX_MODES];
   double* W[RT_MAX_MODES];
   T* WT[RT_MAX_MODES];
@@ -181,6 +184,19 @@ struct TuckerPlan {
     }
     Gt = ar.take<T>(core);
     Gtmp = ar.take<T>(core);
+    // expanded test matrices W_n and split-K partials of the sketch product
+    int64_t wmax = 0, imax = 0;
+    int kmax = 0;
+    for (int n = 0; n < N; ++n) {
+      const int64_t tsize = (n == last) ? sizeTB : sizeTA;
+      const int64_t w = tsize / I[n] * K[n];
+      wmax = w > wmax ? w : wmax;
+      imax = I[n] > imax ? I[n] : imax;
+      kmax = K[n] > kmax ? K[n] : kmax;
+    }
+    W0 = ar.take<T>(wmax);
+    W1 = ar.take<T>(wmax);
+    zpart = ar.take<T>((65536 + imax) * static_cast<int64_t>(kmax));
     stream_bytes = stream_workspace_bytes(d);
     stream_ws = ar.take<char>(stream_bytes);
     return ar.need;
@@ -208,6 +224,54 @@ int contract_chain(const T* base, int64_t* D, int N, const int* modes,
   }
   *result = src;
   return kOk;
+}
+
+// Z_n = X_(n) Omega~_n from the streamed intermediate T (TA for n < N-1,
+// TB for n = N-1): W_n = Omega~_n expanded by B_p in every mode p that T
+// still holds at full size (p != n), then Z_n[i, r] = sum_{a,c} T[a,i,c]
+// W_n[a,c,r] (split-K product).
+template <typename T, typename Plan>
+int sketch_from_intermediate(Plan& P, int n, const T* const* B, const T* Omt,
+                             hipStream_t s) {
+  const int N = P.N, last = N - 1, second = N - 2;
+  int64_t D[RT_MAX_MODES];
+  for (int p = 0; p < N; ++p) D[p] = P.I[p];
+  const T* base;
+  const int contracted = (n != last) ? last : second;
+  if (n != last) {
+    base = P.TA;
+    D[last] = P.K[last];
+  } else {
+    base = P.TB;
+    D[second] = P.K[second];
+  }
+  // W dims: modes p != n in order (all K_p initially), then R~_n.
+  int64_t Wd[RT_MAX_MODES];
+  int wm[RT_MAX_MODES], nw = 0;
+  for (int p = 0; p < N; ++p)
+    if (p != n) {
+      wm[nw] = p;
+      Wd[nw++] = P.K[p];
+    }
+  const T* src = Omt;
+  T* bufs[2] = {P.W0, P.W1};
+  int cur = 0;
+  for (int q = 0; q < nw; ++q) {
+    const int p = wm[q];
+    if (p == contracted) continue;  // T already holds this mode at K_p
+    int64_t Apre = 1, Cpost = P.K[n];
+    for (int r = 0; r < q; ++r) Apre *= Wd[r];
+    for (int r = q + 1; r < nw; ++r) Cpost *= Wd[r];
+    RT_TRY(launch_expand<T>(src, B[p], bufs[cur], Apre, P.I[p], P.K[p], Cpost, s));
+    Wd[q] = P.I[p];
+    src = bufs[cur];
+    cur ^= 1;
+  }
+  int64_t Apre = 1, Cpost = 1;
+  for (int p = 0; p < n; ++p) Apre *= D[p];
+  for (int p = n + 1; p < N; ++p) Cpost *= D[p];
+  return launch_sketch_gemm<T>(base, src, P.Z[n], P.zpart, Apre, P.I[n], Cpost,
+                               P.K[n], s);
 }
 
 template <typename T>
@@ -238,42 +302,25 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second],
                             P.K[second], P.TA, P.TB, s));
     }
-    ProfScope ps_contract(kStageContract, s);
-    for (int n = 0; n < N; ++n) {
-      int64_t D[RT_MAX_MODES];
-      int modes[RT_MAX_MODES], nm = 0;
-      const T* base;
-      for (int p = 0; p < N; ++p) D[p] = P.I[p];
-      if (n != last) {
-        base = P.TA;
-        D[last] = P.K[last];
-        for (int p = 0; p < last; ++p)
-          if (p != n) modes[nm++] = p;
-      } else {
-        base = P.TB;
-        D[second] = P.K[second];
-        for (int p = 0; p < second; ++p) modes[nm++] = p;
+    {
+      ProfScope ps(kStageContract, s);
+      for (int n = 0; n < N; ++n)
+        RT_TRY(sketch_from_intermediate<T>(P, n, B,
+                                           static_cast<const T*>(Omt[sw * N + n]), s));
+    }
+    {
+      ProfScope ps(kStageQr, s);
+      QrBatch qb{};
+      qb.nb = N;
+      for (int n = 0; n < N; ++n) {
+        qb.Z[n] = P.Z[n];
+        qb.Q[n] = P.Q[n];
+        qb.work[n] = P.qrwork[n];
+        qb.I[n] = P.I[n];
+        qb.K[n] = P.K[n];
       }
-      const T* X;
-      RT_TRY(contract_chain<T>(base, D, N, modes, nm, B, P.K, P.X0, P.X1, &X, s));
-      int64_t Apre = 1, Cpost = 1;
-      for (int p = 0; p < n; ++p) Apre *= D[p];
-      for (int p = n + 1; p < N; ++p) Cpost *= D[p];
-      RT_TRY(launch_sketch_z<T>(X, static_cast<const T*>(Omt[sw * N + n]),
-                                P.Z[n], Apre, P.I[n], Cpost, P.K[n], s));
+      RT_TRY(launch_qr<T>(qb, P.iflags + 1, s));
     }
-    ps_contract.~ProfScope();
-    new (&ps_contract) ProfScope(kStageQr, s);
-    QrBatch qb{};
-    qb.nb = N;
-    for (int n = 0; n < N; ++n) {
-      qb.Z[n] = P.Z[n];
-      qb.Q[n] = P.Q[n];
-      qb.work[n] = P.qrwork[n];
-      qb.I[n] = P.I[n];
-      qb.K[n] = P.K[n];
-    }
-    RT_TRY(launch_qr<T>(qb, P.iflags + 1, s));
     if (trace) {
       for (int n = 0; n < N; ++n) {
         const size_t bytes = P.I[n] * P.K[n] * sizeof(T);
@@ -291,16 +338,32 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
   }
 
   // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first, then the rest
-  RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
   {
+    ProfScope ps(kStageCorePass, s);
+    RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
+  }
+  {
+    ProfScope ps(kStageContract, s);
     int64_t D[RT_MAX_MODES];
     for (int p = 0; p < N; ++p) D[p] = P.I[p];
     D[last] = P.K[last];
-    int modes[RT_MAX_MODES], nm = 0;
-    for (int p = 0; p < last; ++p) modes[nm++] = p;
-    const T* X;
-    RT_TRY(contract_chain<T>(P.TA, D, N, modes, nm, B, P.K, P.X0, P.X1, &X, s));
-    if (hipMemcpyAsync(P.Gt, X, P.core * sizeof(T), hipMemcpyDeviceToDevice,
+    const T* src = P.TA;
+    T* bufs[2] = {P.X0, P.X1};
+    int cur = 0;
+    for (int p = last - 1; p >= 0; --p) {  // innermost remaining mode first
+      int64_t Apre = 1, Cpost = 1;
+      for (int q = 0; q < p; ++q) Apre *= D[q];
+      for (int q = p + 1; q < N; ++q) Cpost *= D[q];
+      if (Cpost <= 64 && static_cast<int64_t>(P.K[p]) * Cpost <= 4096)
+        RT_TRY(launch_ttm_small_c<T>(src, B[p], bufs[cur], Apre, D[p],
+                                     static_cast<int>(Cpost), P.K[p], s));
+      else
+        RT_TRY(launch_ttm<T>(src, B[p], bufs[cur], Apre, D[p], Cpost, P.K[p], s));
+      D[p] = P.K[p];
+      src = bufs[cur];
+      cur ^= 1;
+    }
+    if (hipMemcpyAsync(P.Gt, src, P.core * sizeof(T), hipMemcpyDeviceToDevice,
                        s) != hipSuccess)
       return hip_fail(hipGetLastError(), "core copy");
   }

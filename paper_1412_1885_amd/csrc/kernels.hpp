@@ -18,6 +18,21 @@ template <typename T>
 int launch_sketch_z(const T* X, const T* Om, T* Z, int64_t A, int64_t I,
                     int64_t C, int R, hipStream_t s);
 
+// ---- sketch products from streamed intermediates (sketch.hip) ------------
+// out[a, i, c] = sum_j B[i, j] X[a, j, c]  (expand mode: J -> I)
+template <typename T>
+int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
+                  int64_t C, hipStream_t s);
+// Z[i, r] = sum_{a, c} Tm[a, i, c] W[a*C + c, r]; part: split-K scratch of
+// (65536 + I) * R elements.
+template <typename T>
+int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
+                       int64_t I, int64_t C, int R, hipStream_t s);
+// out[a, k, c] = sum_i X[a, i, c] M[i, k] for C <= 64, K <= 64, K*C <= 4096.
+template <typename T>
+int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
+                       int C, int K, hipStream_t s);
+
 // S = X_(n) X_(n)^T in FP64 for X viewed [A, I, C] (I <= 64).
 template <typename T>
 int launch_gram_unfold(const T* X, double* S, int64_t A, int I, int64_t C,

@@ -1,7 +1,8 @@
 // Small FP64 factorizations of the method:
-//  * orthonormal basis of a sketch Z_n by Householder QR (Section IV-A,
-//    step 3 of the range finder; Algorithm 3, line 6), columns signed so
-//    that diag(R) >= 0;
+//  * orthonormal basis of a sketch Z_n (Section IV-A, step 3 of the range
+//    finder; Algorithm 3, line 6) with diag(R) >= 0: CholeskyQR2 in FP64,
+//    falling back to Householder QR when the sketch is numerically rank
+//    deficient;
 //  * symmetric eigen-decomposition (cyclic Jacobi, parallel ordering) of the
 //    R~ x R~ Gram matrices used to truncate the core and to build the HOSVD
 //    initialization of FFCP.
@@ -39,17 +40,16 @@ __device__ void block_reduce_vec(double (&part)[KMAX], double* red /*[waves][KMA
   __syncthreads();
 }
 
+// Householder QR of matrix m of the batch (LAPACK geqrf/orgqr scheme).
 // W: I x K working copy, column-major (W[c*I + i]); P: I x K output Q,
 // column-major FP64 scratch.
 template <typename T, int KMAX>
-__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrBatch b,
-                                                        int32_t* rank_flag) {
+__device__ void householder_qr(const QrBatch& b, int m, int32_t* rank_flag) {
   __shared__ double red[kQrWaves * KMAX];
   __shared__ double wv[KMAX];
   __shared__ double tau[KMAX];
   __shared__ double rdiag[KMAX];
   __shared__ double sc[4];
-  const int m = blockIdx.x;
   const int64_t I = b.I[m];
   const int K = b.K[m];
   const T* Z = static_cast<const T*>(b.Z[m]);
@@ -152,6 +152,103 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrBatch b,
     int c = static_cast<int>(l % K);
     double sgn = rdiag[c] < 0.0 ? -1.0 : 1.0;
     Qo[l] = static_cast<T>(sgn * P[c * I + i]);
+  }
+}
+
+// Cholesky of the K x K symmetric matrix S (LDS, row-major) in place into
+// its upper factor R (S = R^T R).  Returns false if a pivot is not
+// sufficiently positive (the sketch is numerically rank deficient).
+template <int KMAX>
+__device__ bool chol_upper(double* S, int K, double* flag) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double tr = 0.0;
+    for (int j = 0; j < K; ++j) tr += S[j * KMAX + j];
+    flag[0] = 1e-11 * tr / K;  // pivot floor
+    flag[1] = 1.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < K; ++j) {
+    if (t == 0) {
+      double d = S[j * KMAX + j];
+      if (!(d > flag[0])) {
+        flag[1] = 0.0;
+        d = 1.0;
+      }
+      S[j * KMAX + j] = sqrt(d);
+    }
+    __syncthreads();
+    const double rjj = S[j * KMAX + j];
+    for (int c = j + 1 + t; c < K; c += kQrThreads) S[j * KMAX + c] /= rjj;
+    __syncthreads();
+    const int n = K - j - 1;
+    for (int l = t; l < n * n; l += kQrThreads) {
+      const int r = j + 1 + l / n, c = j + 1 + l % n;
+      if (c >= r) S[r * KMAX + c] -= S[j * KMAX + r] * S[j * KMAX + c];
+    }
+    __syncthreads();
+  }
+  return flag[1] > 0.5;
+}
+
+// CholeskyQR2 in FP64: R1 = chol(Z^T Z), Q1 = Z R1^{-1}, R2 = chol(Q1^T Q1),
+// Q = Q1 R2^{-1}.  diag(R2 R1) > 0 by construction, so Q is the same unique
+// factor Householder QR with a positive diagonal gives (up to rounding).
+// Falls back to Householder when a Gram matrix is not positive definite.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrBatch b,
+                                                        int32_t* rank_flag) {
+  __shared__ double S[KMAX * KMAX];
+  __shared__ double fl[4];
+  const int m = blockIdx.x;
+  const int64_t I = b.I[m];
+  const int K = b.K[m];
+  const T* Z = static_cast<const T*>(b.Z[m]);
+  T* Qo = static_cast<T*>(b.Q[m]);
+  double* W = b.work[m];  // I x K row-major FP64 (Q1, then Q)
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  bool ok = true;
+  for (int pass = 0; pass < 2 && ok; ++pass) {
+    // Gram of the current matrix (Z in pass 0, Q1 in pass 1), upper part
+    for (int o = wave; o < K * K; o += kQrWaves) {
+      const int r = o / K, c = o % K;
+      if (c < r) continue;
+      double acc = 0.0;
+      if (pass == 0) {
+        for (int64_t i = lane; i < I; i += 64)
+          acc += static_cast<double>(Z[i * K + r]) * static_cast<double>(Z[i * K + c]);
+      } else {
+        for (int64_t i = lane; i < I; i += 64) acc += W[i * K + r] * W[i * K + c];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) S[r * KMAX + c] = acc;
+    }
+    __syncthreads();
+    ok = chol_upper<KMAX>(S, K, fl);
+    __syncthreads();
+    if (!ok) break;
+    // rows: q R = z  (forward substitution with the upper factor)
+    for (int64_t i = t; i < I; i += kQrThreads) {
+      double q[KMAX];
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        if (j < K) {
+          double v = pass == 0 ? static_cast<double>(Z[i * K + j]) : W[i * K + j];
+          for (int l = 0; l < j; ++l) v -= q[l] * S[l * KMAX + j];
+          q[j] = v / S[j * KMAX + j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < K) W[i * K + j] = q[j];
+    }
+    __syncthreads();
+  }
+  if (ok) {
+    for (int64_t l = t; l < I * K; l += kQrThreads) Qo[l] = static_cast<T>(W[l]);
+  } else {
+    householder_qr<T, KMAX>(b, m, rank_flag);
   }
 }
 

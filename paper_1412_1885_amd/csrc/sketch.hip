@@ -1,0 +1,239 @@
+// Sketch products of Algorithm 3 (line 5) computed from the streamed
+// intermediates without forming X_n.
+//
+// With T = Y x_{p in S} B_p^T the streamed intermediate (S = the modes one
+// pass contracted: {N} for TA, {N-1} for TB), the sketch of mode n is
+//     Z_n = X_(n) Omega~_n,   X_n = T x_{p not in S, p != n} B_p^T,
+// i.e. Z_n[i, r] = sum_{a, c} T[a, i, c] W_n[a, c, r]  with T viewed as
+// [A, I_n, C] and W_n = Omega~_n (reshaped over (j_p)_{p != n}) expanded in
+// every mode p not in S, p != n, by B_p (K_p -> I_p).  W_n is small (the
+// random test matrix of Section IV-A step 1 in Kronecker-structured form),
+// so each sketch is one split-K product instead of a chain of mode products.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// out[a, i, c] = sum_j B[i, j] X[a, j, c]; one thread per output (J <= 64).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void expand_kernel(
+    const T* __restrict__ X, const T* __restrict__ B, T* __restrict__ out,
+    int64_t A, int64_t I, int J, int64_t C) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= A * I * C) return;
+  const int64_t c = idx % C;
+  const int64_t t = idx / C;
+  const int64_t i = t % I;
+  const int64_t a = t / I;
+  const T* xp = X + a * J * C + c;
+  const T* bp = B + i * J;
+  T acc = T(0);
+  for (int j = 0; j < J; ++j) acc += bp[j] * xp[j * C];
+  out[idx] = acc;
+}
+
+// Split-K product part[s][i][r] = sum over the s-th range of k = a*C + c of
+// T[a, i, c] W[k, r].  Tile: 64 rows i x RT (<= 32 or 64) columns r, k in
+// chunks of 32 staged through LDS.  Loads are coalesced along c (C > 1) or
+// along i (C == 1).
+template <typename T, int RT>
+__global__ __launch_bounds__(kThreads) void sketch_gemm_kernel(
+    const T* __restrict__ Tm, const T* __restrict__ W, T* __restrict__ part,
+    int64_t A, int64_t I, int64_t C, int R, int64_t kper) {
+  constexpr int BI = 64, BK = 32;
+  __shared__ T ts[BK][BI + 1];
+  __shared__ T ws[BK][RT];
+  const int t = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * BI;
+  const int64_t K = A * C;
+  const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kper;
+  const int64_t k1 = (k0 + kper < K) ? k0 + kper : K;
+  // thread -> (row group, column group): 64 rows x RT cols over 256 threads
+  constexpr int CPT = RT / 4;  // columns per thread
+  const int ti = t & 63;       // row within tile
+  const int tc = t >> 6;       // column group 0..3
+  T acc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) acc[q] = T(0);
+  for (int64_t kb = k0; kb < k1; kb += BK) {
+    __syncthreads();
+    // stage T tile [BK x BI]
+    for (int l = t; l < BK * BI; l += kThreads) {
+      int kk, ii;
+      if (C == 1) {       // i contiguous
+        kk = l / BI;
+        ii = l % BI;
+      } else {            // c contiguous
+        kk = l % BK;
+        ii = l / BK;
+      }
+      const int64_t k = kb + kk, i = i0 + ii;
+      T v = T(0);
+      if (k < k1 && i < I) {
+        const int64_t a = k / C, c = k % C;
+        v = Tm[(a * I + i) * C + c];
+      }
+      ts[kk][ii] = v;
+    }
+    for (int l = t; l < BK * RT; l += kThreads) {
+      const int kk = l / RT, r = l % RT;
+      const int64_t k = kb + kk;
+      ws[kk][r] = (k < k1 && r < R) ? W[k * R + r] : T(0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < BK; ++kk) {
+      const T x = ts[kk][ti];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) acc[q] += x * ws[kk][tc * CPT + q];
+    }
+  }
+  const int64_t i = i0 + ti;
+  if (i < I) {
+    T* op = part + (static_cast<int64_t>(blockIdx.y) * I + i) * R;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int r = tc * CPT + q;
+      if (r < R) op[r] = acc[q];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void sum_splits_kernel(
+    const T* __restrict__ part, T* __restrict__ out, int64_t n, int S) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= n) return;
+  T acc = T(0);
+  for (int s = 0; s < S; ++s) acc += part[s * n + idx];  // fixed order
+  out[idx] = acc;
+}
+
+// out[a, k, c] = sum_i X[a, i, c] M[i, k] for small C (<= 64) and K (<= 64):
+// one workgroup per a, X[a] and M staged through LDS in 64-row chunks.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ttm_small_c_kernel(
+    const T* __restrict__ X, const T* __restrict__ M, T* __restrict__ out,
+    int64_t A, int64_t I, int C, int K) {
+  constexpr int BI = 64;
+  __shared__ T xs[BI][65];
+  __shared__ T ms[BI][65];
+  const int t = threadIdx.x;
+  const int64_t a = blockIdx.x;
+  // thread owns outputs (k, c) = (o / C, o % C) for o = t, t + 256, ...
+  const int nout = K * C;
+  T acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = T(0);
+  const T* xa = X + a * I * C;
+  for (int64_t i0 = 0; i0 < I; i0 += BI) {
+    __syncthreads();
+    const int rows = static_cast<int>((I - i0) < BI ? (I - i0) : BI);
+    for (int l = t; l < BI * C; l += kThreads) {
+      const int ii = l / C, c = l % C;
+      xs[ii][c] = ii < rows ? xa[(i0 + ii) * C + c] : T(0);
+    }
+    for (int l = t; l < BI * K; l += kThreads) {
+      const int ii = l / K, k = l % K;
+      ms[ii][k] = ii < rows ? M[(i0 + ii) * K + k] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int o = t + q * kThreads;
+      if (o < nout) {
+        const int k = o / C, c = o % C;
+        T s = acc[q];
+        for (int ii = 0; ii < rows; ++ii) s += xs[ii][c] * ms[ii][k];
+        acc[q] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int o = t + q * kThreads;
+    if (o < nout) {
+      const int k = o / C, c = o % C;
+      out[(a * K + k) * C + c] = acc[q];
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
+                  int64_t C, hipStream_t s) {
+  const int64_t n = A * I * C;
+  if (n <= 0) return kOk;
+  hipLaunchKernelGGL(expand_kernel<T>, dim3(static_cast<unsigned>(ceil_div(n, kThreads))),
+                     dim3(kThreads), 0, s, X, B, out, A, I, J, C);
+  RT_LAUNCH_CHECK("expand");
+  return kOk;
+}
+
+int64_t sketch_gemm_splits(int64_t I, int64_t K) {
+  const int64_t iblocks = ceil_div(I, 64);
+  int64_t S = ceil_div(1024, iblocks);
+  const int64_t maxS = ceil_div(K, 32);
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  return S;
+}
+
+template <typename T>
+int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
+                       int64_t I, int64_t C, int R, hipStream_t s) {
+  const int64_t K = A * C;
+  const int64_t S = sketch_gemm_splits(I, K);
+  int64_t kper = ceil_div(K, S);
+  kper = ceil_div(kper, 32) * 32;
+  const int64_t Sused = ceil_div(K, kper);
+  dim3 grid(static_cast<unsigned>(ceil_div(I, 64)), static_cast<unsigned>(Sused));
+  if (R <= 32) {
+    hipLaunchKernelGGL((sketch_gemm_kernel<T, 32>), grid, dim3(kThreads), 0, s, Tm,
+                       W, part, A, I, C, R, kper);
+  } else if (R <= 64) {
+    hipLaunchKernelGGL((sketch_gemm_kernel<T, 64>), grid, dim3(kThreads), 0, s, Tm,
+                       W, part, A, I, C, R, kper);
+  } else {
+    set_error("sketch width %d exceeds 64", R);
+    return kErrUnsupported;
+  }
+  RT_LAUNCH_CHECK("sketch_gemm");
+  const int64_t n = I * R;
+  hipLaunchKernelGGL(sum_splits_kernel<T>, dim3(static_cast<unsigned>(ceil_div(n, kThreads))),
+                     dim3(kThreads), 0, s, part, Z, n, static_cast<int>(Sused));
+  RT_LAUNCH_CHECK("sketch_gemm sum");
+  return kOk;
+}
+
+template <typename T>
+int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
+                       int C, int K, hipStream_t s) {
+  if (C > 64 || K > 64 || K * C > 16 * kThreads) {
+    set_error("ttm_small_c: C=%d K=%d unsupported", C, K);
+    return kErrUnsupported;
+  }
+  hipLaunchKernelGGL(ttm_small_c_kernel<T>, dim3(static_cast<unsigned>(A)),
+                     dim3(kThreads), 0, s, X, M, out, A, I, C, K);
+  RT_LAUNCH_CHECK("ttm_small_c");
+  return kOk;
+}
+
+#define RT_INST(T)                                                              \
+  template int launch_expand<T>(const T*, const T*, T*, int64_t, int64_t, int,  \
+                                int64_t, hipStream_t);                          \
+  template int launch_sketch_gemm<T>(const T*, const T*, T*, T*, int64_t,       \
+                                     int64_t, int64_t, int, hipStream_t);       \
+  template int launch_ttm_small_c<T>(const T*, const T*, T*, int64_t, int64_t,  \
+                                     int, int, hipStream_t);
+RT_INST(float)
+RT_INST(double)
+#undef RT_INST
+
+}  // namespace rt
