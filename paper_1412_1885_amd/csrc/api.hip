@@ -169,7 +169,7 @@ struct TuckerPlan {
     chain = sizeTA > sizeTB ? sizeTA : sizeTB;
     partial = ar.take<double>(norm2_blocks());
     scal = ar.take<double>(8);
-    iflags = ar.take<int32_t>(8);
+    iflags = ar.take<int32_t>(8 + 16);
     TA = ar.take<T>(sizeTA);
     TB = ar.take<T>(sizeTB);
     X0 = ar.take<T>(chain);
@@ -177,7 +177,7 @@ struct TuckerPlan {
     for (int n = 0; n < N; ++n) {
       Z[n] = ar.take<T>(I[n] * K[n]);
       Q[n] = ar.take<T>(I[n] * K[n]);
-      qrwork[n] = ar.take<double>(2 * I[n] * K[n]);
+      qrwork[n] = ar.take<double>(qr_work_doubles(I[n], K[n]));
       gram[n] = ar.take<double>(K[n] * K[n]);
       W[n] = ar.take<double>(K[n] * K[n]);
       WT[n] = ar.take<T>(K[n] * K[n]);
@@ -196,7 +196,10 @@ struct TuckerPlan {
     }
     W0 = ar.take<T>(wmax);
     W1 = ar.take<T>(wmax);
-    zpart = ar.take<T>((65536 + imax) * static_cast<int64_t>(kmax));
+    // the last core contraction also runs through the split-K product with
+    // prod_{p>1} R~_p rows
+    const int64_t rows_max = imax > core / K[0] ? imax : core / K[0];
+    zpart = ar.take<T>((65536 + rows_max) * static_cast<int64_t>(kmax));
     stream_bytes = stream_workspace_bytes(d);
     stream_ws = ar.take<char>(stream_bytes);
     return ar.need;
@@ -312,6 +315,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       ProfScope ps(kStageQr, s);
       QrBatch qb{};
       qb.nb = N;
+      qb.need = P.iflags + 4;
       for (int n = 0; n < N; ++n) {
         qb.Z[n] = P.Z[n];
         qb.Q[n] = P.Q[n];
@@ -350,11 +354,11 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     const T* src = P.TA;
     T* bufs[2] = {P.X0, P.X1};
     int cur = 0;
-    for (int p = last - 1; p >= 0; --p) {  // innermost remaining mode first
+    for (int p = last - 1; p >= 1; --p) {  // innermost remaining mode first
       int64_t Apre = 1, Cpost = 1;
       for (int q = 0; q < p; ++q) Apre *= D[q];
       for (int q = p + 1; q < N; ++q) Cpost *= D[q];
-      if (Cpost <= 64 && static_cast<int64_t>(P.K[p]) * Cpost <= 4096)
+      if (Cpost <= 64)
         RT_TRY(launch_ttm_small_c<T>(src, B[p], bufs[cur], Apre, D[p],
                                      static_cast<int>(Cpost), P.K[p], s));
       else
@@ -363,9 +367,12 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       src = bufs[cur];
       cur ^= 1;
     }
-    if (hipMemcpyAsync(P.Gt, src, P.core * sizeof(T), hipMemcpyDeviceToDevice,
-                       s) != hipSuccess)
-      return hip_fail(hipGetLastError(), "core copy");
+    // mode 1 last, as one split-K product over I_1 (rows = the other core
+    // indices), then transposed into G~ = [R~_1, ...].
+    const int64_t rest = P.core / P.K[0];
+    RT_TRY(launch_sketch_gemm<T>(src, B[0], bufs[cur], P.zpart, P.I[0], rest, 1,
+                                 P.K[0], s));
+    RT_TRY(launch_transpose<T>(bufs[cur], P.Gt, rest, P.K[0], s));
   }
   if (trace && trace->Gt &&
       hipMemcpyAsync(trace->Gt, P.Gt, P.core * sizeof(T),
@@ -386,7 +393,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     int64_t Apre = 1;
     for (int n = 0; n < N; ++n) {
       const int64_t Cpost = P.core / (Apre * P.K[n]);
-      RT_TRY(launch_gram_unfold<T>(P.Gt, P.gram[n], Apre, P.K[n], Cpost, s));
+      RT_TRY(launch_gram_waves<T>(P.Gt, P.gram[n], Apre, P.K[n], Cpost, s));
       Apre *= P.K[n];
       eb.S[n] = P.gram[n];
       eb.W[n] = P.W[n];

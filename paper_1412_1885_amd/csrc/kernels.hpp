@@ -28,7 +28,14 @@ int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
 template <typename T>
 int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
                        int64_t I, int64_t C, int R, hipStream_t s);
-// out[a, k, c] = sum_i X[a, i, c] M[i, k] for C <= 64, K <= 64, K*C <= 4096.
+// out[c][r] = in[r][c] (R x C matrix).
+template <typename T>
+int launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t s);
+// S = X_(n) X_(n)^T (FP64) for X viewed [A, I, C], one wavefront per entry.
+template <typename T>
+int launch_gram_waves(const T* X, double* S, int64_t A, int I, int64_t C,
+                      hipStream_t s);
+// out[a, k, c] = sum_i X[a, i, c] M[i, k] for C <= 64, K <= 64.
 template <typename T>
 int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
                        int C, int K, hipStream_t s);
@@ -82,9 +89,12 @@ struct QrBatch {
   int64_t I[16];
   int K[16];
   int nb;
+  int32_t* need;  // per-matrix flag: CholeskyQR2 failed, Householder ran
 };
 template <typename T>
 int launch_qr(const QrBatch& b, int32_t* rank_flag, hipStream_t s);
+// FP64 work doubles launch_qr needs per matrix (work[b])
+int64_t qr_work_doubles(int64_t I, int K);
 
 // Batched symmetric eigen-decomposition by cyclic Jacobi (FP64).
 // S[b] is n_b x n_b (n_b <= 64), W[b] receives the top-k_b eigenvectors as

@@ -44,7 +44,10 @@ __device__ void block_reduce_vec(double (&part)[KMAX], double* red /*[waves][KMA
 // W: I x K working copy, column-major (W[c*I + i]); P: I x K output Q,
 // column-major FP64 scratch.
 template <typename T, int KMAX>
-__device__ void householder_qr(const QrBatch& b, int m, int32_t* rank_flag) {
+__global__ __launch_bounds__(kQrThreads) void householder_kernel(
+    QrBatch b, int32_t* rank_flag, const int32_t* need) {
+  const int m = blockIdx.x;
+  if (need[m] == 0) return;  // CholeskyQR2 succeeded for this matrix
   __shared__ double red[kQrWaves * KMAX];
   __shared__ double wv[KMAX];
   __shared__ double tau[KMAX];
@@ -195,60 +198,153 @@ __device__ bool chol_upper(double* S, int K, double* flag) {
 // Q = Q1 R2^{-1}.  diag(R2 R1) > 0 by construction, so Q is the same unique
 // factor Householder QR with a positive diagonal gives (up to rounding).
 // Falls back to Householder when a Gram matrix is not positive definite.
+//
+// The row work is spread over many workgroups (row chunks x matrices):
+//   rows(0): partial Gram of Z per chunk
+//   chol(0): sum of the partials (fixed order), R1, R1^{-1}
+//   rows(1): Q1 = Z R1^{-1} (FP64, kept in work) and its partial Gram
+//   chol(1): R2, R2^{-1}
+//   rows(2): Q = Q1 R2^{-1}, written in the output type
+// Work layout per matrix (doubles): [0, IK) Q1 | [IK, 2IK) Householder
+// scratch | kQrChunks x K x K partial Grams | K x K inverse factor.
+constexpr int kQrChunks = 64;
+constexpr int kQrBlock = 64;  // rows staged in LDS at a time
+
+__host__ __device__ inline int64_t qr_rows_per_chunk(int64_t I) {
+  int64_t r = (I + kQrChunks - 1) / kQrChunks;
+  r = (r + kQrBlock - 1) / kQrBlock * kQrBlock;
+  return r < kQrBlock ? kQrBlock : r;
+}
+
 template <typename T, int KMAX>
-__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrBatch b,
-                                                        int32_t* rank_flag) {
-  __shared__ double S[KMAX * KMAX];
-  __shared__ double fl[4];
-  const int m = blockIdx.x;
+__global__ __launch_bounds__(kQrThreads) void qr_rows_kernel(QrBatch b, int phase) {
+  // thread -> (row group g, column c): c = t % KMAX, g = t / KMAX
+  constexpr int kG = kQrThreads / KMAX;
+  constexpr int kRowsPerThread = kQrBlock / kG;   // transform rows
+  constexpr int kGramRows = (KMAX + kG - 1) / kG; // Gram rows r = g + kG*q
+  __shared__ double zs[kQrBlock][KMAX + 1];
+  __shared__ double zo[kQrBlock][KMAX + 1];
+  __shared__ double Ri[KMAX][KMAX + 1];
+  const int m = blockIdx.y;
+  if (phase > 0 && b.need[m] != 0) return;
   const int64_t I = b.I[m];
   const int K = b.K[m];
+  const int64_t rpc = qr_rows_per_chunk(I);
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rpc;
+  if (r0 >= I) return;
+  const int64_t r1 = (r0 + rpc) < I ? (r0 + rpc) : I;
   const T* Z = static_cast<const T*>(b.Z[m]);
   T* Qo = static_cast<T*>(b.Q[m]);
-  double* W = b.work[m];  // I x K row-major FP64 (Q1, then Q)
+  double* W = b.work[m];
+  double* part = W + 2 * I * K;
+  const double* rinv = part + static_cast<int64_t>(kQrChunks) * K * K;
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  bool ok = true;
-  for (int pass = 0; pass < 2 && ok; ++pass) {
-    // Gram of the current matrix (Z in pass 0, Q1 in pass 1), upper part
-    for (int o = wave; o < K * K; o += kQrWaves) {
-      const int r = o / K, c = o % K;
-      if (c < r) continue;
-      double acc = 0.0;
-      if (pass == 0) {
-        for (int64_t i = lane; i < I; i += 64)
-          acc += static_cast<double>(Z[i * K + r]) * static_cast<double>(Z[i * K + c]);
-      } else {
-        for (int64_t i = lane; i < I; i += 64) acc += W[i * K + r] * W[i * K + c];
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) S[r * KMAX + c] = acc;
+  const int c = t % KMAX, g = t / KMAX;
+  if (phase > 0) {
+    for (int l = t; l < KMAX * KMAX; l += kQrThreads) {
+      const int i = l / KMAX, j = l % KMAX;
+      Ri[i][j] = (i < K && j < K) ? rinv[i * K + j] : 0.0;
+    }
+  }
+  double acc[kGramRows];
+#pragma unroll
+  for (int q = 0; q < kGramRows; ++q) acc[q] = 0.0;
+  for (int64_t i0 = r0; i0 < r1; i0 += kQrBlock) {
+    const int rows = static_cast<int>((r1 - i0) < kQrBlock ? (r1 - i0) : kQrBlock);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      const int ii = g + kG * q;
+      double v = 0.0;
+      if (ii < rows && c < K)
+        v = phase == 2 ? W[(i0 + ii) * K + c]
+                       : static_cast<double>(Z[(i0 + ii) * K + c]);
+      zs[ii][c] = v;
     }
     __syncthreads();
-    ok = chol_upper<KMAX>(S, K, fl);
-    __syncthreads();
-    if (!ok) break;
-    // rows: q R = z  (forward substitution with the upper factor)
-    for (int64_t i = t; i < I; i += kQrThreads) {
-      double q[KMAX];
+    double (*src)[KMAX + 1] = zs;
+    if (phase > 0) {
+      // row transform: out[ii][c] = sum_{l <= c} z[ii][l] Rinv[l][c]
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        if (j < K) {
-          double v = pass == 0 ? static_cast<double>(Z[i * K + j]) : W[i * K + j];
-          for (int l = 0; l < j; ++l) v -= q[l] * S[l * KMAX + j];
-          q[j] = v / S[j * KMAX + j];
+      for (int q = 0; q < kRowsPerThread; ++q) {
+        const int ii = g + kG * q;
+        double v = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < KMAX; ++l)
+          if (l <= c) v += zs[ii][l] * Ri[l][c];
+        zo[ii][c] = v;
+        if (ii < rows && c < K) {
+          if (phase == 1)
+            W[(i0 + ii) * K + c] = v;
+          else
+            Qo[(i0 + ii) * K + c] = static_cast<T>(v);
         }
       }
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < K) W[i * K + j] = q[j];
+      __syncthreads();
+      src = zo;
     }
-    __syncthreads();
+    if (phase < 2) {
+      // Gram rows r = g + kG*q, column c (padding rows/columns are zero)
+      for (int ii = 0; ii < rows; ++ii) {
+        const double zc = src[ii][c];
+#pragma unroll
+        for (int q = 0; q < kGramRows; ++q) {
+          const int r = g + kG * q;
+          if (r < KMAX) acc[q] += src[ii][r] * zc;
+        }
+      }
+    }
   }
-  if (ok) {
-    for (int64_t l = t; l < I * K; l += kQrThreads) Qo[l] = static_cast<T>(W[l]);
-  } else {
-    householder_qr<T, KMAX>(b, m, rank_flag);
+  if (phase < 2) {
+    double* pc = part + static_cast<int64_t>(blockIdx.x) * K * K;
+#pragma unroll
+    for (int q = 0; q < kGramRows; ++q) {
+      const int r = g + kG * q;
+      if (r < K && c < K) pc[r * K + c] = acc[q];
+    }
+  }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kQrThreads) void qr_chol_kernel(QrBatch b, int pass) {
+  __shared__ double S[KMAX * KMAX];
+  __shared__ double Rs[KMAX * KMAX];
+  __shared__ double fl[4];
+  const int m = blockIdx.x;
+  if (pass > 0 && b.need[m] != 0) return;
+  const int64_t I = b.I[m];
+  const int K = b.K[m];
+  double* part = b.work[m] + 2 * I * K;
+  double* rinv = part + static_cast<int64_t>(kQrChunks) * K * K;
+  const int64_t rpc = qr_rows_per_chunk(I);
+  const int chunks = static_cast<int>((I + rpc - 1) / rpc);
+  const int t = threadIdx.x;
+  for (int l = t; l < K * K; l += kQrThreads) {
+    const int r = l / K, cc = l % K;
+    double v = 0.0;
+    for (int ch = 0; ch < chunks; ++ch) v += part[static_cast<int64_t>(ch) * K * K + l];
+    S[r * KMAX + cc] = v;
+  }
+  __syncthreads();
+  const bool ok = chol_upper<KMAX>(S, K, fl);
+  __syncthreads();
+  if (!ok) {
+    if (t == 0) b.need[m] = 1;
+    return;
+  }
+  if (pass == 0 && t == 0) b.need[m] = 0;
+  // R^{-1}: thread j back-substitutes column j (upper triangular)
+  for (int j = t; j < K; j += kQrThreads) {
+    for (int i = j; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) v -= S[i * KMAX + k] * Rs[k * KMAX + j];
+      Rs[i * KMAX + j] = v / S[i * KMAX + i];
+    }
+  }
+  __syncthreads();
+  for (int l = t; l < K * K; l += kQrThreads) {
+    const int i = l / K, j = l % K;
+    rinv[l] = (i <= j) ? Rs[i * KMAX + j] : 0.0;
   }
 }
 
@@ -284,7 +380,9 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
     }
     fro = block_sum(p, red);
   }
-  const double thresh = 1e-30 * fro + 1e-300;
+  // off-diagonal norm below 1e-13 of the matrix norm (above the rounding
+  // floor of the rotations, so the loop ends after a few sweeps)
+  const double thresh = 1e-26 * fro + 1e-300;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double p = 0.0;
     for (int l = t; l < n * n; l += kEigThreads) {
@@ -315,29 +413,28 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
         cs[t][1] = s;
       }
       __syncthreads();
-      // rows: S <- J^T S
-      for (int l = t; l < (np / 2) * n; l += kEigThreads) {
-        int pi = l / n, j = l % n;
-        int p0 = pr[pi][0], q0 = pr[pi][1];
-        if (q0 >= n) continue;
-        double c = cs[pi][0], s = cs[pi][1];
-        double xp = S[p0][j], xq = S[q0][j];
-        S[p0][j] = c * xp - s * xq;
-        S[q0][j] = s * xp + c * xq;
+      // rows: S <- J^T S (lane = column j, waves take pairs in turn)
+      const int jl = t & 63;
+      for (int pi = t >> 6; pi < np / 2; pi += kEigThreads / 64) {
+        const int p0 = pr[pi][0], q0 = pr[pi][1];
+        if (q0 >= n || jl >= n) continue;
+        const double c = cs[pi][0], s = cs[pi][1];
+        const double xp = S[p0][jl], xq = S[q0][jl];
+        S[p0][jl] = c * xp - s * xq;
+        S[q0][jl] = s * xp + c * xq;
       }
       __syncthreads();
       // columns: S <- S J, V <- V J
-      for (int l = t; l < (np / 2) * n; l += kEigThreads) {
-        int pi = l / n, j = l % n;
-        int p0 = pr[pi][0], q0 = pr[pi][1];
-        if (q0 >= n) continue;
-        double c = cs[pi][0], s = cs[pi][1];
-        double xp = S[j][p0], xq = S[j][q0];
-        S[j][p0] = c * xp - s * xq;
-        S[j][q0] = s * xp + c * xq;
-        double vp = V[j][p0], vq = V[j][q0];
-        V[j][p0] = c * vp - s * vq;
-        V[j][q0] = s * vp + c * vq;
+      for (int pi = t >> 6; pi < np / 2; pi += kEigThreads / 64) {
+        const int p0 = pr[pi][0], q0 = pr[pi][1];
+        if (q0 >= n || jl >= n) continue;
+        const double c = cs[pi][0], s = cs[pi][1];
+        const double xp = S[jl][p0], xq = S[jl][q0];
+        S[jl][p0] = c * xp - s * xq;
+        S[jl][q0] = s * xp + c * xq;
+        const double vp = V[jl][p0], vq = V[jl][q0];
+        V[jl][p0] = c * vp - s * vq;
+        V[jl][q0] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -372,13 +469,29 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
 
 template <typename T, int KMAX>
 int qr_dispatch(const QrBatch& b, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL((qr_kernel<T, KMAX>), dim3(b.nb), dim3(kQrThreads), 0, s,
-                     b, flag);
-  RT_LAUNCH_CHECK("qr");
+  const dim3 rows_grid(kQrChunks, b.nb);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL((qr_rows_kernel<T, KMAX>), rows_grid, dim3(kQrThreads), 0, s,
+                       b, pass);
+    RT_LAUNCH_CHECK("qr rows");
+    hipLaunchKernelGGL((qr_chol_kernel<KMAX>), dim3(b.nb), dim3(kQrThreads), 0, s,
+                       b, pass);
+    RT_LAUNCH_CHECK("qr chol");
+  }
+  hipLaunchKernelGGL((qr_rows_kernel<T, KMAX>), rows_grid, dim3(kQrThreads), 0, s, b,
+                     2);
+  RT_LAUNCH_CHECK("qr rows");
+  hipLaunchKernelGGL((householder_kernel<T, KMAX>), dim3(b.nb), dim3(kQrThreads),
+                     0, s, b, flag, static_cast<const int32_t*>(b.need));
+  RT_LAUNCH_CHECK("qr fallback");
   return kOk;
 }
 
 }  // namespace
+
+int64_t qr_work_doubles(int64_t I, int K) {
+  return 2 * I * K + static_cast<int64_t>(kQrChunks + 1) * K * K;
+}
 
 template <typename T>
 int launch_qr(const QrBatch& b, int32_t* flag, hipStream_t s) {

@@ -114,52 +114,96 @@ __global__ __launch_bounds__(kThreads) void sum_splits_kernel(
 }
 
 // out[a, k, c] = sum_i X[a, i, c] M[i, k] for small C (<= 64) and K (<= 64):
-// one workgroup per a, X[a] and M staged through LDS in 64-row chunks.
+// one workgroup per a; X[a] and M staged through LDS in 64-row chunks; each
+// thread owns a 4 (k) x 4 (c) register block of the output.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void ttm_small_c_kernel(
     const T* __restrict__ X, const T* __restrict__ M, T* __restrict__ out,
     int64_t A, int64_t I, int C, int K) {
   constexpr int BI = 64;
-  __shared__ T xs[BI][65];
-  __shared__ T ms[BI][65];
+  __shared__ T xs[BI][64];
+  __shared__ T ms[BI][64];
   const int t = threadIdx.x;
   const int64_t a = blockIdx.x;
-  // thread owns outputs (k, c) = (o / C, o % C) for o = t, t + 256, ...
-  const int nout = K * C;
-  T acc[16];
+  const int kb = (t >> 4) * 4, cb = (t & 15) * 4;
+  T acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = T(0);
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
   const T* xa = X + a * I * C;
   for (int64_t i0 = 0; i0 < I; i0 += BI) {
     __syncthreads();
     const int rows = static_cast<int>((I - i0) < BI ? (I - i0) : BI);
-    for (int l = t; l < BI * C; l += kThreads) {
-      const int ii = l / C, c = l % C;
-      xs[ii][c] = ii < rows ? xa[(i0 + ii) * C + c] : T(0);
-    }
-    for (int l = t; l < BI * K; l += kThreads) {
-      const int ii = l / K, k = l % K;
-      ms[ii][k] = ii < rows ? M[(i0 + ii) * K + k] : T(0);
+    for (int l = t; l < BI * 64; l += kThreads) {
+      const int ii = l >> 6, c = l & 63;
+      xs[ii][c] = (ii < rows && c < C) ? xa[(i0 + ii) * C + c] : T(0);
+      ms[ii][c] = (ii < rows && c < K) ? M[(i0 + ii) * K + c] : T(0);
     }
     __syncthreads();
+    for (int ii = 0; ii < rows; ++ii) {
+      T xv[4], mv[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int o = t + q * kThreads;
-      if (o < nout) {
-        const int k = o / C, c = o % C;
-        T s = acc[q];
-        for (int ii = 0; ii < rows; ++ii) s += xs[ii][c] * ms[ii][k];
-        acc[q] = s;
+      for (int j = 0; j < 4; ++j) {
+        xv[j] = xs[ii][cb + j];
+        mv[j] = ms[ii][kb + j];
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += mv[i] * xv[j];
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int o = t + q * kThreads;
-    if (o < nout) {
-      const int k = o / C, c = o % C;
-      out[(a * K + k) * C + c] = acc[q];
-    }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (kb + i < K && cb + j < C) out[(a * K + kb + i) * C + cb + j] = acc[i][j];
+}
+
+// out[c][r] = in[r][c] for an R x C matrix (tiled through LDS).
+template <typename T>
+__global__ void transpose_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                 int64_t R, int64_t C) {
+  __shared__ T tl[32][33];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 32, c0 = static_cast<int64_t>(blockIdx.x) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + j, c = c0 + tx;
+    tl[j][tx] = (r < R && c < C) ? in[r * C + c] : T(0);
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t c = c0 + j, r = r0 + tx;
+    if (r < R && c < C) out[c * R + r] = tl[tx][j];
+  }
+}
+
+// S = X_(n) X_(n)^T in FP64 for X viewed [A, I, C]; one wavefront per
+// entry of the upper triangle (lanes stride the (a, c) pairs).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gram_waves_kernel(
+    const T* __restrict__ X, double* __restrict__ S, int64_t A, int I, int64_t C) {
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (pair >= I * (I + 1) / 2) return;
+  int o = pair, r = 0;
+  while (o >= I - r) {
+    o -= I - r;
+    ++r;
+  }
+  const int c2 = r + o;
+  double acc = 0.0;
+  const int64_t n = A * C;
+  for (int64_t l = lane; l < n; l += 64) {
+    const int64_t a = l / C, c = l % C;
+    acc += static_cast<double>(X[(a * I + r) * C + c]) *
+           static_cast<double>(X[(a * I + c2) * C + c]);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    S[r * I + c2] = acc;
+    S[c2 * I + r] = acc;
   }
 }
 
@@ -213,9 +257,27 @@ int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
 }
 
 template <typename T>
+int launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t s) {
+  dim3 grid(static_cast<unsigned>(ceil_div(C, 32)), static_cast<unsigned>(ceil_div(R, 32)));
+  hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, in, out, R, C);
+  RT_LAUNCH_CHECK("transpose");
+  return kOk;
+}
+
+template <typename T>
+int launch_gram_waves(const T* X, double* S, int64_t A, int I, int64_t C,
+                      hipStream_t s) {
+  const int npairs = I * (I + 1) / 2;
+  hipLaunchKernelGGL(gram_waves_kernel<T>, dim3((npairs + 3) / 4), dim3(kThreads), 0,
+                     s, X, S, A, I, C);
+  RT_LAUNCH_CHECK("gram_waves");
+  return kOk;
+}
+
+template <typename T>
 int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
                        int C, int K, hipStream_t s) {
-  if (C > 64 || K > 64 || K * C > 16 * kThreads) {
+  if (C > 64 || K > 64) {
     set_error("ttm_small_c: C=%d K=%d unsupported", C, K);
     return kErrUnsupported;
   }
@@ -231,7 +293,10 @@ int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
   template int launch_sketch_gemm<T>(const T*, const T*, T*, T*, int64_t,       \
                                      int64_t, int64_t, int, hipStream_t);       \
   template int launch_ttm_small_c<T>(const T*, const T*, T*, int64_t, int64_t,  \
-                                     int, int, hipStream_t);
+                                     int, int, hipStream_t);                    \
+  template int launch_transpose<T>(const T*, T*, int64_t, int64_t, hipStream_t); \
+  template int launch_gram_waves<T>(const T*, double*, int64_t, int, int64_t,   \
+                                    hipStream_t);
 RT_INST(float)
 RT_INST(double)
 #undef RT_INST

@@ -10,18 +10,19 @@
 // eq. (22) restricted to one GPU: each workgroup owns whole slabs, and the
 // partial products over column ranges are summed in a fixed order.
 //
-// Matrix cores: v_mfma_f32_32x32x2f32 (FP32 path).  A wavefront owns a
-// 32-row chunk of a slab and a range of CT 32-column tiles:
-//   P tile (32 rows x 32 of K2): A operand = M rows (lane (m, h) holds
-//       M[r0+m][c0+16h+4u+e], loaded as float4), B operand = B2 rows held in
-//       registers for the wave's whole column range;
-//   Q tiles (32 of K1 x 32 cols): A operand = B1 rows of the chunk, B
-//       operand = M[r0+2t+h][c0+m] (coalesced 128-byte row segments).
-// The K index of each MFMA is a permutation of the contracted index, applied
-// identically to both operands.  The same tile is read twice in two layouts;
-// the second read hits the caches, so HBM sees one read of Y.
-// ||Y||^2 (FP64) and a non-finite check ride along on the P-layout loads,
-// which touch every element exactly once.
+// Data path.  A wavefront owns a range of CT 32-column tiles of a slab and
+// walks the slab in 32-row chunks.  Each 32 x 32 FP32 tile is read from HBM
+// once with fully coalesced float4 loads (8 rows x 128 bytes per
+// instruction, prefetched one tile ahead across chunks), written to a
+// wave-private LDS tile whose 16-byte chunks are XOR-swizzled by row, and
+// read back in the two operand layouts of v_mfma_f32_32x32x2f32:
+//   P (32 rows x 32 of K2): A operand M[r0+m][c0+16h+4u+e] (b128 reads),
+//       B operand B2[c0+16h+4u+e][m] (registers, or LDS in the sweep pass);
+//   Q (32 of K1 x 32 cols): A operand B1[r0+2t+h][m], B operand
+//       M[r0+2t+h][c0+m] (b32 reads).
+// The K index of each MFMA is a permutation of the contracted index applied
+// identically to both operands.  ||Y||^2 (FP64) and a non-finite check ride
+// along on the staged values, which cover every element exactly once.
 #include "stream.hpp"
 
 #include "kernels.hpp"
@@ -34,7 +35,8 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
-constexpr int kMaxCT = 4;  // 32-column tiles per wave (register budget)
+constexpr int kMaxCT = 4;     // 32-column tiles per wave (register budget)
+constexpr int kTile = 1024;   // floats per staged 32 x 32 tile
 
 struct DualArgs {
   const float* Y;
@@ -47,23 +49,17 @@ struct DualArgs {
   float* TA;
   float* TB;
   int wps;          // wavefronts per slab (1, 2, 4 or 8)
-  int red_offset;   // float offset of the P-reduction tiles in LDS
+  int stage_offset; // float offset of the per-wave tiles in dynamic LDS
   double* norm_partial;  // per workgroup, or null
 };
 
-// Raw buffer resource over one slab, used for 32-bit loads: offsets >=
-// `bytes` read as zero (hardware range check), which masks rows past the
-// slab end; the row step of the Q layout goes in the scalar offset.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const float* base,
-                                                            uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, bytes,
-                                           0x00020000);
-}
-
-constexpr uint32_t kOob = 0x7ffffff0u;  // any offset past every slab
-
 __device__ __forceinline__ float4 ld4(const float* p) {
   return *reinterpret_cast<const float4*>(p);
+}
+
+// Position of logical (row, 16-byte chunk) in a staged tile.
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return row * 32 + 4 * (chunk ^ (row & 7));
 }
 
 // DOQ = true: sweep pass (P and Q; B2 in LDS to leave registers to the Q
@@ -71,10 +67,11 @@ __device__ __forceinline__ float4 ld4(const float* p) {
 template <int CT, bool DOQ>
 __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
   extern __shared__ float lds[];
-  float* b2s = lds;                     // B2, I2 x K2 row-major (DOQ only)
-  float* red = lds + p.red_offset;      // kWaves partial P tiles (32 x 32)
-  __shared__ double nred[kWaves];
+  float* b2s = lds;                                    // I2 x K2 (DOQ only)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* tile = lds + p.stage_offset + wave * kTile;   // this wave's tile
+  float* stage = lds + p.stage_offset;                 // all tiles (reduction)
+  __shared__ double nred[kWaves];
   const int m = lane & 31, h = lane >> 5;
   const int wps = p.wps, G = kWaves / wps;
   const int g = wave / wps, sub = wave % wps;
@@ -100,20 +97,33 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
   }
   double nacc = 0.0;
   const int64_t slab = static_cast<int64_t>(I1) * I2;
-  const uint32_t slab_bytes = static_cast<uint32_t>(slab * 4);
+  // coalesced load mapping: lane -> (row 8u + lrow, 16-byte chunk lchunk)
+  const int lrow = lane >> 3, lchunk = lane & 7;
 
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * G; base < p.A;
        base += static_cast<int64_t>(gridDim.x) * G) {
     const int64_t a = base + g;
     const bool live = a < p.A;
-    const __amdgpu_buffer_rsrc_t rs = slab_rsrc(p.Y + (live ? a : 0) * slab,
-                                               live ? slab_bytes : 0u);
+    const float* Ysl = p.Y + (live ? a : 0) * slab;
     v16f accq[DOQ ? CT : 1];
     if constexpr (DOQ) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) accq[ct] = v16f{};
     }
+    float4 gcur[4], gnext[4];
+    auto load_tile = [&](int rr, int ct, float4(&dst)[4]) {
+      const int col = colbase + 32 * ct + 4 * lchunk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = rr + 8 * u + lrow;
+        dst[u] = (live && row < I1 && col < I2)
+                     ? ld4(Ysl + static_cast<int64_t>(row) * I2 + col)
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    if (nct > 0) load_tile(0, 0, gcur);
     for (int r0 = 0; r0 < I1; r0 += 32) {
+      const int rn = r0 + 32;
       float b1v[16];
       if constexpr (DOQ) {
 #pragma unroll
@@ -123,64 +133,51 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
         }
       }
       v16f accp = v16f{};
-      // P layout: lane (m, h) reads M[r0 + m][c0 + 16h + 4u .. +3] (float4).
-      const bool prow_ok = live && (r0 + m) < I1;
-      const float* prow_ptr = p.Y + (live ? a : 0) * slab +
-                              static_cast<int64_t>(prow_ok ? r0 + m : 0) * I2;
-      // Q layout: lane (m, h) reads M[r0 + 2t + h][c0 + m]; the 2t part is a
-      // wave-uniform scalar offset.
-      const uint32_t qrow_off = static_cast<uint32_t>((r0 + h) * I2) * 4u;
-      float4 pv[2][4];
-      float qv[16];
-      auto load_p = [&](int ct, int buf) {
-        const int c0 = colbase + 32 * ct;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int col = c0 + 16 * h + 4 * u;
-          pv[buf][u] = (prow_ok && col < I2) ? ld4(prow_ptr + col)
-                                             : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-      };
-      if (nct > 0) load_p(0, 0);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         if (ct < nct) {
-          const int buf = ct & 1;
           const int c0 = colbase + 32 * ct;
-          if (ct + 1 < nct) load_p(ct + 1, buf ^ 1);
-          if constexpr (DOQ) {
-            const int col = c0 + m;
-            const uint32_t off = col < I2 ? qrow_off + 4u * col : kOob;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-              qv[t] = __builtin_bit_cast(
-                  float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 8 * t * I2, 0));
-          }
+          if (ct + 1 < nct) load_tile(r0, ct + 1, gnext);
+          else if (rn < I1) load_tile(rn, 0, gnext);
+          // stage the tile (wave-private; LDS accesses of a wave are ordered)
           float ss = 0.f;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const float e4[4] = {pv[buf][u].x, pv[buf][u].y, pv[buf][u].z, pv[buf][u].w};
+            *reinterpret_cast<float4*>(tile + swz(8 * u + lrow, lchunk)) = gcur[u];
+            ss += gcur[u].x * gcur[u].x + gcur[u].y * gcur[u].y +
+                  gcur[u].z * gcur[u].z + gcur[u].w * gcur[u].w;
+          }
+          nacc += static_cast<double>(ss);
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 v = *reinterpret_cast<const float4*>(tile + swz(m, 4 * h + u));
+            const float e4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               float bv;
               if constexpr (DOQ) {
                 int c = c0 + 16 * h + 4 * u + e;
-                c = c < I2 ? c : I2 - 1;  // the matching Y value reads as 0
+                c = c < I2 ? c : I2 - 1;  // the matching Y value is 0
                 bv = b2s[c * K2 + mB];
               } else {
                 bv = b2f[ct][4 * u + e];
               }
               accp = __builtin_amdgcn_mfma_f32_32x32x2f32(e4[e], bv, accp, 0, 0, 0);
-              ss += e4[e] * e4[e];
             }
           }
           if constexpr (DOQ) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t)
-              accq[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(b1v[t], qv[t],
-                                                              accq[ct], 0, 0, 0);
+            for (int t = 0; t < 16; ++t) {
+              const int row = 2 * t + h;
+              const float qv = tile[swz(row, m >> 2) + (m & 3)];
+              accq[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(b1v[t], qv, accq[ct],
+                                                              0, 0, 0);
+            }
           }
-          nacc += static_cast<double>(ss);
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int u = 0; u < 4; ++u) gcur[u] = gnext[u];
         }
       }
       // P: lane holds P[8(v/4) + 4h + v%4][m]
@@ -189,21 +186,21 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
-            if (row < I1 && m < K2)
-              p.TA[(a * I1 + row) * K2 + m] = accp[v];
+            if (row < I1 && m < K2) p.TA[(a * I1 + row) * K2 + m] = accp[v];
           }
         }
       } else {
-        float* mine = red + wave * 1024;
+        // the staged tiles are consumed: reuse them for the reduction
+        __syncthreads();
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-          mine[(8 * (v >> 2) + 4 * h + (v & 3)) * 32 + m] = accp[v];
+          tile[(8 * (v >> 2) + 4 * h + (v & 3)) * 32 + m] = accp[v];
         __syncthreads();
         const int rows_per = 32 / wps;
         for (int idx = lane; idx < rows_per * 32; idx += 64) {
           const int rl = sub * rows_per + idx / 32, n = idx % 32;
           float s = 0.f;
-          for (int w = 0; w < wps; ++w) s += red[(g * wps + w) * 1024 + rl * 32 + n];
+          for (int w = 0; w < wps; ++w) s += stage[(g * wps + w) * kTile + rl * 32 + n];
           const int row = r0 + rl;
           if (live && row < I1 && n < K2) p.TA[(a * I1 + row) * K2 + n] = s;
         }
@@ -240,9 +237,12 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+size_t b2_floats(int I2, int K2, bool doQ) {
+  return doQ ? (static_cast<size_t>(I2) * K2 + 63) / 64 * 64 : 0;
+}
+
 size_t dual_lds_bytes(int I2, int K2, bool doQ) {
-  const size_t b2 = doQ ? (static_cast<size_t>(I2) * K2 + 63) / 64 * 64 : 0;
-  return (b2 + kWaves * 1024) * sizeof(float);
+  return (b2_floats(I2, K2, doQ) + kWaves * kTile) * sizeof(float);
 }
 
 template <int CT, bool DOQ>
@@ -272,9 +272,9 @@ int launch_dual_ct(int ct, const DualArgs& a, int grid, size_t lds, hipStream_t 
 
 // Choose (waves per slab, tiles per wave) for a slab width; false if the
 // MFMA kernel does not apply.
-bool plan_dual(int I2, int K1, int K2, int* wps, int* ct) {
+bool plan_dual(int I2, int K1, int K2, bool doQ, int* wps, int* ct) {
   if (K1 > 32 || K2 > 32 || K2 < 1 || (I2 & 3) != 0) return false;
-  if (dual_lds_bytes(I2, K2, true) + 1024 > kLdsLimit) return false;
+  if (dual_lds_bytes(I2, K2, doQ) + 1024 > kLdsLimit) return false;
   const int tiles = (I2 + 31) / 32;
   for (int w = 1; w <= kWaves; w *= 2) {
     const int c = (tiles + w - 1) / w;
@@ -298,8 +298,8 @@ int run_dual_f32(const StreamCtx& c, const float* Y, const float* B2, int K2,
                  bool doNorm, hipStream_t s, bool* used) {
   int wps = 0, ct = 0;
   *used = false;
-  if (!plan_dual(static_cast<int>(c.I2), K1, K2, &wps, &ct) || c.I1 > (1 << 30) ||
-      c.I2 > (1 << 30))
+  if (!plan_dual(static_cast<int>(c.I2), doQ ? K1 : 0, K2, doQ, &wps, &ct) ||
+      c.I1 > (1 << 30) || c.I2 > (1 << 30))
     return kOk;
   DualArgs a{};
   a.Y = Y;
@@ -315,8 +315,8 @@ int run_dual_f32(const StreamCtx& c, const float* Y, const float* B2, int K2,
   a.wps = wps;
   const int grid = grid_for(c.A, wps);
   a.norm_partial = doNorm ? c.norm_partial : nullptr;
+  a.stage_offset = static_cast<int>(b2_floats(a.I2, K2, doQ));
   const size_t lds = dual_lds_bytes(a.I2, K2, doQ);
-  a.red_offset = doQ ? static_cast<int>((static_cast<size_t>(a.I2) * K2 + 63) / 64 * 64) : 0;
   const int rc0 = doQ ? launch_dual_ct<true>(ct, a, grid, lds, s)
                       : launch_dual_ct<false>(ct, a, grid, lds, s);
   if (rc0 != kOk) return rc0;
@@ -383,18 +383,24 @@ int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1,
 }
 
 template <typename T>
-int stream_single(const StreamCtx& c, int, const T* B2, int K2, T* TA,
+int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
                   hipStream_t s) {
   if (c.precision == RT_BF16_MIXED) {
     set_error("BF16 mixed precision is not available in this build");
     return kErrUnsupported;
   }
   const T* Y = static_cast<const T*>(c.y);
+  const bool doNorm = sweep == 0;
   if constexpr (sizeof(T) == sizeof(float)) {
     bool used = false;
-    int rc = run_dual_f32(c, Y, B2, K2, nullptr, 0, TA, nullptr, false, false, s,
+    int rc = run_dual_f32(c, Y, B2, K2, nullptr, 0, TA, nullptr, false, doNorm, s,
                           &used);
     if (rc != kOk || used) return rc;
+  }
+  if (doNorm) {
+    int rc = launch_norm2<T>(Y, c.A * c.I1 * c.I2, c.norm_partial, norm2_blocks(),
+                             c.norm_out, c.nonfinite, s);
+    if (rc != kOk) return rc;
   }
   return launch_ttm<T>(Y, B2, TA, c.A * c.I1, c.I2, 1, K2, s);
 }

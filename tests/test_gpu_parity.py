@@ -148,6 +148,27 @@ def test_tucker_no_truncate(P):
                               ref["G"], ref["U"]) <= 1e-4
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_tucker_rank_deficient_sketch(P, precision):
+    """Noise-free Tucker tensor of multilinear rank 3 sketched with 8 columns:
+    the sketch Gram matrices are singular, CholeskyQR2 rejects them and the
+    Householder fallback forms the bases.  The signal subspace, the truncated
+    factors and the core still match the oracle; every basis is orthonormal."""
+    d = synth.case_tucker(306, (40, 44, 48), (3, 3, 3), None, (8, 8, 8))
+    out, ref, Y = run_tucker(P, d, (3, 3, 3), 1, precision)
+    tol = 1e-4 if precision == "f32" else 1e-10
+    for n in range(3):
+        q = host(out["trace"]["Q"][n])
+        assert np.linalg.norm(q.T @ q - np.eye(8)) <= 10 * tol
+        # the signal part of range(Q) is the oracle's
+        us = T.unfold(d["Y"], n)
+        u_sig = np.linalg.svd(us, full_matrices=False)[0][:, :3]
+        assert np.linalg.norm(u_sig - q @ (q.T @ u_sig)) <= tol
+        assert projector_distance(host(out["U"][n]), ref["U"][n]) <= tol
+    assert aligned_core_error(host(out["G"]), [host(u) for u in out["U"]],
+                              ref["G"], ref["U"]) <= tol
+
+
 def test_tucker_nonfinite_flag(P):
     d = synth.case_tucker(304, (20, 21, 22), (3, 3, 3), 30.0, (5, 5, 5))
     Y = synth.f32(d["Y"]).copy()
