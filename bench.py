@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the randomized Tucker compression + FFCP hot path on one GPU.
+
+One step is one pass of the whole path over a resident synthetic tensor:
+rt_tucker_rand (mode-n sketches, FP64 sketch QR, core projection, truncation
+to the Tucker ranks) followed by rt_ffcp (CP-ALS through the compressed core,
+HOSVD initialization, run to the stated fit-change tolerance).
+
+Workload (synthetic, seeded): 1000 x 1000 x 1000 FP32 CP tensor of rank 20
+with per-mode column congruence drawn from U[0.5, 0.95], Gaussian noise at
+SNR 30 dB; Omega_n 1000 x 30, Omega~_n 900 x 30; Tucker ranks (20, 20, 20);
+FFCP with R = 20, ALS, stop when the fit changes by less than 1e-7.
+
+Printed: one JSON line.  ``value`` is the algorithmic HBM rate of the Tucker
+stage (bytes of Y the method must stream per call / its time); ``roofline``
+prices the dominant kernel against the chip's peak from HIP events recorded
+live on the library's stream; ``cpu_baseline`` is the FP64 NumPy oracle on
+the same tensor (same unit; --cpu-slab bounds it to a mode-3 slab).
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("Tucker sketch+project HBM GB/s (% peak); FFCP time-to-fit, "
+          "mixed vs plain FP32")
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=1000,
+                    help="I for the I x I x I tensor")
+    ap.add_argument("--precision", choices=("f32",), default="f32")
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--max-it", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--cpu-slab", type=int, default=1000,
+                    help="mode-3 slab of the tensor the oracle runs on")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
+                    help="also run K plain device copies of Y (HBM counter "
+                         "calibration under a profiler)")
+    return ap.parse_args()
+
+
+def stream_source_digest():
+    """Digest of the streaming-kernel source; stored traffic counters are
+    only valid for the kernel they were taken on."""
+    p = os.path.join(ROOT, "paper_1412_1885_amd", "csrc", "stream.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload):
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        tab = json.load(f)
+    e = tab.get(kernel, {}).get(workload)
+    if not e or e.get("source_digest") != stream_source_digest():
+        return None
+    return float(e["bytes_per_launch"])
+
+
+def cpu_baseline(Y, omegas, omega_tildes, ranks, slab):
+    """The FP64 oracle (untuned) on Y[:, :, :slab] with Omega_3 rows
+    0..slab-1; rate in the metric's unit (algorithmic FP32 bytes of the two
+    passes over the slab / wall time)."""
+    from oracle import randtucker as RT
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing: report the affinity set
+        threads = len(os.sched_getaffinity(0))
+    Ys = Y[:, :, :slab].cpu().numpy().astype(np.float64)
+    om = [o.astype(np.float64) for o in omegas]
+    om[2] = om[2][:slab]
+    omt = [[o.astype(np.float64) for o in omega_tildes[0]]]
+    t0 = time.perf_counter()
+    RT.rand_tucker(Ys, om, omt, sweeps=1, ranks=ranks)
+    dt = time.perf_counter() - t0
+    nbytes = 2 * Ys.size * 4
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"RandTucker2i S=1 (sketches, QR, core, truncation) in "
+                       f"FP64 NumPy on the {Ys.shape[0]}x{Ys.shape[1]}x{slab} "
+                       f"mode-3 slab of the same tensor, {dt:.2f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the sharded path is described, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1412_1885_amd as P
+    import synth
+
+    P.lib()  # raises if the HIP library is missing: no fallback
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    I, R, rt = args.size, 20, 30
+    dims = (I, I, I)
+    ranks = (R, R, R)
+    d = synth.cp_congruent_device(1885, dims, R, 0.5, 0.95, 30.0, (rt,) * 3,
+                                  sweeps=1, device=dev)
+    Y = d["Y"]
+    om32 = synth.f32(d["omegas"])
+    omt32 = [synth.f32(d["omega_tildes"][0])]
+    om_d = [torch.from_numpy(o).to(dev) for o in om32]
+    omt_d = [[torch.from_numpy(o).to(dev) for o in omt32[0]]]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step(tws, fws, ev):
+        ev[0].record(stream)
+        out = P.tucker_rand(Y, om_d, omt_d, ranks=ranks, sweeps=1,
+                            precision=args.precision, workspace=tws, sync=False)
+        ev[1].record(stream)
+        f = P.ffcp(out["U"], out["G"], R, update="als", init="hosvd",
+                   max_it=args.max_it, tol=args.tol, workspace=fws, sync=False)
+        ev[2].record(stream)
+        return out, f
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    # warmup (first call allocates the workspaces)
+    tws = fws = None
+    for _ in range(max(args.warmup, 1)):
+        out, f = step(tws, fws, mk())
+        tws = out["workspace"]
+        fws = f.get("workspace")
+    torch.cuda.synchronize()
+
+    P.profile_enable(True)
+    evs = [mk() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out, f = step(tws, fws, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = P.profile_read()
+    P.profile_enable(False)
+
+    tucker_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    ffcp_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    finfo = np.frombuffer(f["info_dev"].cpu().numpy().tobytes(), P.FFCP_INFO_DTYPE)[0]
+    tinfo = np.frombuffer(out["info_dev"].cpu().numpy().tobytes(),
+                          P.TUCKER_INFO_DTYPE)[0]
+
+    # algorithmic HBM bytes of the Tucker stage: each pass over Y reads it
+    # once (sweep pass + core pass for S = 1)
+    ybytes = Y.numel() * Y.element_size()
+    passes = 2
+    t_tucker = float(np.mean(tucker_ms)) * 1e-3
+    value = passes * ybytes / t_tucker / 1e9
+
+    # dominant kernel: the dual-contraction sweep pass (first_pass stage)
+    ms_dual, n_dual = prof["first_pass"]
+    t_dual = ms_dual / max(n_dual, 1) * 1e-3
+    flops_dual = 2.0 * Y.numel() * (rt + rt)   # Y x_3 Omega_3^T and Y x_2 Omega_2^T
+    achieved = flops_dual / t_dual / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    workload = f"cp{R}_congruent_{I}x{I}x{I}_f32"
+    traffic = stored_traffic("dual_f32_kernel", workload)
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": traffic,
+            "kernel": "dual_f32_kernel (sweep pass: Y x_3 Omega_3^T and "
+                      "Y x_2 Omega_2^T in one read of Y)",
+            "avg_ms": round(t_dual * 1e3, 4),
+            "hbm_gbs": round(ybytes / t_dual / 1e9, 1)}
+
+    if args.copy_calibration:
+        # plain elementwise copy kernel of known traffic (reads 4 B, writes
+        # 8 B per element): the scale for the HBM byte counters
+        dst = torch.empty(Y.shape, dtype=torch.float64, device=dev)
+        for _ in range(args.copy_calibration):
+            dst.copy_(Y)
+        torch.cuda.synchronize()
+        del dst
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "description": (f"{I}^3 FP32 CP rank {R}, column congruence "
+                            "U[0.5,0.95], SNR 30 dB; Omega_n "
+                            f"{I}x{rt}, Omega~_n {rt * rt}x{rt}; Tucker ranks "
+                            f"{ranks}, one sketch sweep; FFCP ALS R={R}, HOSVD "
+                            f"init, tol {args.tol}"),
+            "dims": list(dims), "ranks": list(ranks), "ranks_tilde": [rt] * 3,
+            "sweeps": 1, "R": R, "update": "als", "precision": args.precision,
+        },
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "tucker_ms": round(float(np.mean(tucker_ms)), 4),
+        "ffcp_ms": round(float(np.mean(ffcp_ms)), 4),
+        "ffcp_iterations": int(finfo["iterations"]),
+        "ffcp_converged": int(finfo["converged"]),
+        "fit_core": float(finfo["fit"]),
+        "normY2": float(tinfo["normY2"]),
+        "stages_ms": {k: round(v[0] / max(v[1], 1), 4)
+                      for k, v in prof.items() if v[1] > 0},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

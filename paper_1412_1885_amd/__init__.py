@@ -12,5 +12,5 @@ from ._binding import (  # noqa: F401
     ffcp_desc, ffcp_workspace, ffcp, ttm, cp_fit_dense,
     rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense, rt_stream_pass,
     stream_pass, profile_enable, profile_read,
-    LIB_PATH,
+    LIB_PATH, TUCKER_INFO_DTYPE, FFCP_INFO_DTYPE,
 )

@@ -291,7 +291,7 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
     _check(lib().rt_ffcp(ctypes.byref(desc), _ptr_array(U), _ptr(G), ainit, padp,
                          _ptr(ws), ws.numel(), _ptr_array(A), _ptr(lam), _ptr(ft),
                          _ptr(info), _stream_handle(stream)))
-    out = {"A": A, "lam": lam, "info_dev": info, "fit_trace_dev": ft}
+    out = {"A": A, "lam": lam, "info_dev": info, "fit_trace_dev": ft, "workspace": ws}
     if sync:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]

@@ -186,3 +186,44 @@ def init_factors(rng, dims, R, nonneg=False):
     if nonneg:
         return [rng.uniform(0.0, 1.0, size=(I, R)) for I in dims]
     return [rng.standard_normal((I, R)) for I in dims]
+
+
+# ------------------------------------------------ device-resident workloads
+
+def cp_congruent_device(case, dims, R, c_lo, c_hi, snr_db, ranks_tilde,
+                        sweeps=1, device="cuda"):
+    """Large CP workload built directly in device memory.
+
+    Factors, Omega_n and Omega~_n come from the same seeded numpy streams as
+    ``case_cp_congruent``; Y* = [[A_1, ..., A_N]] is formed in FP64 by torch
+    (mode-1 unfolding times the transposed Khatri-Rao product of the other
+    factors), Gaussian noise from torch's generator seeded with the case's
+    noise stream is scaled to the exact SNR, and the sum is rounded once to
+    FP32.  Returns Y (device float32), the factors and the method's randoms
+    (host FP64)."""
+    import torch
+    g = rngs(case)
+    A = congruent_factors(g["factors"], dims, R, c_lo, c_hi)
+    om = omegas(g["omega"], dims, ranks_tilde)
+    omt = [omega_tildes(g["omega_t1"], ranks_tilde)]
+    if sweeps >= 2:
+        omt.append(omega_tildes(g["omega_t2"], ranks_tilde))
+    noise_seed = int(g["noise"].integers(0, 2**62))
+    At = [torch.from_numpy(a).to(device) for a in A]
+    kr = At[-1]
+    for a in reversed(At[1:-1]):   # rows: (i_2, ..., i_N) row-major
+        kr = (a[:, None, :] * kr[None, :, :]).reshape(-1, R)
+    Ystar = At[0] @ kr.T           # I_1 x prod_{n>1} I_n, FP64
+    del kr
+    gen = torch.Generator(device=device)
+    gen.manual_seed(noise_seed)
+    E = torch.randn(Ystar.shape, dtype=torch.float64, device=device,
+                    generator=gen)
+    s = torch.sqrt(torch.sum(Ystar * Ystar) /
+                   (torch.sum(E * E) * 10.0 ** (snr_db / 10.0)))
+    E.mul_(s).add_(Ystar)
+    del Ystar
+    Y = E.to(torch.float32).reshape(tuple(dims))
+    del E
+    return {"Y": Y, "A_true": A, "omegas": om, "omega_tildes": omt,
+            "init_rng": g["init"]}
