@@ -513,7 +513,9 @@ struct FfcpPlan {
       Rmin = d->ranks[n] < Rmin ? d->ranks[n] : Rmin;
       Rmax = d->ranks[n] > Rmax ? d->ranks[n] : Rmax;
     }
-    int64_t wsize = core / Rmin * R;
+    // MTTKRP intermediates (rows padded to a multiple of 4 columns) and the
+    // core-sized chain of the ||Yt||^2 computation
+    int64_t wsize = core / Rmin * ((R + 3) / 4 * 4);
     if (wsize < core) wsize = core;
     for (int n = 0; n < N; ++n) {
       A[n] = ar.take<double>(d->dims[n] * R);
@@ -526,7 +528,8 @@ struct FfcpPlan {
     G64 = ar.take<double>(core);
     int64_t hs = static_cast<int64_t>(Rmax) * (R > Rmax ? R : Rmax);
     H = ar.take<double>(hs);
-    Qm = ar.take<double>(Imax * R);
+    // I_n x R lift (generic kernel) or the first MTTKRP step (compressed ALS)
+    Qm = ar.take<double>(Imax * R > wsize ? Imax * R : wsize);
     T = ar.take<double>(R * R);
     W1 = ar.take<double>(wsize);
     W2 = ar.take<double>(wsize);
@@ -729,6 +732,10 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
                          k, R);
       RT_LAUNCH_CHECK("hosvd pad");
     }
+  }
+  if (ffcp_als_core_applicable(a)) {
+    const int rc = launch_ffcp_als_core(a, s);
+    if (rc != kErrUnsupported) return rc;
   }
   return launch_ffcp(a, s);
 }

@@ -1,0 +1,660 @@
+// FFCP with the ALS update (Algorithm 1 with eq. (14), Section III-B) run
+// entirely in the compressed space.
+//
+// For the unconstrained update every factor stays in the range of its Tucker
+// basis: A_n = U_n H T^{-1} = U_n Vh_n with Vh_n = H T^{-1} (R_n x R).  With
+// M_n = U_n^T U_n (computed once; the identity up to the rounding of U_n), all
+// the quantities Algorithm 1 forms in the I_n-dimensional space have exact
+// compressed-space counterparts:
+//   V_n    = U_n^T A_n         = M_n Vh_n
+//   Gram_n = A_n^T A_n         = Vh_n^T M_n Vh_n = Vh_n^T V_n
+//   ||a_r||^2 (column norms)   = (Vh_n^T M_n Vh_n)_rr
+// so one iteration costs O(N (R prod_p R_p + R^3)) independently of I_n
+// (eq. (10): CP of the Tucker core), and A_n = U_n Vh_n is formed once at the
+// end.  Results equal the I_n-space recursion up to FP64 rounding order.
+//
+// One workgroup runs the whole loop (the work per step is tiny and serial in
+// the modes); the core (FP32, promoted on read), the MTTKRP intermediates and
+// all R x R / R_n x R matrices live in LDS when they fit.  Wave 0 inverts T
+// by Gauss-Jordan with the working columns in registers (one per lane) and
+// the pivot column broadcast through scalar registers: a Cholesky or a
+// triangular solve in LDS serializes on LDS round trips, one per entry.
+// Vh = H T^{-1} is then a small product over all threads.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kLdsMax = 160 * 1024;
+
+struct InfoDev {
+  int32_t iterations, converged, ridged, reserved;
+  double fit, fit_prev;
+};
+
+struct CoreAlsArgs {
+  FfcpArgs a;
+  int RP;             // R rounded up to a multiple of 4: row stride of R-wide rows
+  int64_t core;       // prod R_n
+  int64_t x1_doubles; // first MTTKRP step (shared by modes 0..N-2)
+  // LDS byte offsets
+  int oV[8], oVh[8], oM[8], oGram[8];
+  int oT, oL, oH, oP, oNrm, oG0, oRed, oG, oX1, oW1, oW2, oStage;
+  // MTTKRP schedule: step st of mode n contracts mode sm with V_sm; the
+  // operand is [sApre, R_sm, sCpost] (times RP after the first step)
+  int sm[8][8], sApre[8][8], sCpost[8][8];
+};
+
+// 1/p from the hardware estimate refined by two Newton steps (within an ulp
+// or two of the correctly rounded quotient; the IEEE division sequence is
+// several times longer and sits on the pivot chain)
+__device__ __forceinline__ double recip(double p) {
+  double x = __builtin_amdgcn_rcp(p);
+  double e = fma(-p, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-p, x, 1.0);
+  return fma(x, e, x);
+}
+
+// value of v held by lane `lane` (uniform), through the scalar unit
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave-level in-place Gauss-Jordan inversion of the symmetric positive
+// definite R x R matrix T + delta I (row stride RP) into Tinv.  Lane j holds
+// column j in registers; step k broadcasts the pivot column from lane k
+// through scalar registers, so no step waits on LDS.  Without pivoting the
+// pivots are the Schur-complement diagonals, i.e. the squared diagonal of
+// the Cholesky factor: a pivot <= 0 means T is not numerically positive
+// definite (returns false).
+template <int RMAX>
+__device__ __forceinline__ bool gj_inverse_wave(const double* T, int RP, int R,
+                                                double delta, double* Tinv) {
+  const int j = threadIdx.x & 63;
+  const int jc = j < R ? j : R - 1;   // clamped: every load is in bounds
+  double col[RMAX];
+#pragma unroll
+  for (int i = 0; i < RMAX; ++i) {
+    const int ic = i < R ? i : R - 1;
+    const double v = T[ic * RP + jc] + (i == j ? delta : 0.0);
+    col[i] = (i < R && j < R) ? v : 0.0;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k < R) {
+      double p = lane_bcast(col[k], k);
+      if (!(p > 0.0)) {
+        ok = false;
+        p = 1.0;
+      }
+      const double rip = ((j == k) ? 1.0 : col[k]) * recip(p);
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) {
+        if (i != k) {
+          const double f = lane_bcast(col[i], k);   // zero for i >= R
+          col[i] = ((j == k) ? 0.0 : col[i]) - f * rip;
+        }
+      }
+      col[k] = rip;
+    }
+  }
+  if (j < R) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) Tinv[i * RP + j] = col[i];
+  }
+  return ok;
+}
+
+// out (p x q, row stride ldo) = X^T Y over `rows` rows of the row-major
+// float matrices X (rows x p) and Y (rows x q); 64-row blocks staged in LDS
+// (st: 64 (p + q) doubles).  p, q <= 64.
+template <int NT>
+__device__ void cross_rows(const float* X, int p, const float* Y, int q,
+                           int64_t rows, double* out, int ldo, double* st) {
+  constexpr int kG = NT / 64;
+  constexpr int kAcc = 64 / kG;
+  const int t = threadIdx.x;
+  const int v = t & 63, g = t >> 6;
+  double acc[kAcc];
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) acc[k] = 0.0;
+  double* xs = st;
+  double* ys = st + 64 * p;
+  for (int64_t i0 = 0; i0 < rows; i0 += 64) {
+    const int nr = static_cast<int>((rows - i0) < 64 ? (rows - i0) : 64);
+    __syncthreads();
+    for (int l = t; l < nr * p; l += NT) xs[l] = X[i0 * p + l];
+    for (int l = t; l < nr * q; l += NT) ys[l] = Y[i0 * q + l];
+    __syncthreads();
+    if (v < q) {
+      for (int ii = 0; ii < nr; ++ii) {
+        const double yv = ys[ii * q + v];
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) {
+          const int u = g + kG * k;
+          if (u < p) acc[k] += xs[ii * p + u] * yv;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) {
+    const int u = g + kG * k;
+    if (u < p && v < q) out[u * ldo + v] = acc[k];
+  }
+  __syncthreads();
+}
+
+// C (m x n, ldc) = op(A) B with op(A) = A (m x k, lda) or A^T (A: k x m).
+template <int NT>
+__device__ void small_mm(const double* A, int lda, bool transA, const double* B,
+                         int ldb, double* C, int ldc, int m, int k, int n) {
+  for (int l = threadIdx.x; l < m * n; l += NT) {
+    const int i = l / n, j = l % n;
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q)
+      acc += (transA ? A[q * lda + i] : A[i * lda + q]) * B[q * ldb + j];
+    C[i * ldc + j] = acc;
+  }
+}
+
+template <int RMAX, int NT, bool GLDS>
+__global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
+  extern __shared__ __align__(16) char smem[];
+  const FfcpArgs& a = c.a;
+  const int t = threadIdx.x;
+  const int N = a.N, R = a.R, RP = c.RP, R4 = RP / 4;
+  const int64_t core = c.core;
+  auto D = [&](int off) { return reinterpret_cast<double*>(smem + off); };
+  InfoDev* info = static_cast<InfoDev*>(a.info);
+
+  // ---- setup -------------------------------------------------------------
+  const float* G;
+  double* X1;
+  double* W1;
+  double* W2;
+  if constexpr (GLDS) {
+    float* gs = reinterpret_cast<float*>(smem + c.oG);
+    for (int64_t l = t; l < core; l += NT) gs[l] = a.G[l];
+    G = gs;
+    X1 = D(c.oX1);
+    W1 = D(c.oW1);
+    W2 = D(c.oW2);
+  } else {
+    G = a.G;
+    X1 = a.Qm;   // global scratch (sized for the first contraction)
+    W1 = a.W1;
+    W2 = a.W2;
+  }
+  // zero every R-wide row region (padding columns must stay zero)
+  for (int n = 0; n < N; ++n) {
+    for (int l = t; l < a.Rn[n] * RP; l += NT) {
+      D(c.oV[n])[l] = 0.0;
+      D(c.oVh[n])[l] = 0.0;
+    }
+    for (int l = t; l < R * RP; l += NT) D(c.oGram[n])[l] = 0.0;
+  }
+  __syncthreads();
+  double* stage = D(c.oStage);
+  for (int n = 0; n < N; ++n) {
+    const int Rn = a.Rn[n];
+    cross_rows<NT>(a.U[n], Rn, a.U[n], Rn, a.I[n], D(c.oM[n]), Rn, stage);
+    if (a.A_init[n]) {
+      cross_rows<NT>(a.U[n], Rn, a.A_init[n], R, a.I[n], D(c.oV[n]), RP, stage);
+      cross_rows<NT>(a.A_init[n], R, a.A_init[n], R, a.I[n], D(c.oGram[n]), RP,
+                     stage);
+    } else {
+      // HOSVD (or caller) coefficients: A_n = U_n V_init
+      double* Vh = D(c.oVh[n]);
+      for (int l = t; l < Rn * R; l += NT) Vh[(l / R) * RP + l % R] = a.V_init[n][l];
+      __syncthreads();
+      small_mm<NT>(D(c.oM[n]), Rn, false, Vh, RP, D(c.oV[n]), RP, Rn, Rn, R);
+      __syncthreads();
+      small_mm<NT>(Vh, RP, true, D(c.oV[n]), RP, D(c.oGram[n]), RP, R, Rn, R);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+
+  // ||Yt||^2 = <G, G x_1 M_1 ... x_N M_N> unless given (global scratch)
+  double nrm2 = a.normY2;
+  double* red = D(c.oRed);
+  if (!(nrm2 >= 0.0)) {
+    const double* src = nullptr;
+    double* bufs[2] = {a.W1, a.W2};  // core-sized, global
+    int cur = 0;
+    int64_t Apre = 1;
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
+      const int64_t Cpost = core / (Apre * Rn);
+      const double* M = D(c.oM[n]);
+      double* dst = bufs[cur];
+      for (int64_t l = t; l < core; l += NT) {
+        const int64_t cc = l % Cpost;
+        const int64_t rest = l / Cpost;
+        const int i = static_cast<int>(rest % Rn);
+        const int64_t aa = rest / Rn;
+        double acc = 0.0;
+        for (int j = 0; j < Rn; ++j) {
+          const int64_t idx = (aa * Rn + j) * Cpost + cc;
+          const double x = src ? src[idx] : static_cast<double>(G[idx]);
+          acc += x * M[j * Rn + i];
+        }
+        dst[l] = acc;
+      }
+      __syncthreads();
+      src = dst;
+      cur ^= 1;
+      Apre *= Rn;
+    }
+    double p = 0.0;
+    for (int64_t l = t; l < core; l += NT) p += static_cast<double>(G[l]) * src[l];
+    nrm2 = block_sum(p, red);
+    __syncthreads();
+  }
+
+  // ---- iterations ----------------------------------------------------------
+  double* T = D(c.oT);
+  double* L = D(c.oL);  // T^{-1}
+  double* Pm = D(c.oP);
+  double* G0 = D(c.oG0);
+  double* Hlast = D(c.oH);
+  double fit_prev = 0.0, fit = 0.0;
+  int it = 0, converged = 0, ridged = 0;
+  for (it = 1; it <= a.max_it; ++it) {
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
+      // H = G_(n) [KR_{p != n} V_p]: contract the last remaining mode != n
+      // (schedule precomputed on the host: mode, leading and trailing sizes).
+      // The first step of modes 0..N-2 contracts mode N-1 with V_{N-1},
+      // which only mode N-1 updates: it is computed once per iteration (X1).
+      const double* src = nullptr;
+      for (int st = 0; st < N - 1; ++st) {
+        const int m = c.sm[n][st];
+        const int Apre = c.sApre[n][st], Cpost = c.sCpost[n][st];
+        const bool last = st == N - 2;
+        const int Rm = a.Rn[m];
+        const double* Vm = D(c.oV[m]);
+        double* dst = last ? Hlast : (st == 0 ? X1 : (((st - 1) & 1) ? W2 : W1));
+        const bool reuse = st == 0 && !last && n > 0 && n < N - 1;
+        if (!reuse && src == nullptr) {
+          // first step from the FP32 core: 4 consecutive (a, c) x 4 r per item
+          const int nac = Apre * Cpost;
+          const int total = ((nac + 3) / 4) * R4;
+          for (int item = t; item < total; item += NT) {
+            const int rq = item % R4;
+            const int ab = item / R4;
+            int off[4];
+            bool val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int ac = 4 * ab + u;
+              val[u] = ac < nac;
+              const int acc_ = val[u] ? ac : nac - 1;   // clamped, in bounds
+              const int cc = acc_ % Cpost, aa = acc_ / Cpost;
+              off[u] = aa * Rm * Cpost + cc;
+            }
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            const double* vp = Vm + 4 * rq;
+            // operands of 4 consecutive j are loaded before any is used, so
+            // four LDS round trips overlap (tail j clamped, weight zero)
+            for (int j0 = 0; j0 < Rm; j0 += 4) {
+              double2 v01[4], v23[4];
+              float g[4][4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+                v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
+                v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) g[q][u] = G[off[u] + j * Cpost];
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const bool in = j0 + q < Rm;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const double gv = in ? static_cast<double>(g[q][u]) : 0.0;
+                  acc[u][0] += gv * v01[q].x;
+                  acc[u][1] += gv * v01[q].y;
+                  acc[u][2] += gv * v23[q].x;
+                  acc[u][3] += gv * v23[q].y;
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (val[u]) {
+                double* dp = dst + (4 * ab + u) * RP + 4 * rq;
+                *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
+                *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
+              }
+            }
+          }
+          __syncthreads();
+        } else if (!reuse) {
+          const int total = Apre * Cpost * R4;
+          for (int item = t; item < total; item += NT) {
+            const int rq = item % R4;
+            const int ac = item / R4;
+            const int cc = ac % Cpost, aa = ac / Cpost;
+            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+            const double* vp = Vm + 4 * rq;
+            const double* sp = src + (aa * Rm * Cpost + cc) * RP + 4 * rq;
+            const int sj = Cpost * RP;
+            for (int j0 = 0; j0 < Rm; j0 += 4) {
+              double2 s01[4], s23[4], v01[4], v23[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+                s01[q] = *reinterpret_cast<const double2*>(sp + j * sj);
+                s23[q] = *reinterpret_cast<const double2*>(sp + j * sj + 2);
+                v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
+                v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                if (j0 + q < Rm) {
+                  acc0 += s01[q].x * v01[q].x;
+                  acc1 += s01[q].y * v01[q].y;
+                  acc2 += s23[q].x * v23[q].x;
+                  acc3 += s23[q].y * v23[q].y;
+                }
+              }
+            }
+            double* dp = dst + ac * RP + 4 * rq;
+            *reinterpret_cast<double2*>(dp) = make_double2(acc0, acc1);
+            *reinterpret_cast<double2*>(dp + 2) = make_double2(acc2, acc3);
+          }
+          __syncthreads();
+        }
+        src = dst;
+      }
+      const double* H = src;  // Rn x RP (Hlast)
+
+      // T = hadamard of the other Grams
+      for (int l = t; l < R * R; l += NT) {
+        const int i = l / R, j = l % R;
+        double v = 1.0;
+        for (int p = 0; p < N; ++p)
+          if (p != n) v *= D(c.oGram[p])[i * RP + j];
+        T[i * RP + j] = v;
+      }
+      __syncthreads();
+
+      double* Vh = D(c.oVh[n]);
+      // L <- T^{-1} by wave 0 (ridge T + delta I when T is not numerically
+      // positive definite)
+      if (t < 64) {
+        if (!gj_inverse_wave<RMAX>(T, RP, R, 0.0, L)) {
+          double tr = 0.0;
+          for (int k = 0; k < R; ++k) tr += T[k * RP + k];
+          gj_inverse_wave<RMAX>(T, RP, R, 1e-12 * tr / R, L);
+          ridged = 1;
+        }
+      }
+      __syncthreads();
+      // Vh = H T^{-1}
+      for (int l = t; l < Rn * R4; l += NT) {
+        const int i = l / R4, rq = l % R4;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (int q = 0; q < R; ++q) {
+          const double hv = H[i * RP + q];
+          const double2 v01 = *reinterpret_cast<const double2*>(L + q * RP + 4 * rq);
+          const double2 v23 = *reinterpret_cast<const double2*>(L + q * RP + 4 * rq + 2);
+          acc0 += hv * v01.x;
+          acc1 += hv * v01.y;
+          acc2 += hv * v23.x;
+          acc3 += hv * v23.y;
+        }
+        double* vp = Vh + i * RP + 4 * rq;
+        *reinterpret_cast<double2*>(vp) = make_double2(acc0, acc1);
+        *reinterpret_cast<double2*>(vp + 2) = make_double2(acc2, acc3);
+      }
+      __syncthreads();
+
+      // P = M_n Vh;  G0 = Vh^T P (Gram of the unnormalized factor)
+      const double* M = D(c.oM[n]);
+      for (int l = t; l < Rn * R4; l += NT) {
+        const int j = l / R4, rq = l % R4;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (int q = 0; q < Rn; ++q) {
+          const double mv = M[j * Rn + q];
+          const double2 v01 = *reinterpret_cast<const double2*>(Vh + q * RP + 4 * rq);
+          const double2 v23 = *reinterpret_cast<const double2*>(Vh + q * RP + 4 * rq + 2);
+          acc0 += mv * v01.x;
+          acc1 += mv * v01.y;
+          acc2 += mv * v23.x;
+          acc3 += mv * v23.y;
+        }
+        double* pp = Pm + j * RP + 4 * rq;
+        *reinterpret_cast<double2*>(pp) = make_double2(acc0, acc1);
+        *reinterpret_cast<double2*>(pp + 2) = make_double2(acc2, acc3);
+      }
+      __syncthreads();
+      for (int l = t; l < R * R; l += NT) {
+        const int i = l / R, j = l % R;
+        double acc = 0.0;
+        for (int q = 0; q < Rn; ++q) acc += Vh[q * RP + i] * Pm[q * RP + j];
+        G0[i * RP + j] = acc;
+      }
+      __syncthreads();
+      // columns normalized for n < N-1 (zero columns stay zero):
+      // Vh /= nr, V_n = P / nr, Gram_n = G0 / (nr nr^T)
+      double* Vn = D(c.oV[n]);
+      double* Gn = D(c.oGram[n]);
+      const bool normalize = n < N - 1;
+      for (int l = t; l < Rn * R; l += NT) {
+        const int j = l / R, r = l % R;
+        const double nr = normalize ? sqrt(G0[r * RP + r]) : 0.0;
+        if (nr > 0.0) {
+          Vh[j * RP + r] /= nr;
+          Vn[j * RP + r] = Pm[j * RP + r] / nr;
+        } else {
+          Vn[j * RP + r] = Pm[j * RP + r];
+        }
+      }
+      for (int l = t; l < R * R; l += NT) {
+        const int i = l / R, j = l % R;
+        double v = G0[i * RP + j];
+        if (normalize) {
+          const double ni = sqrt(G0[i * RP + i]), nj = sqrt(G0[j * RP + j]);
+          if (ni > 0.0) v /= ni;
+          if (nj > 0.0) v /= nj;
+        }
+        Gn[i * RP + j] = v;
+      }
+      __syncthreads();
+    }
+    // ---- fit (the last mode's H is still in Hlast) -------------------------
+    {
+      const int Rl = a.Rn[N - 1];
+      const double* Vl = D(c.oV[N - 1]);
+      double p = 0.0;
+      for (int l = t; l < Rl * R; l += NT) {
+        const int j = l / R, r = l % R;
+        p += Hlast[j * RP + r] * Vl[j * RP + r];
+      }
+      const double inner = block_sum(p, red);
+      double q = 0.0;
+      for (int l = t; l < R * R; l += NT) {
+        const int i = l / R, j = l % R;
+        double v = 1.0;
+        for (int pp = 0; pp < N; ++pp) v *= D(c.oGram[pp])[i * RP + j];
+        q += v;
+      }
+      const double yh2 = block_sum(q, red);
+      double res2 = nrm2 - 2.0 * inner + yh2;
+      res2 = res2 > 0.0 ? res2 : 0.0;
+      fit = 1.0 - sqrt(res2) / sqrt(nrm2);
+    }
+    if (t == 0 && a.fit_trace) a.fit_trace[it - 1] = fit;
+    if (it >= 2 && fabs(fit - fit_prev) < a.tol) {
+      converged = 1;
+      break;
+    }
+    if (it < a.max_it) fit_prev = fit;
+    __syncthreads();
+  }
+  if (it > a.max_it) it = a.max_it;
+  // ridged is known to wave 0 only
+  __shared__ int ridged_any;
+  if (t == 0) ridged_any = ridged;
+  __syncthreads();
+
+  // ---- outputs: A_n = U_n Vh_n; the last factor normalized, lambda -----------
+  for (int n = 0; n < N; ++n) {
+    const int Rn = a.Rn[n];
+    const double* Vh = D(c.oVh[n]);
+    const float* Un = a.U[n];
+    const double* Gn = D(c.oGram[n]);
+    const int64_t cnt = a.I[n] * R;
+    for (int64_t l = t; l < cnt; l += NT) {
+      const int64_t i = l / R;
+      const int r = static_cast<int>(l % R);
+      double acc = 0.0;
+      for (int j = 0; j < Rn; ++j) acc += static_cast<double>(Un[i * Rn + j]) * Vh[j * RP + r];
+      if (n == N - 1) {
+        const double nr = sqrt(Gn[r * RP + r]);
+        if (nr > 0.0) acc /= nr;
+      }
+      a.A_out[n][l] = static_cast<float>(acc);
+    }
+  }
+  {
+    const double* Gl = D(c.oGram[N - 1]);
+    for (int r = t; r < R; r += NT) a.lambda[r] = static_cast<float>(sqrt(Gl[r * RP + r]));
+  }
+  if (t == 0 && info) {
+    info->iterations = it;
+    info->converged = converged;
+    info->ridged = ridged_any;
+    info->reserved = 0;
+    info->fit = fit;
+    info->fit_prev = fit_prev;
+  }
+}
+
+// LDS layout; returns the byte size or -1 when the small matrices alone do
+// not fit.  glds selects the core and MTTKRP buffers in LDS as well.
+int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
+  const FfcpArgs& a = c.a;
+  const int N = a.N, R = a.R;
+  c.RP = (R + 3) / 4 * 4;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off += (bytes + 15) / 16 * 16;
+    return static_cast<int>(o);
+  };
+  int Rmax = 0;
+  int64_t core = 1;
+  for (int n = 0; n < N; ++n) {
+    Rmax = a.Rn[n] > Rmax ? a.Rn[n] : Rmax;
+    core *= a.Rn[n];
+  }
+  c.core = core;
+  for (int n = 0; n < N; ++n) {
+    c.oV[n] = take(8LL * a.Rn[n] * c.RP);
+    c.oVh[n] = take(8LL * a.Rn[n] * c.RP);
+    c.oM[n] = take(8LL * a.Rn[n] * a.Rn[n]);
+    c.oGram[n] = take(8LL * R * c.RP);
+  }
+  c.oT = take(8LL * R * c.RP);
+  c.oL = take(8LL * R * c.RP);
+  c.oH = take(8LL * Rmax * c.RP);
+  c.oP = take(8LL * Rmax * c.RP);
+  c.oNrm = take(8LL * c.RP);
+  c.oG0 = take(8LL * R * c.RP);
+  c.oRed = take(8LL * 64);
+  // staging for the setup cross products: 64 rows of (p + q) <= 2 max(R, Rn)
+  const int wmax = R > Rmax ? R : Rmax;
+  c.oStage = take(8LL * 64 * 2 * wmax);
+  // MTTKRP intermediates: the first step (X1) and the alternating later
+  // steps (W1, W2); the final step writes H
+  int64_t x1 = 0, w[2] = {0, 0};
+  for (int n = 0; n < N; ++n) {
+    int rem[8], nrem = N;
+    for (int p = 0; p < N; ++p) rem[p] = p;
+    int step = 0;
+    while (nrem > 1) {
+      int pos = nrem - 1;
+      if (rem[pos] == n) pos = nrem - 2;
+      int Apre = 1, Cpost = 1;
+      for (int q = 0; q < pos; ++q) Apre *= a.Rn[rem[q]];
+      for (int q = pos + 1; q < nrem; ++q) Cpost *= a.Rn[rem[q]];
+      c.sm[n][step] = rem[pos];
+      c.sApre[n][step] = Apre;
+      c.sCpost[n][step] = Cpost;
+      if (nrem > 2) {  // the final step writes H
+        const int64_t out = static_cast<int64_t>(Apre) * Cpost * c.RP;
+        if (step == 0)
+          x1 = out > x1 ? out : x1;
+        else
+          w[(step - 1) & 1] = out > w[(step - 1) & 1] ? out : w[(step - 1) & 1];
+      }
+      for (int q = pos; q < nrem - 1; ++q) rem[q] = rem[q + 1];
+      --nrem;
+      ++step;
+    }
+  }
+  c.x1_doubles = x1;
+  if (!glds) {
+    c.oG = c.oX1 = c.oW1 = c.oW2 = 0;
+    return off;
+  }
+  c.oG = take(4LL * core);
+  c.oX1 = take(8LL * (x1 > 0 ? x1 : 1));
+  c.oW1 = take(8LL * (w[0] > 0 ? w[0] : 1));
+  c.oW2 = take(8LL * (w[1] > 0 ? w[1] : 1));
+  return off;
+}
+
+template <int RMAX, int NT, bool GLDS>
+int launch_one(const CoreAlsArgs& c, int64_t lds, hipStream_t s) {
+  auto k = ffcp_als_core_kernel<RMAX, NT, GLDS>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds));
+  if (e != hipSuccess) return hip_fail(e, "ffcp core LDS attribute");
+  hipLaunchKernelGGL(k, dim3(1), dim3(NT), static_cast<size_t>(lds), s, c);
+  RT_LAUNCH_CHECK("ffcp core ALS");
+  return kOk;
+}
+
+template <int RMAX, int NT>
+int launch_r(CoreAlsArgs& c, hipStream_t s) {
+  int64_t lds = layout(c, true, NT);
+  if (lds + 64 <= kLdsMax) return launch_one<RMAX, NT, true>(c, lds, s);
+  lds = layout(c, false, NT);
+  if (lds + 64 <= kLdsMax) return launch_one<RMAX, NT, false>(c, lds, s);
+  return kErrUnsupported;
+}
+
+}  // namespace
+
+bool ffcp_als_core_applicable(const FfcpArgs& a) {
+  return a.update == 0 && !(a.l1 > 0.0) && a.R <= 64;
+}
+
+int launch_ffcp_als_core(const FfcpArgs& a, hipStream_t s) {
+  CoreAlsArgs c{};
+  c.a = a;
+  if (a.R <= 16) return launch_r<16, 512>(c, s);
+  if (a.R <= 24) return launch_r<24, 512>(c, s);
+  if (a.R <= 32) return launch_r<32, 512>(c, s);
+  return launch_r<64, 512>(c, s);
+}
+
+}  // namespace rt

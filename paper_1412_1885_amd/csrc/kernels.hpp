@@ -139,5 +139,9 @@ struct FfcpArgs {
   double* scal;    // scalars
 };
 int launch_ffcp(const FfcpArgs& a, hipStream_t s);
+// ALS without the l1 term, run in the compressed space (one workgroup, LDS
+// resident); kErrUnsupported when the problem does not fit.
+bool ffcp_als_core_applicable(const FfcpArgs& a);
+int launch_ffcp_als_core(const FfcpArgs& a, hipStream_t s);
 
 }  // namespace rt
