@@ -578,9 +578,11 @@ int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
   c.oNrm = take(8LL * c.RP);
   c.oG0 = take(8LL * R * c.RP);
   c.oRed = take(8LL * 64);
-  // staging for the setup cross products: 64 rows of (p + q) <= 2 max(R, Rn)
+  // staging for the setup cross products: 64 rows of (p + q) <= 2 max(R, Rn);
+  // with the MTTKRP buffers in LDS it shares the first-step buffer (X1 is
+  // not in use before the iterations start)
   const int wmax = R > Rmax ? R : Rmax;
-  c.oStage = take(8LL * 64 * 2 * wmax);
+  const int64_t stage_bytes = 8LL * 64 * 2 * wmax;
   // MTTKRP intermediates: the first step (X1) and the alternating later
   // steps (W1, W2); the final step writes H
   int64_t x1 = 0, w[2] = {0, 0};
@@ -611,11 +613,13 @@ int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
   }
   c.x1_doubles = x1;
   if (!glds) {
+    c.oStage = take(stage_bytes);
     c.oG = c.oX1 = c.oW1 = c.oW2 = 0;
     return off;
   }
   c.oG = take(4LL * core);
-  c.oX1 = take(8LL * (x1 > 0 ? x1 : 1));
+  c.oX1 = take(8LL * x1 > stage_bytes ? 8LL * x1 : stage_bytes);
+  c.oStage = c.oX1;
   c.oW1 = take(8LL * (w[0] > 0 ? w[0] : 1));
   c.oW2 = take(8LL * (w[1] > 0 ? w[1] : 1));
   return off;
