@@ -98,8 +98,11 @@ def cpu_baseline(Y, omegas, omega_tildes, ranks, slab):
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(threads),
             "kind": "oracle",
             "sample": (f"RandTucker2i S=1 (sketches, QR, core, truncation) in "
-                       f"FP64 NumPy on the {Ys.shape[0]}x{Ys.shape[1]}x{slab} "
-                       f"mode-3 slab of the same tensor, {dt:.2f} s")}
+                       f"FP64 NumPy on "
+                       + ("the whole tensor" if slab >= Y.shape[2] else
+                          f"the {Ys.shape[0]}x{Ys.shape[1]}x{slab} mode-3 slab "
+                          "of the tensor")
+                       + f", {dt:.2f} s")}
 
 
 def main():
