@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Throughput of the randomized Tucker compression + FFCP hot path on one GPU.
 
-One step is one pass of the whole path over a resident synthetic tensor:
-rt_tucker_rand (mode-n sketches, FP64 sketch QR, core projection, truncation
-to the Tucker ranks) followed by rt_ffcp (CP-ALS through the compressed core,
-HOSVD initialization, run to the stated fit-change tolerance).
+One step is one pass of the whole path over a resident synthetic tensor, in
+the precision form: rt_tucker_rand with BF16 streaming passes (statistics,
+FP32 read + BF16 copy fused into the first sketch sweep, one power sweep,
+the core pass on the BF16 copy; FP64 sketch QR; truncation to the Tucker
+ranks) followed by rt_ffcp (CP-ALS through the compressed core, HOSVD
+initialization, run to the stated fit-change tolerance).  The plain FP32
+path (one sweep) is timed beside it on the same tensor.
 
 Workload (synthetic, seeded): 1000 x 1000 x 1000 FP32 CP tensor of rank 20
 with per-mode column congruence drawn from U[0.5, 0.95], Gaussian noise at
@@ -12,10 +15,11 @@ SNR 30 dB; Omega_n 1000 x 30, Omega~_n 900 x 30; Tucker ranks (20, 20, 20);
 FFCP with R = 20, ALS, stop when the fit changes by less than 1e-7.
 
 Printed: one JSON line.  ``value`` is the algorithmic HBM rate of the Tucker
-stage (bytes of Y the method must stream per call / its time); ``roofline``
-prices the dominant kernel against the chip's peak from HIP events recorded
-live on the library's stream; ``cpu_baseline`` is the FP64 NumPy oracle on
-the same tensor (same unit; --cpu-slab bounds it to a mode-3 slab).
+stage of the step (bytes of Y the method must stream per call / its time);
+``roofline`` prices the dominant kernel against the chip's peak from HIP
+events recorded live on the library's stream; ``cpu_baseline`` is the FP64
+NumPy oracle on the same tensor (same unit; --cpu-slab bounds it to a
+mode-3 slab).
 """
 
 import argparse
@@ -44,7 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=1000,
                     help="I for the I x I x I tensor")
-    ap.add_argument("--precision", choices=("f32",), default="f32")
+    ap.add_argument("--precision", choices=("bf16", "f32"), default="bf16",
+                    help="form timed as the step (bf16: precision form, two sweeps)")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -77,10 +82,10 @@ def stored_traffic(kernel, workload):
     return float(e["bytes_per_launch"])
 
 
-def cpu_baseline(Y, omegas, omega_tildes, ranks, slab):
+def cpu_baseline(Y, omegas, omega_tildes, ranks, slab, sweeps, bytes_per_elem):
     """The FP64 oracle (untuned) on Y[:, :, :slab] with Omega_3 rows
-    0..slab-1; rate in the metric's unit (algorithmic FP32 bytes of the two
-    passes over the slab / wall time)."""
+    0..slab-1, with the step's number of sweeps; rate in the metric's unit
+    (the step's algorithmic bytes per element x elements / wall time)."""
     from oracle import randtucker as RT
     try:
         from threadpoolctl import threadpool_info
@@ -90,19 +95,64 @@ def cpu_baseline(Y, omegas, omega_tildes, ranks, slab):
     Ys = Y[:, :, :slab].cpu().numpy().astype(np.float64)
     om = [o.astype(np.float64) for o in omegas]
     om[2] = om[2][:slab]
-    omt = [[o.astype(np.float64) for o in omega_tildes[0]]]
+    omt = [[o.astype(np.float64) for o in lst] for lst in omega_tildes[:sweeps]]
     t0 = time.perf_counter()
-    RT.rand_tucker(Ys, om, omt, sweeps=1, ranks=ranks)
+    RT.rand_tucker(Ys, om, omt, sweeps=sweeps, ranks=ranks)
     dt = time.perf_counter() - t0
-    nbytes = 2 * Ys.size * 4
+    nbytes = bytes_per_elem * Ys.size
+    where = ("the whole tensor" if slab >= Y.shape[2] else
+             f"the {Ys.shape[0]}x{Ys.shape[1]}x{slab} mode-3 slab of the tensor")
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": (f"RandTucker2i S=1 (sketches, QR, core, truncation) in "
-                       f"FP64 NumPy on "
-                       + ("the whole tensor" if slab >= Y.shape[2] else
-                          f"the {Ys.shape[0]}x{Ys.shape[1]}x{slab} mode-3 slab "
-                          "of the tensor")
-                       + f", {dt:.2f} s")}
+            "sample": (f"RandTucker2i S={sweeps} (sketches, QR, core, truncation) "
+                       f"in FP64 NumPy on {where}, {dt:.2f} s")}
+
+
+def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
+             warmup, tol, max_it, ybf16):
+    """Time `steps` calls of tucker_rand + ffcp in one form; returns timings,
+    the last outputs and the per-stage event totals."""
+    stream = torch.cuda.current_stream()
+
+    def step(tws, fws, ev):
+        ev[0].record(stream)
+        out = P.tucker_rand(Y, om_d, omt_d[:sweeps], ranks=ranks, sweeps=sweeps,
+                            precision=precision, workspace=tws, ybf16=ybf16,
+                            sync=False)
+        ev[1].record(stream)
+        f = P.ffcp(out["U"], out["G"], R, update="als", init="hosvd",
+                   max_it=max_it, tol=tol, workspace=fws, sync=False)
+        ev[2].record(stream)
+        return out, f
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tws = fws = None
+    for _ in range(max(warmup, 1)):      # the first call sizes the workspaces
+        out, f = step(tws, fws, mk())
+        tws, fws = out["workspace"], f["workspace"]
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    evs = [mk() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out, f = step(tws, fws, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = P.profile_read()
+    P.profile_enable(False)
+    finfo = np.frombuffer(f["info_dev"].cpu().numpy().tobytes(), P.FFCP_INFO_DTYPE)[0]
+    tinfo = np.frombuffer(out["info_dev"].cpu().numpy().tobytes(),
+                          P.TUCKER_INFO_DTYPE)[0]
+    fit_y = P.cp_fit_dense(Y, f["A"], f["lam"])[0]
+    return {
+        "tucker_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+        "ffcp_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+        "wall_ms": wall / steps * 1e3,
+        "prof": prof, "iterations": int(finfo["iterations"]),
+        "converged": int(finfo["converged"]), "fit_core": float(finfo["fit"]),
+        "fit_y": float(fit_y), "normY2": float(tinfo["normY2"]),
+    }
 
 
 def main():
@@ -126,73 +176,55 @@ def main():
     dims = (I, I, I)
     ranks = (R, R, R)
     d = synth.cp_congruent_device(1885, dims, R, 0.5, 0.95, 30.0, (rt,) * 3,
-                                  sweeps=1, device=dev)
+                                  sweeps=2, device=dev)
     Y = d["Y"]
     om32 = synth.f32(d["omegas"])
-    omt32 = [synth.f32(d["omega_tildes"][0])]
+    omt32 = [synth.f32(x) for x in d["omega_tildes"]]
     om_d = [torch.from_numpy(o).to(dev) for o in om32]
-    omt_d = [[torch.from_numpy(o).to(dev) for o in omt32[0]]]
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-
-    def step(tws, fws, ev):
-        ev[0].record(stream)
-        out = P.tucker_rand(Y, om_d, omt_d, ranks=ranks, sweeps=1,
-                            precision=args.precision, workspace=tws, sync=False)
-        ev[1].record(stream)
-        f = P.ffcp(out["U"], out["G"], R, update="als", init="hosvd",
-                   max_it=args.max_it, tol=args.tol, workspace=fws, sync=False)
-        ev[2].record(stream)
-        return out, f
-
-    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    # warmup (first call allocates the workspaces)
-    tws = fws = None
-    for _ in range(max(args.warmup, 1)):
-        out, f = step(tws, fws, mk())
-        tws = out["workspace"]
-        fws = f.get("workspace")
+    omt_d = [[torch.from_numpy(o).to(dev) for o in lst] for lst in omt32]
+    ybf16 = torch.empty(dims, dtype=torch.int16, device=dev)
     torch.cuda.synchronize()
 
-    P.profile_enable(True)
-    evs = [mk() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        out, f = step(tws, fws, evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = P.profile_read()
-    P.profile_enable(False)
+    forms = {"bf16": 2, "f32": 1}
+    main_form = args.precision
+    other = "f32" if main_form == "bf16" else "bf16"
+    res = {}
+    for form in (other, main_form):      # the step's form runs last
+        res[form] = run_form(P, torch, Y, om_d, omt_d, ranks, R, form, forms[form],
+                             args.steps, args.warmup, args.tol, args.max_it, ybf16)
+    m = res[main_form]
 
-    tucker_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    ffcp_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    finfo = np.frombuffer(f["info_dev"].cpu().numpy().tobytes(), P.FFCP_INFO_DTYPE)[0]
-    tinfo = np.frombuffer(out["info_dev"].cpu().numpy().tobytes(),
-                          P.TUCKER_INFO_DTYPE)[0]
+    # algorithmic HBM bytes of the Tucker stage (each pass reads Y once):
+    # plain FP32, one sweep: sweep + core = 2 x 4 B per element; precision
+    # form, two sweeps: FP32 read + BF16 write (first sweep) + two BF16 reads
+    n = Y.numel()
+    alg_bytes = {"f32": 2 * 4 * n, "bf16": (4 + 2 + 2 + 2) * n}
+    value = alg_bytes[main_form] / (m["tucker_ms"] * 1e-3) / 1e9
 
-    # algorithmic HBM bytes of the Tucker stage: each pass over Y reads it
-    # once (sweep pass + core pass for S = 1)
-    ybytes = Y.numel() * Y.element_size()
-    passes = 2
-    t_tucker = float(np.mean(tucker_ms)) * 1e-3
-    value = passes * ybytes / t_tucker / 1e9
-
-    # dominant kernel: the dual-contraction sweep pass (first_pass stage)
-    ms_dual, n_dual = prof["first_pass"]
-    t_dual = ms_dual / max(n_dual, 1) * 1e-3
-    flops_dual = 2.0 * Y.numel() * (rt + rt)   # Y x_3 Omega_3^T and Y x_2 Omega_2^T
-    achieved = flops_dual / t_dual / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    # dominant kernel: the first sweep's streaming kernel
+    ms_k, n_k = m["prof"]["first_pass"]
+    t_k = ms_k / max(n_k, 1) * 1e-3
     workload = f"cp{R}_congruent_{I}x{I}x{I}_f32"
-    traffic = stored_traffic("dual_f32_kernel", workload)
-    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic,
-            "kernel": "dual_f32_kernel (sweep pass: Y x_3 Omega_3^T and "
-                      "Y x_2 Omega_2^T in one read of Y)",
-            "avg_ms": round(t_dual * 1e3, 4),
-            "hbm_gbs": round(ybytes / t_dual / 1e9, 1)}
+    if main_form == "f32":
+        flops = 2.0 * n * (rt + rt)   # Y x_3 Omega_3^T and Y x_2 Omega_2^T
+        achieved = flops / t_k / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2),
+                "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS["f32"], 4),
+                "traffic": stored_traffic("dual_f32_kernel", workload),
+                "kernel": "dual_f32_kernel (first sweep: Y x_3 Omega_3^T and "
+                          "Y x_2 Omega_2^T in one read of Y)",
+                "avg_ms": round(t_k * 1e3, 4)}
+    else:
+        kbytes = (4 + 2) * n          # FP32 read + BF16 copy written
+        achieved = kbytes / t_k / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic("bf16_stream_kernel", workload),
+                "kernel": "bf16_stream_kernel<true,true> (first sweep: FP32 read, "
+                          "BF16 copy write, Y x_3 Omega_3^T and Y x_2 Omega_2^T)",
+                "avg_ms": round(t_k * 1e3, 4)}
 
     if args.copy_calibration:
         # plain elementwise copy kernel of known traffic (reads 4 B, writes
@@ -205,7 +237,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab)
+        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab, forms[main_form],
+                           alg_bytes[main_form] // n)
+
+    def summary(form):
+        r = res[form]
+        return {"sweeps": forms[form], "tucker_ms": round(r["tucker_ms"], 4),
+                "tucker_gbs": round(alg_bytes[form] / (r["tucker_ms"] * 1e-3) / 1e9, 1),
+                "ffcp_ms": round(r["ffcp_ms"], 4),
+                "time_to_fit_ms": round(r["tucker_ms"] + r["ffcp_ms"], 4),
+                "ffcp_iterations": r["iterations"], "ffcp_converged": r["converged"],
+                "fit_core": r["fit_core"], "fit_y": r["fit_y"],
+                "stages_ms": {k: round(v[0] / max(v[1], 1), 4)
+                              for k, v in r["prof"].items() if v[1] > 0}}
 
     line = {
         "metric": METRIC,
@@ -214,31 +258,27 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "ms_per_step": round(m["wall_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": main_form,
         "data": "synthetic",
         "config": {
             "workload": workload,
             "description": (f"{I}^3 FP32 CP rank {R}, column congruence "
                             "U[0.5,0.95], SNR 30 dB; Omega_n "
                             f"{I}x{rt}, Omega~_n {rt * rt}x{rt}; Tucker ranks "
-                            f"{ranks}, one sketch sweep; FFCP ALS R={R}, HOSVD "
-                            f"init, tol {args.tol}"),
+                            f"{ranks}; FFCP ALS R={R}, HOSVD init, tol {args.tol}"),
             "dims": list(dims), "ranks": list(ranks), "ranks_tilde": [rt] * 3,
-            "sweeps": 1, "R": R, "update": "als", "precision": args.precision,
+            "sweeps": forms[main_form], "R": R, "update": "als",
         },
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
-        "tucker_ms": round(float(np.mean(tucker_ms)), 4),
-        "ffcp_ms": round(float(np.mean(ffcp_ms)), 4),
-        "ffcp_iterations": int(finfo["iterations"]),
-        "ffcp_converged": int(finfo["converged"]),
-        "fit_core": float(finfo["fit"]),
-        "normY2": float(tinfo["normY2"]),
-        "stages_ms": {k: round(v[0] / max(v[1], 1), 4)
-                      for k, v in prof.items() if v[1] > 0},
+        main_form: summary(main_form),
+        other: summary(other),
+        "fit_y_rel_diff_mixed_vs_plain": abs(res["bf16"]["fit_y"] - res["f32"]["fit_y"]) /
+            max(abs(res["f32"]["fit_y"]), 1e-300),
+        "normY2": m["normY2"],
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -301,9 +301,12 @@ int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
  * enqueues with HIP events on the caller's stream; rt_profile_read waits for
  * the recorded events and returns per-stage totals.  Host-side only; the
  * events are created by the library (no device memory).
- * Stages: 0 = first streamed pass over Y (sweep with conversion/norm),
- * 1 = later sweep passes, 2 = core pass, 3 = intermediate contractions and
- * sketch products, 4 = QR, 5 = truncation (Gram, eig, rotation), 6 = FFCP.
+ * Stages (each brackets the launches named): 0 = the streaming kernel of the
+ * first sweep (the one that also converts to BF16 in the precision form),
+ * 1 = the streaming kernel of later sweeps, 2 = the core pass's streaming
+ * kernel, 3 = intermediate contractions and sketch products, 4 = QR,
+ * 5 = truncation (Gram, eig, rotation), 6 = FFCP, 7 = per-slab statistics
+ * pass of the precision form (exponents, ||Y||^2).
  */
 #define RT_PROFILE_STAGES 8
 typedef struct {

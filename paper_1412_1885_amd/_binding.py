@@ -345,7 +345,7 @@ class Profile(ctypes.Structure):
 
 
 PROFILE_STAGES = ("first_pass", "sweep_pass", "core_pass", "contract", "qr",
-                  "truncate", "ffcp", "reserved")
+                  "truncate", "ffcp", "stats")
 
 
 def profile_enable(on=True):

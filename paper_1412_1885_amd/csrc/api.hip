@@ -45,12 +45,6 @@ int check_ptr(const void* p, const char* name) {
   return kOk;
 }
 
-#define RT_TRY(x)             \
-  do {                        \
-    int _rc = (x);            \
-    if (_rc != kOk) return _rc; \
-  } while (0)
-
 // ------------------------------------------------------------ tucker_rand
 
 int validate_tucker(const rt_tucker_desc* d) {
@@ -114,6 +108,9 @@ int validate_tucker(const rt_tucker_desc* d) {
     set_error("sketch core prod R~_n = %lld too large", (long long)core);
     return kErrUnsupported;
   }
+  if (d->precision == RT_BF16_MIXED)
+    RT_TRY(bf16_check_shape(d->dims[d->N - 2], d->dims[d->N - 1],
+                            d->ranks_tilde[d->N - 2], d->ranks_tilde[d->N - 1]));
   return kOk;
 }
 
@@ -300,11 +297,8 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
 
   for (int sw = 0; sw < d->sweeps; ++sw) {
     // streamed pass: TA = Y x_last B_last^T, TB = Y x_second B_second^T
-    {
-      ProfScope ps(sw == 0 ? kStageFirstPass : kStageSweepPass, s);
-      RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second],
-                            P.K[second], P.TA, P.TB, s));
-    }
+    RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second], P.K[second], P.TA,
+                          P.TB, s));
     {
       ProfScope ps(kStageContract, s);
       for (int n = 0; n < N; ++n)
@@ -342,10 +336,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
   }
 
   // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first, then the rest
-  {
-    ProfScope ps(kStageCorePass, s);
-    RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
-  }
+  RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
   {
     ProfScope ps(kStageContract, s);
     int64_t D[RT_MAX_MODES];
@@ -388,6 +379,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
                        s) != hipSuccess)
       return hip_fail(hipGetLastError(), "G copy");
   } else {
+    ProfScope ps(kStageTruncate, s);
     EigBatch eb{};
     eb.nb = N;
     int64_t Apre = 1;
@@ -733,6 +725,7 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
       RT_LAUNCH_CHECK("hosvd pad");
     }
   }
+  ProfScope ps(kStageFfcp, s);
   if (ffcp_als_core_applicable(a)) {
     const int rc = launch_ffcp_als_core(a, s);
     if (rc != kErrUnsupported) return rc;

@@ -29,6 +29,12 @@ int hip_fail(hipError_t e, const char* what);
     if (_e != hipSuccess) return ::rt::hip_fail(_e, what);      \
   } while (0)
 
+#define RT_TRY(x)                      \
+  do {                                 \
+    int _rc = (x);                     \
+    if (_rc != ::rt::kOk) return _rc;  \
+  } while (0)
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

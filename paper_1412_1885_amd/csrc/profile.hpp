@@ -12,7 +12,8 @@ enum ProfStage {
   kStageContract = 3,
   kStageQr = 4,
   kStageTruncate = 5,
-  kStageFfcp = 6
+  kStageFfcp = 6,
+  kStageStats = 7
 };
 
 bool prof_enabled();

@@ -26,6 +26,7 @@
 #include "stream.hpp"
 
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace rt {
 
@@ -295,7 +296,7 @@ int grid_for(int64_t A, int wps) {
 
 int run_dual_f32(const StreamCtx& c, const float* Y, const float* B2, int K2,
                  const float* B1, int K1, float* TA, float* TB, bool doQ,
-                 bool doNorm, hipStream_t s, bool* used) {
+                 bool doNorm, int stage, hipStream_t s, bool* used) {
   int wps = 0, ct = 0;
   *used = false;
   if (!plan_dual(static_cast<int>(c.I2), doQ ? K1 : 0, K2, doQ, &wps, &ct) ||
@@ -317,8 +318,12 @@ int run_dual_f32(const StreamCtx& c, const float* Y, const float* B2, int K2,
   a.norm_partial = doNorm ? c.norm_partial : nullptr;
   a.stage_offset = static_cast<int>(b2_floats(a.I2, K2, doQ));
   const size_t lds = dual_lds_bytes(a.I2, K2, doQ);
-  const int rc0 = doQ ? launch_dual_ct<true>(ct, a, grid, lds, s)
-                      : launch_dual_ct<false>(ct, a, grid, lds, s);
+  int rc0;
+  {
+    ProfScope ps(stage, s);
+    rc0 = doQ ? launch_dual_ct<true>(ct, a, grid, lds, s)
+              : launch_dual_ct<false>(ct, a, grid, lds, s);
+  }
   if (rc0 != kOk) return rc0;
   RT_LAUNCH_CHECK("dual_f32");
   if (doNorm) {
@@ -331,8 +336,14 @@ int run_dual_f32(const StreamCtx& c, const float* Y, const float* B2, int K2,
 
 }  // namespace
 
-size_t stream_workspace_bytes(const rt_tucker_desc*) {
-  return 1024 * sizeof(double) + 256;
+size_t stream_workspace_bytes(const rt_tucker_desc* d) {
+  size_t b = 1024 * sizeof(double) + 256;
+  if (d->precision == RT_BF16_MIXED) {
+    int64_t A = 1;
+    for (int p = 0; p < d->N - 2; ++p) A *= d->dims[p];
+    b += bf16_stream_workspace_bytes(A, d->dims[d->N - 2], d->dims[d->N - 1]);
+  }
+  return b;
 }
 
 StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
@@ -361,14 +372,18 @@ template <typename T>
 int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1,
                 int K1, T* TA, T* TB, hipStream_t s) {
   if (c.precision == RT_BF16_MIXED) {
-    set_error("BF16 mixed precision is not available in this build");
+    if constexpr (sizeof(T) == sizeof(float))
+      return bf16_stream_pass(c, sweep == 0, B2, K2, B1, K1, TA, TB,
+                              sweep == 0 ? kStageFirstPass : kStageSweepPass, s);
+    set_error("BF16 mixed precision computes in FP32");
     return kErrUnsupported;
   }
   const T* Y = static_cast<const T*>(c.y);
   const bool doNorm = sweep == 0;
   if constexpr (sizeof(T) == sizeof(float)) {
     bool used = false;
-    int rc = run_dual_f32(c, Y, B2, K2, B1, K1, TA, TB, true, doNorm, s, &used);
+    int rc = run_dual_f32(c, Y, B2, K2, B1, K1, TA, TB, true, doNorm,
+                          sweep == 0 ? kStageFirstPass : kStageSweepPass, s, &used);
     if (rc != kOk || used) return rc;
   }
   // generic path: two vector-ALU passes and a separate norm pass
@@ -377,6 +392,7 @@ int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1,
                              c.norm_out, c.nonfinite, s);
     if (rc != kOk) return rc;
   }
+  ProfScope ps(sweep == 0 ? kStageFirstPass : kStageSweepPass, s);
   int rc = launch_ttm<T>(Y, B2, TA, c.A * c.I1, c.I2, 1, K2, s);
   if (rc != kOk) return rc;
   return launch_ttm<T>(Y, B1, TB, c.A, c.I1, c.I2, K1, s);
@@ -386,15 +402,18 @@ template <typename T>
 int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
                   hipStream_t s) {
   if (c.precision == RT_BF16_MIXED) {
-    set_error("BF16 mixed precision is not available in this build");
+    if constexpr (sizeof(T) == sizeof(float))
+      return bf16_stream_pass(c, sweep == 0, B2, K2, nullptr, 0, TA, nullptr,
+                              kStageCorePass, s);
+    set_error("BF16 mixed precision computes in FP32");
     return kErrUnsupported;
   }
   const T* Y = static_cast<const T*>(c.y);
   const bool doNorm = sweep == 0;
   if constexpr (sizeof(T) == sizeof(float)) {
     bool used = false;
-    int rc = run_dual_f32(c, Y, B2, K2, nullptr, 0, TA, nullptr, false, doNorm, s,
-                          &used);
+    int rc = run_dual_f32(c, Y, B2, K2, nullptr, 0, TA, nullptr, false, doNorm,
+                          kStageCorePass, s, &used);
     if (rc != kOk || used) return rc;
   }
   if (doNorm) {
@@ -402,6 +421,7 @@ int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
                              c.norm_out, c.nonfinite, s);
     if (rc != kOk) return rc;
   }
+  ProfScope ps(kStageCorePass, s);
   return launch_ttm<T>(Y, B2, TA, c.A * c.I1, c.I2, 1, K2, s);
 }
 

@@ -31,6 +31,14 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
                           uint16_t* ybf16, void* ws, size_t ws_bytes,
                           double* norm_out, int32_t* nonfinite);
 
+// BF16 precision form (stream_bf16.hip)
+size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2);
+int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2);
+// stage: profiling stage that brackets the streaming kernel itself
+int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
+                     const float* B1, int K1, float* TA, float* TB, int stage,
+                     hipStream_t s);
+
 template <typename T>
 int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2,
                 const T* B1, int K1, T* TA, T* TB, hipStream_t s);

@@ -1,0 +1,370 @@
+// BF16 precision form of the Y-streaming passes (RT_BF16_MIXED).
+//
+// The sketches and the core projection contract Y against thin factor
+// matrices (Algorithm 3, lines 3-6 and 8; the blocked products of eq. (22)).
+// In this form the tensor is stored once in BF16 and every pass after the
+// first reads 2 bytes per element; the products run on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation, so at R~ <= 32 a pass is
+// bound by HBM bandwidth, not by the matrix cores.
+//
+// Scaling.  Each slab a of the streaming view [A, I1, I2] carries a power of
+// two 2^e_a with e_a the binary exponent of max|Y[a]|; the stored value is
+// bf16_rne(Y * 2^-e_a) and every product of the slab is multiplied by 2^e_a.
+// The scale is exact (a power of two), keeps each slab's largest entries in
+// [1, 2) and its small entries out of the BF16 subnormal range.
+//
+// Passes.  The first pass of a call (FP32 input) reads FP32, rounds, writes
+// the BF16 copy and feeds the rounded values to the matrix cores in the same
+// kernel; ||Y||^2, the non-finite flag and the slab exponents come from a
+// statistics pass before it.  Later sweeps and the core pass read the BF16
+// copy.
+//
+// Data path (one workgroup of 8 wavefronts per slab).  Wave w owns the
+// 32-row blocks w, w+8, w+16, w+24 (I1 <= 1024) and walks the slab in
+// 64-column tiles.  Lane l loads, for each 16-column chunk q of the tile,
+// the 8 values Y[r0 + l%32][c0 + 16q + 8(l/32) .. +7] (16 bytes of BF16):
+// exactly the A operand of the 32x32x16 MFMA for TA = M B2 (K = columns).
+// For TB = B1^T M (K = rows) the B operand needs 8 consecutive rows of one
+// column, so the wave also writes its tile transposed into a private LDS
+// tile and reads it back with 16-byte loads.  TA accumulates in registers
+// across the column tiles; TB's partial sums over each wave's rows are
+// reduced across the 8 waves in LDS, in a fixed order, once per column tile.
+#include "stream.hpp"
+
+#include "kernels.hpp"
+#include "profile.hpp"
+
+namespace rt {
+
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kBW = 8;                 // wavefronts per workgroup
+constexpr int kBThreads = kBW * 64;
+constexpr int kRBMax = 4;              // 32-row blocks per wave
+constexpr int kCT = 64;                // columns per tile
+constexpr int kYtStride = 40;          // halfwords per row of the transposed tile
+constexpr int kMaxI1 = 32 * kBW * kRBMax;
+
+struct BfArgs {
+  const void* Y;          // FP32 (first pass) or BF16 bit patterns
+  uint16_t* Yb;           // BF16 copy written by the first pass
+  const int32_t* exps;    // per-slab exponent
+  int64_t A;
+  int I1, I2;
+  const uint16_t* B2t;    // [32][ldb2] BF16, zero beyond (K2, I2)
+  int ldb2, K2;
+  const uint16_t* B1t;    // [32][ldb1] BF16, zero beyond (K1, I1)
+  int ldb1, K1;
+  float* TA;              // [A, I1, K2]
+  float* TB;              // [A, K1, I2]
+};
+
+__device__ __forceinline__ v8bf as_v8bf(uint4 u) { return __builtin_bit_cast(v8bf, u); }
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  return static_cast<uint32_t>(f32_to_bf16_rne(lo)) |
+         (static_cast<uint32_t>(f32_to_bf16_rne(hi)) << 16);
+}
+
+template <bool SRC_F32, bool DOQ>
+__global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 31, g = lane >> 5;
+  uint16_t* yt = reinterpret_cast<uint16_t*>(smem) + w * (kCT * kYtStride);
+  float* red = reinterpret_cast<float*>(smem + kBW * kCT * kYtStride * 2);
+  const int nrb = (a.I1 + 31) / 32;
+  const int nct = (a.I2 + kCT - 1) / kCT;
+  const int64_t slab_elems = static_cast<int64_t>(a.I1) * a.I2;
+
+  for (int64_t slab = blockIdx.x; slab < a.A; slab += gridDim.x) {
+    const int e = a.exps[slab];
+    const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
+    const int64_t base = slab * slab_elems;
+    v16f accA[kRBMax];
+#pragma unroll
+    for (int i = 0; i < kRBMax; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) accA[i][v] = 0.0f;
+
+    for (int ct = 0; ct < nct; ++ct) {
+      const int c0 = ct * kCT;
+      v8bf b2[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        b2[q] = as_v8bf(*reinterpret_cast<const uint4*>(
+            a.B2t + static_cast<int64_t>(lr) * a.ldb2 + c0 + 16 * q + 8 * g));
+      v16f accB[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accB[s][v] = 0.0f;
+
+#pragma unroll
+      for (int i = 0; i < kRBMax; ++i) {
+        const int rb = w + kBW * i;
+        // keep each row block's loads in its own iteration (register budget)
+        __builtin_amdgcn_sched_barrier(0);
+        if (rb < nrb) {
+          const int r = rb * 32 + lr;
+          uint4 yv[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = c0 + 16 * q + 8 * g;
+            const bool ok = r < a.I1 && c < a.I2;   // I2 % 8 == 0
+            const int64_t off = base + static_cast<int64_t>(r) * a.I2 + c;
+            if constexpr (SRC_F32) {
+              float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+              if (ok) {
+                const float* p = static_cast<const float*>(a.Y) + off;
+                lo = *reinterpret_cast<const float4*>(p);
+                hi = *reinterpret_cast<const float4*>(p + 4);
+              }
+              yv[q].x = pack2(lo.x * down, lo.y * down);
+              yv[q].y = pack2(lo.z * down, lo.w * down);
+              yv[q].z = pack2(hi.x * down, hi.y * down);
+              yv[q].w = pack2(hi.z * down, hi.w * down);
+              if (ok) *reinterpret_cast<uint4*>(a.Yb + off) = yv[q];
+            } else {
+              yv[q] = make_uint4(0u, 0u, 0u, 0u);
+              if (ok)
+                yv[q] = *reinterpret_cast<const uint4*>(
+                    static_cast<const uint16_t*>(a.Y) + off);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            accA[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yv[q]), b2[q],
+                                                              accA[i], 0, 0, 0);
+          if constexpr (DOQ) {
+            // transposed copy: yt[col][row]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t wds[4] = {yv[q].x, yv[q].y, yv[q].z, yv[q].w};
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const uint16_t h = static_cast<uint16_t>(wds[j >> 1] >> (16 * (j & 1)));
+                yt[(16 * q + 8 * g + j) * kYtStride + lr] = h;
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const v8bf b1 = as_v8bf(*reinterpret_cast<const uint4*>(
+                  a.B1t + static_cast<int64_t>(lr) * a.ldb1 + rb * 32 + 16 * h + 8 * g));
+#pragma unroll
+              for (int s = 0; s < 2; ++s) {
+                const v8bf yc = as_v8bf(*reinterpret_cast<const uint4*>(
+                    yt + (32 * s + lr) * kYtStride + 16 * h + 8 * g));
+                accB[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, yc, accB[s], 0, 0,
+                                                                  0);
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+        }
+      }
+
+      if constexpr (DOQ) {
+        // TB partial of this wave (32 x 64) -> LDS; fixed-order sum over waves
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int m = 8 * (v / 4) + 4 * g + (v % 4);
+            red[(w * 32 + m) * kCT + 32 * s + lr] = accB[s][v];
+          }
+        __syncthreads();
+        for (int l = threadIdx.x; l < 32 * kCT; l += kBThreads) {
+          const int m = l / kCT, n = l % kCT;
+          float sum = 0.0f;
+#pragma unroll
+          for (int ww = 0; ww < kBW; ++ww) sum += red[(ww * 32 + m) * kCT + n];
+          if (m < a.K1 && c0 + n < a.I2)
+            a.TB[(slab * a.K1 + m) * a.I2 + c0 + n] = sum * up;
+        }
+        __syncthreads();
+      }
+    }
+    // TA rows of this wave's blocks
+#pragma unroll
+    for (int i = 0; i < kRBMax; ++i) {
+      const int rb = w + kBW * i;
+      if (rb < nrb) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = 8 * (v / 4) + 4 * g + (v % 4);
+          const int r = rb * 32 + m;
+          if (r < a.I1 && lr < a.K2)
+            a.TA[(slab * a.I1 + r) * a.K2 + lr] = accA[i][v] * up;
+        }
+      }
+    }
+  }
+}
+
+// Per-slab statistics of the input: exponent of max|Y[a]| (FP32 input only),
+// ||Y||^2 partial sums per workgroup (FP64).
+template <bool SRC_F32>
+__global__ __launch_bounds__(256) void slab_stats_kernel(const void* Y, int64_t A,
+                                                         int64_t slab, int32_t* exps,
+                                                         double* partial) {
+  __shared__ float smax[4];
+  __shared__ double ssum[4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double acc = 0.0;
+  for (int64_t a = blockIdx.x; a < A; a += gridDim.x) {
+    float mx = 0.0f;
+    double s = 0.0;
+    if constexpr (SRC_F32) {
+      const float* p = static_cast<const float*>(Y) + a * slab;
+      const int64_t n4 = slab / 4;
+      for (int64_t l = t; l < n4; l += 256) {
+        const float4 v = reinterpret_cast<const float4*>(p)[l];
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        const double dx = v.x, dy = v.y, dz = v.z, dw = v.w;
+        s += (dx * dx + dy * dy) + (dz * dz + dw * dw);
+        if (!(fabsf(v.x) <= 3.4e38f && fabsf(v.y) <= 3.4e38f && fabsf(v.z) <= 3.4e38f &&
+              fabsf(v.w) <= 3.4e38f))
+          s = __longlong_as_double(0x7ff8000000000000LL);
+      }
+      for (int64_t l = n4 * 4 + t; l < slab; l += 256) {
+        const float v = p[l];
+        mx = fmaxf(mx, fabsf(v));
+        s += static_cast<double>(v) * v;
+        if (!(fabsf(v) <= 3.4e38f)) s = __longlong_as_double(0x7ff8000000000000LL);
+      }
+    } else {
+      const uint16_t* p = static_cast<const uint16_t*>(Y) + a * slab;
+      for (int64_t l = t; l < slab; l += 256) {
+        const float v = bf16_to_f32(p[l]);
+        s += static_cast<double>(v) * v;
+      }
+    }
+    s = wave_sum(s);
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    __syncthreads();
+    if (lane == 0) {
+      smax[wv] = mx;
+      ssum[wv] = s;
+    }
+    __syncthreads();
+    if (t == 0) {
+      const float m = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+      int e = 0;
+      if (SRC_F32 && m > 0.0f && m <= 3.4e38f) e = ilogbf(m);
+      exps[a] = e < -126 ? -126 : (e > 127 ? 127 : e);   // 2^-e stays finite
+      acc += (ssum[0] + ssum[1]) + (ssum[2] + ssum[3]);
+    }
+  }
+  if (t == 0) partial[blockIdx.x] = acc;
+}
+
+// Bt[k][c] = bf16_rne(B[c][k]) for k < K, c < I; zero in the padding
+// (k < 32, c < ld).
+__global__ void prep_bt_kernel(const float* B, int I, int K, uint16_t* Bt, int ld) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= 32 * ld) return;
+  const int k = l / ld, c = l % ld;
+  Bt[l] = (k < K && c < I) ? f32_to_bf16_rne(B[static_cast<int64_t>(c) * K + k]) : 0;
+}
+
+int stats_grid(int64_t A) { return static_cast<int>(A < 1024 ? A : 1024); }
+
+template <bool SRC_F32, bool DOQ>
+int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
+  auto k = bf16_stream_kernel<SRC_F32, DOQ>;
+  const size_t lds = DOQ ? static_cast<size_t>(kBW) * kCT * kYtStride * 2 +
+                               static_cast<size_t>(kBW) * 32 * kCT * 4
+                         : 0;
+  if (lds > 0) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return hip_fail(e, "bf16 stream LDS attribute");
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kBThreads), lds, s, a);
+  RT_LAUNCH_CHECK("bf16 stream");
+  return kOk;
+}
+
+}  // namespace
+
+// Workspace of the BF16 passes (inside the streaming workspace): slab
+// exponents and the two transposed BF16 factor copies.
+size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
+  const int64_t l1 = (I1 + 63) / 64 * 64, l2 = (I2 + 63) / 64 * 64;
+  return static_cast<size_t>(A) * 4 + 256 + 2 * 32 * (l1 + l2) + 512;
+}
+
+int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
+  if (I1 > kMaxI1 || I2 % 8 != 0 || K1 > 32 || K2 > 32 || I2 > (1 << 30)) {
+    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 8 == 0 and "
+              "sketch widths <= 32 (got %lld, %lld, %d, %d)",
+              kMaxI1, (long long)I1, (long long)I2, K1, K2);
+    return kErrUnsupported;
+  }
+  return kOk;
+}
+
+// One BF16 streaming pass.  first: statistics + FP32 read + BF16 write
+// (unless the input is already BF16).  B1 == nullptr: TA only.
+int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
+                     const float* B1, int K1, float* TA, float* TB, int stage,
+                     hipStream_t s) {
+  RT_TRY(bf16_check_shape(c.I1, c.I2, B1 ? K1 : 0, K2));
+  const int64_t l1 = (c.I1 + 63) / 64 * 64, l2 = (c.I2 + 63) / 64 * 64;
+  char* base = static_cast<char*>(c.ws) + 1024 * sizeof(double) + 256;
+  int32_t* exps = reinterpret_cast<int32_t*>(base);
+  uint16_t* B2t = reinterpret_cast<uint16_t*>(base + (c.A * 4 + 255) / 256 * 256);
+  uint16_t* B1t = B2t + 32 * l2;
+  if (first) {
+    const int g = stats_grid(c.A);
+    ProfScope ps(kStageStats, s);
+    if (c.bf16_input)
+      hipLaunchKernelGGL(slab_stats_kernel<false>, dim3(g), dim3(256), 0, s, c.ybf16,
+                         c.A, c.I1 * c.I2, exps, c.norm_partial);
+    else
+      hipLaunchKernelGGL(slab_stats_kernel<true>, dim3(g), dim3(256), 0, s, c.y, c.A,
+                         c.I1 * c.I2, exps, c.norm_partial);
+    RT_LAUNCH_CHECK("slab stats");
+    RT_TRY(launch_sum_partials(c.norm_partial, g, c.norm_out, c.nonfinite, s));
+  }
+  hipLaunchKernelGGL(prep_bt_kernel, dim3((32 * l2 + 255) / 256), dim3(256), 0, s, B2,
+                     static_cast<int>(c.I2), K2, B2t, static_cast<int>(l2));
+  RT_LAUNCH_CHECK("prep B2");
+  if (B1) {
+    hipLaunchKernelGGL(prep_bt_kernel, dim3((32 * l1 + 255) / 256), dim3(256), 0, s,
+                       B1, static_cast<int>(c.I1), K1, B1t, static_cast<int>(l1));
+    RT_LAUNCH_CHECK("prep B1");
+  }
+  BfArgs a{};
+  const bool from_f32 = first && !c.bf16_input;
+  a.Y = from_f32 ? c.y : static_cast<const void*>(c.ybf16);
+  a.Yb = from_f32 ? c.ybf16 : nullptr;
+  a.exps = exps;
+  a.A = c.A;
+  a.I1 = static_cast<int>(c.I1);
+  a.I2 = static_cast<int>(c.I2);
+  a.B2t = B2t;
+  a.ldb2 = static_cast<int>(l2);
+  a.K2 = K2;
+  a.B1t = B1t;
+  a.ldb1 = static_cast<int>(l1);
+  a.K1 = B1 ? K1 : 0;
+  a.TA = TA;
+  a.TB = TB;
+  const int grid = static_cast<int>(c.A < 2048 ? c.A : 2048);
+  ProfScope ps(stage, s);
+  if (B1) return from_f32 ? launch_bf<true, true>(a, grid, s) : launch_bf<false, true>(a, grid, s);
+  return from_f32 ? launch_bf<true, false>(a, grid, s) : launch_bf<false, false>(a, grid, s);
+}
+
+}  // namespace rt

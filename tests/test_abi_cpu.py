@@ -73,6 +73,21 @@ def test_tucker_workspace_validation():
         assert P.last_error()
 
 
+def test_bf16_shapes_checked_at_validation():
+    """The BF16 streaming pass needs I_N % 8 == 0, I_{N-1} <= 1024 and the
+    two streamed sketch widths <= 32: rejected before anything is launched."""
+    n = ctypes.c_size_t(0)
+    ok = P.tucker_desc([4, 20, 32], [4, 5, 5], [3, 3, 3], precision="bf16")
+    assert P.lib().rt_tucker_rand_workspace(ctypes.byref(ok), ctypes.byref(n)) == 0
+    for dims, rt in (([4, 20, 30], [4, 5, 5]),        # I_N % 8 != 0
+                     ([4, 1100, 32], [4, 5, 5]),      # I_{N-1} > 1024
+                     ([4, 40, 64], [4, 5, 33])):      # streamed width > 32
+        d = P.tucker_desc(dims, rt, [3, 3, 3], precision="bf16")
+        rc = P.lib().rt_tucker_rand_workspace(ctypes.byref(d), ctypes.byref(n))
+        assert rc == -2, (dims, rt, rc)   # RT_ERR_UNSUPPORTED
+        assert "BF16" in P.last_error()
+
+
 def test_gauss_seidel_flag_reports_unsupported():
     d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7])
     d.flags |= B.RT_FLAG_GAUSS_SEIDEL
