@@ -69,26 +69,87 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
          (static_cast<uint32_t>(f32_to_bf16_rne(hi)) << 16);
 }
 
+// Raw operands of one 32 x 64 tile for one lane: 4 chunks of 8 values,
+// FP32 (first pass) or BF16.
+template <bool SRC_F32>
+struct TileRaw;
+template <>
+struct TileRaw<true> {
+  float4 v[8];
+};
+template <>
+struct TileRaw<false> {
+  uint4 v[4];
+};
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// Buffer descriptor over one slab (byte range); loads past it return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0,
+                                           static_cast<int>(bytes), 0x00020000);
+}
+
+// Loads the lane's part of the 32 x 64 tile at rows rb*32.. and columns
+// c0..: buffer loads with a 32-bit offset into the slab; masked lanes get an
+// offset past the slab, so the hardware returns zeros without branches.
+template <bool SRC_F32>
+__device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArgs& a,
+                                          int rb, int lr, int c0, int g,
+                                          TileRaw<SRC_F32>& t) {
+  constexpr int kEl = SRC_F32 ? 4 : 2;
+  const int r = rb * 32 + lr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + 16 * q + 8 * g;
+    const bool ok = r < a.I1 && c < a.I2;   // I2 % 8 == 0
+    const int off = ok ? (r * a.I2 + c) * kEl : 0x7ffffff0;
+    if constexpr (SRC_F32) {
+      const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? off + 16 : off, 0, 0);
+      t.v[2 * q] = make_float4(__uint_as_float(lo.x), __uint_as_float(lo.y),
+                               __uint_as_float(lo.z), __uint_as_float(lo.w));
+      t.v[2 * q + 1] = make_float4(__uint_as_float(hi.x), __uint_as_float(hi.y),
+                                   __uint_as_float(hi.z), __uint_as_float(hi.w));
+    } else {
+      const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      t.v[q] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+  }
+}
+
 template <bool SRC_F32, bool DOQ>
 __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   extern __shared__ __align__(16) char smem[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int lr = lane & 31, g = lane >> 5;
   uint16_t* yt = reinterpret_cast<uint16_t*>(smem) + w * (kCT * kYtStride);
   float* red = reinterpret_cast<float*>(smem + kBW * kCT * kYtStride * 2);
   const int nrb = (a.I1 + 31) / 32;
   const int nct = (a.I2 + kCT - 1) / kCT;
+  const int myrb = w < nrb ? (nrb - 1 - w) / kBW + 1 : 0;   // row blocks of this wave
   const int64_t slab_elems = static_cast<int64_t>(a.I1) * a.I2;
 
-  for (int64_t slab = blockIdx.x; slab < a.A; slab += gridDim.x) {
+  // one slab per workgroup: no outer loop, so nothing slab-invariant is kept
+  // live across slabs
+  {
+    const int64_t slab = blockIdx.x;
     const int e = a.exps[slab];
     const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
     const int64_t base = slab * slab_elems;
+    const __amdgpu_buffer_rsrc_t rs =
+        SRC_F32 ? slab_rsrc(static_cast<const float*>(a.Y) + base, slab_elems * 4)
+                : slab_rsrc(static_cast<const uint16_t*>(a.Y) + base, slab_elems * 2);
     v16f accA[kRBMax];
 #pragma unroll
     for (int i = 0; i < kRBMax; ++i)
 #pragma unroll
       for (int v = 0; v < 16; ++v) accA[i][v] = 0.0f;
+
+    // tiles are visited in the order (ct, i); each is loaded one step ahead
+    TileRaw<SRC_F32> buf[2];
+    if (!(SRC_F32 && DOQ) && myrb > 0) load_tile<SRC_F32>(rs, a, w, lr, 0, g, buf[0]);
 
     for (int ct = 0; ct < nct; ++ct) {
       const int c0 = ct * kCT;
@@ -105,34 +166,35 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
 
 #pragma unroll
       for (int i = 0; i < kRBMax; ++i) {
-        const int rb = w + kBW * i;
-        // keep each row block's loads in its own iteration (register budget)
-        __builtin_amdgcn_sched_barrier(0);
-        if (rb < nrb) {
-          const int r = rb * 32 + lr;
+        if (i < myrb) {
+          const int rb = w + kBW * i;
+          // prefetch the next tile of this wave (the FP32-source sweep keeps
+          // one buffer: its raw tile is twice as large)
+          constexpr bool kPrefetch = !(SRC_F32 && DOQ);
+          if constexpr (kPrefetch) {
+            if (i + 1 < myrb)
+              load_tile<SRC_F32>(rs, a, rb + kBW, lr, c0, g, buf[(i + 1) & 1]);
+            else if (ct + 1 < nct)
+              load_tile<SRC_F32>(rs, a, w, lr, c0 + kCT, g, buf[(i + 1) & 1]);
+          } else {
+            load_tile<SRC_F32>(rs, a, rb, lr, c0, g, buf[i & 1]);
+          }
+          const TileRaw<SRC_F32>& cur = buf[i & 1];
           uint4 yv[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int c = c0 + 16 * q + 8 * g;
-            const bool ok = r < a.I1 && c < a.I2;   // I2 % 8 == 0
-            const int64_t off = base + static_cast<int64_t>(r) * a.I2 + c;
             if constexpr (SRC_F32) {
-              float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
-              if (ok) {
-                const float* p = static_cast<const float*>(a.Y) + off;
-                lo = *reinterpret_cast<const float4*>(p);
-                hi = *reinterpret_cast<const float4*>(p + 4);
-              }
+              const float4 lo = cur.v[2 * q], hi = cur.v[2 * q + 1];
               yv[q].x = pack2(lo.x * down, lo.y * down);
               yv[q].y = pack2(lo.z * down, lo.w * down);
               yv[q].z = pack2(hi.x * down, hi.y * down);
               yv[q].w = pack2(hi.z * down, hi.w * down);
-              if (ok) *reinterpret_cast<uint4*>(a.Yb + off) = yv[q];
+              const int r = rb * 32 + lr, c = c0 + 16 * q + 8 * g;
+              if (r < a.I1 && c < a.I2)
+                *reinterpret_cast<uint4*>(a.Yb + base + static_cast<int64_t>(r) * a.I2 + c) =
+                    yv[q];
             } else {
-              yv[q] = make_uint4(0u, 0u, 0u, 0u);
-              if (ok)
-                yv[q] = *reinterpret_cast<const uint4*>(
-                    static_cast<const uint16_t*>(a.Y) + off);
+              yv[q] = cur.v[q];
             }
           }
 #pragma unroll
@@ -170,6 +232,13 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           }
         }
+      }
+      // the step order is (ct, i) with i < myrb: when myrb is odd the
+      // buffer parity flips at the column-tile boundary
+      if (!(SRC_F32 && DOQ) && (myrb & 1)) {
+        const TileRaw<SRC_F32> t = buf[1];
+        buf[1] = buf[0];
+        buf[0] = t;
       }
 
       if constexpr (DOQ) {
@@ -361,7 +430,11 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   a.K1 = B1 ? K1 : 0;
   a.TA = TA;
   a.TB = TB;
-  const int grid = static_cast<int>(c.A < 2048 ? c.A : 2048);
+  if (c.A > 0x7fffffff) {
+    set_error("BF16 streaming pass: too many slabs (%lld)", (long long)c.A);
+    return kErrUnsupported;
+  }
+  const int grid = static_cast<int>(c.A);   // one workgroup per slab
   ProfScope ps(stage, s);
   if (B1) return from_f32 ? launch_bf<true, true>(a, grid, s) : launch_bf<false, true>(a, grid, s);
   return from_f32 ? launch_bf<true, false>(a, grid, s) : launch_bf<false, false>(a, grid, s);
