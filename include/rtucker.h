@@ -320,6 +320,66 @@ int rt_profile_enable(int on);
  * event query fails. */
 int rt_profile_read(rt_profile* out);
 
+/*
+ * Learned FFCP initializer (no counterpart in the paper: it supplies the
+ * "initialize A" of Algorithm 1, line 1).  A 3-layer MLP maps the normalized
+ * core x = vec(G)/||G|| (d0 = prod R_n entries) to compressed factors V_n
+ * (R_n x R) of that core:
+ *   h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), y = h2 W3 + b3,
+ *   y = [vec V_1, ..., vec V_N] (row-major V_n, d3 = R sum R_n),
+ * gelu(z) = z Phi(z).  Training minimizes the CP loss of the core,
+ *   L = mean over the batch of ||G/||G|| - [[V_1..V_N]]||^2,
+ * whose factor gradient is eq. (5) applied to the core (eq. (17)).  Matrix
+ * products take BF16 operands (weights, activations, and in the backward
+ * pass the output and pre-activation gradients) with FP32 accumulation;
+ * master weights, biases and Adam moments are FP32.  Core order 3 only;
+ * R <= 32, R_n <= 32; d0, d3, hidden widths multiples of 8.
+ */
+typedef struct {
+  int32_t batch;                   /* cores per call                          */
+  int32_t N;                       /* core order (3)                          */
+  int32_t R;                       /* CP rank                                 */
+  int32_t hidden1, hidden2;        /* hidden widths                           */
+  int32_t core_dims[RT_MAX_MODES]; /* R_1..R_N                                */
+} rt_mlp_desc;
+
+/* Device buffers of the network, layer l = 0, 1, 2 with widths
+ * (d0, hidden1, hidden2, d3): W[l] d_l x d_{l+1} row-major FP32 (master),
+ * Wb[l] its BF16 copy (bit patterns, what the products read), b[l] FP32;
+ * Adam moments mW/vW/mb/vb (FP32, same shapes; training only). */
+typedef struct {
+  float* W[3];
+  float* b[3];
+  uint16_t* Wb[3];
+  float* mW[3];
+  float* vW[3];
+  float* mb[3];
+  float* vb[3];
+} rt_mlp_params;
+
+/* Workspace bytes of every rt_mlp_* call with this descriptor. */
+int rt_mlp_workspace(const rt_mlp_desc* desc, size_t* bytes);
+/* Wb[l] = bf16_rne(W[l]) (after initializing or loading W). */
+int rt_mlp_sync_bf16(const rt_mlp_desc* desc, const rt_mlp_params* params,
+                     void* stream);
+/* Inference: G (device, batch x d0 FP32 cores) -> V (device, batch x d3 FP32),
+ * the predicted factors scaled by ||G||^(1/N): FFCP's initial V_n. */
+int rt_mlp_forward(const rt_mlp_desc* desc, const rt_mlp_params* params,
+                   const float* G, float* V, void* ws, size_t ws_bytes,
+                   void* stream);
+/* Loss and gradients without updating: gW[l], gb[l] (host arrays of device
+ * FP32 buffers shaped like W[l], b[l]); loss (device, batch FP32 per-core
+ * losses; their mean is L). */
+int rt_mlp_grad(const rt_mlp_desc* desc, const rt_mlp_params* params,
+                const float* G, float* const* gW, float* const* gb, float* loss,
+                void* ws, size_t ws_bytes, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected with `step`
+ * >= 1) on the batch G; updates W, b, the moments and Wb in place; loss as
+ * in rt_mlp_grad (may be NULL). */
+int rt_mlp_train_step(const rt_mlp_desc* desc, const rt_mlp_params* params,
+                      const float* G, float lr, int32_t step, float* loss, void* ws,
+                      size_t ws_bytes, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* rt_status_string(int status);
 /* Last error message of the calling thread (static per-thread buffer). */

@@ -18,9 +18,10 @@ CP of the core):
 
 The initial factors handed to FFCP are V_n ||G||^(1/N) and A_n = U_n V_n.
 
-``bf16`` (optional) is a rounding function applied where the GPU rounds
-(weights and the activations that feed a bf16 GEMM), so a GPU comparison can
-consume the same rounded values.
+``bf16`` (optional) is a rounding function applied where the GPU rounds:
+every operand of a BF16 matrix product (weights, the activations, and in the
+backward pass the output gradient and the pre-activation gradients), so a
+GPU comparison consumes the same rounded values.
 
 Pins: tests/test_oracle_mlp.py (central finite differences of the loss vs
 the analytic backward; dL/dV equal to eq. (5) computed with the FFCP
@@ -121,15 +122,15 @@ def loss_and_backward(params, Ghats, bf16=None):
     r = (lambda a: a) if bf16 is None else bf16
     W2, W3 = r(params["W2"]), r(params["W3"])
     g = {}
-    g["W3"] = r(h2).T @ dY
+    g["W3"] = r(h2).T @ r(dY)
     g["b3"] = dY.sum(axis=0)
-    dh2 = dY @ W3.T
+    dh2 = r(dY) @ W3.T
     dz2 = dh2 * gelu_grad(z2)
-    g["W2"] = r(h1).T @ dz2
+    g["W2"] = r(h1).T @ r(dz2)
     g["b2"] = dz2.sum(axis=0)
-    dh1 = dz2 @ W2.T
+    dh1 = r(dz2) @ W2.T
     dz1 = dh1 * gelu_grad(z1)
-    g["W1"] = r(X).T @ dz1
+    g["W1"] = r(X).T @ r(dz1)
     g["b1"] = dz1.sum(axis=0)
     return total / B, g
 

@@ -13,4 +13,5 @@ from ._binding import (  # noqa: F401
     rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense, rt_stream_pass,
     stream_pass, profile_enable, profile_read,
     LIB_PATH, TUCKER_INFO_DTYPE, FFCP_INFO_DTYPE,
+    MLP, mlp_desc,
 )

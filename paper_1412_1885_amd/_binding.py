@@ -51,6 +51,16 @@ class FfcpDesc(ctypes.Structure):
 TUCKER_INFO_DTYPE = np.dtype([("normY2", "<f8"), ("normG2", "<f8"),
                               ("nonfinite", "<i4"), ("rank_deficient", "<i4"),
                               ("reserved", "<i8", (2,))])
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("N", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("hidden1", ctypes.c_int32), ("hidden2", ctypes.c_int32),
+                ("core_dims", ctypes.c_int32 * 8)]
+
+
+class MlpParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p * 3) for k in ("W", "b", "Wb", "mW", "vW", "mb", "vb")]
+
+
 FFCP_INFO_DTYPE = np.dtype([("iterations", "<i4"), ("converged", "<i4"),
                             ("ridged", "<i4"), ("reserved", "<i4"),
                             ("fit", "<f8"), ("fit_prev", "<f8")])
@@ -88,13 +98,23 @@ def lib():
         L.rt_cp_fit_workspace.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
         L.rt_cp_fit_dense.argtypes = [ctypes.POINTER(FfcpDesc), vp, ctypes.POINTER(vp),
                                       vp, vp, sz, vp, vp]
+        L.rt_mlp_workspace.argtypes = [ctypes.POINTER(MlpDesc), ctypes.POINTER(sz)]
+        L.rt_mlp_sync_bf16.argtypes = [ctypes.POINTER(MlpDesc), ctypes.POINTER(MlpParams), vp]
+        L.rt_mlp_forward.argtypes = [ctypes.POINTER(MlpDesc), ctypes.POINTER(MlpParams), vp,
+                                     vp, vp, sz, vp]
+        L.rt_mlp_grad.argtypes = [ctypes.POINTER(MlpDesc), ctypes.POINTER(MlpParams), vp,
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, sz, vp]
+        L.rt_mlp_train_step.argtypes = [ctypes.POINTER(MlpDesc), ctypes.POINTER(MlpParams),
+                                        vp, ctypes.c_float, i32, vp, vp, sz, vp]
         L.rt_status_string.argtypes = [ctypes.c_int]
         L.rt_status_string.restype = ctypes.c_char_p
         L.rt_last_error.restype = ctypes.c_char_p
         L.rt_version.restype = ctypes.c_char_p
         for f in ("rt_tucker_rand_workspace", "rt_tucker_rand", "rt_ffcp_workspace",
                   "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
-                  "rt_stream_pass", "rt_profile_enable", "rt_profile_read"):
+                  "rt_stream_pass", "rt_profile_enable", "rt_profile_read",
+                  "rt_mlp_workspace", "rt_mlp_sync_bf16", "rt_mlp_forward", "rt_mlp_grad",
+                  "rt_mlp_train_step"):
             getattr(L, f).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -383,3 +403,132 @@ rt_ffcp = ffcp
 rt_ttm = ttm
 rt_cp_fit_dense = cp_fit_dense
 rt_stream_pass = stream_pass
+
+
+# ------------------------------------------------------------ learned init
+
+def mlp_desc(batch, core_dims, R, hidden=(1024, 1024)):
+    d = MlpDesc()
+    d.batch = int(batch)
+    d.N = len(core_dims)
+    d.R = int(R)
+    d.hidden1, d.hidden2 = int(hidden[0]), int(hidden[1])
+    for n, c in enumerate(core_dims):
+        d.core_dims[n] = int(c)
+    return d
+
+
+class MLP:
+    """Device parameters of the learned FFCP initializer (rt_mlp_*): FP32
+    master weights and biases, their BF16 copies and the Adam moments, all
+    torch tensors on `device`.  Layer widths: (prod core_dims, hidden1,
+    hidden2, R * sum core_dims)."""
+
+    def __init__(self, core_dims, R, hidden=(1024, 1024), device="cuda"):
+        torch = _torch()
+        self.core_dims = [int(c) for c in core_dims]
+        self.R = int(R)
+        self.hidden = tuple(int(h) for h in hidden)
+        d0 = int(np.prod(self.core_dims))
+        d3 = self.R * sum(self.core_dims)
+        self.dims = [d0, self.hidden[0], self.hidden[1], d3]
+        f32 = dict(dtype=torch.float32, device=device)
+        self.W = [torch.zeros(self.dims[l], self.dims[l + 1], **f32) for l in range(3)]
+        self.b = [torch.zeros(self.dims[l + 1], **f32) for l in range(3)]
+        self.Wb = [torch.zeros(self.dims[l], self.dims[l + 1], dtype=torch.int16,
+                               device=device) for l in range(3)]
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.step = 0
+        self._ws = None
+
+    def params(self):
+        p = MlpParams()
+        for name in ("W", "b", "Wb", "mW", "vW", "mb", "vb"):
+            arr = getattr(p, name)
+            for l, t in enumerate(getattr(self, name)):
+                arr[l] = t.data_ptr()
+        return p
+
+    def desc(self, batch):
+        return mlp_desc(batch, self.core_dims, self.R, self.hidden)
+
+    def load(self, W, b):
+        """Set the FP32 weights (host arrays, W[l]: d_l x d_{l+1}) and refresh
+        the BF16 copies; resets the optimizer state."""
+        torch = _torch()
+        for l in range(3):
+            self.W[l].copy_(torch.from_numpy(np.ascontiguousarray(W[l], np.float32)))
+            self.b[l].copy_(torch.from_numpy(np.ascontiguousarray(b[l], np.float32)))
+        for t in self.mW + self.vW + self.mb + self.vb:
+            t.zero_()
+        self.step = 0
+        self.sync_bf16()
+
+    def sync_bf16(self, stream=None):
+        d = self.desc(1)
+        p = self.params()
+        _check(lib().rt_mlp_sync_bf16(ctypes.byref(d), ctypes.byref(p),
+                                       _stream_handle(stream)))
+
+    def _workspace(self, d, device):
+        n = ctypes.c_size_t(0)
+        _check(lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)))
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = _workspace(n.value, device)
+        return self._ws
+
+    def forward(self, G, stream=None):
+        """G: device float32 (batch, *core_dims) -> V (batch, d3) float32,
+        the predicted factors scaled by ||G||^(1/N)."""
+        torch = _torch()
+        _require_device(G, "G", torch.float32)
+        B = int(G.shape[0])
+        d = self.desc(B)
+        ws = self._workspace(d, G.device)
+        V = torch.empty(B, self.dims[3], dtype=torch.float32, device=G.device)
+        p = self.params()
+        _check(lib().rt_mlp_forward(ctypes.byref(d), ctypes.byref(p), _ptr(G), _ptr(V),
+                                    _ptr(ws), ws.numel(), _stream_handle(stream)))
+        return V
+
+    def split(self, V):
+        """Per-core list of N coefficient matrices R_n x R from forward()."""
+        out, off = [], 0
+        for c in self.core_dims:
+            out.append(V[:, off:off + c * self.R].reshape(-1, c, self.R))
+            off += c * self.R
+        return out
+
+    def grad(self, G, stream=None):
+        """(per-core losses, [gW], [gb]) without updating the parameters."""
+        torch = _torch()
+        _require_device(G, "G", torch.float32)
+        B = int(G.shape[0])
+        d = self.desc(B)
+        ws = self._workspace(d, G.device)
+        gW = [torch.empty_like(w) for w in self.W]
+        gb = [torch.empty_like(b) for b in self.b]
+        loss = torch.empty(B, dtype=torch.float32, device=G.device)
+        p = self.params()
+        _check(lib().rt_mlp_grad(ctypes.byref(d), ctypes.byref(p), _ptr(G),
+                                 _ptr_array(gW), _ptr_array(gb), _ptr(loss), _ptr(ws),
+                                 ws.numel(), _stream_handle(stream)))
+        return loss, gW, gb
+
+    def train_step(self, G, lr, stream=None):
+        """One Adam step on the batch G; returns the device per-core losses."""
+        torch = _torch()
+        _require_device(G, "G", torch.float32)
+        B = int(G.shape[0])
+        d = self.desc(B)
+        ws = self._workspace(d, G.device)
+        loss = torch.empty(B, dtype=torch.float32, device=G.device)
+        self.step += 1
+        p = self.params()
+        _check(lib().rt_mlp_train_step(ctypes.byref(d), ctypes.byref(p), _ptr(G),
+                                       float(lr), self.step, _ptr(loss), _ptr(ws),
+                                       ws.numel(), _stream_handle(stream)))
+        return loss

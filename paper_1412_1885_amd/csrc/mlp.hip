@@ -1,0 +1,628 @@
+// Learned FFCP initializer (Algorithm 1, line 1: "initialize A").
+//
+// A 3-layer MLP maps a normalized Tucker core x = vec(G)/||G|| to
+// compressed CP factors V_n (R_n x R) of that core:
+//     h1 = gelu(x W1 + b1),  h2 = gelu(h1 W2 + b2),  y = h2 W3 + b3,
+//     y = [vec V_1, ..., vec V_N]  (row-major V_n),
+// trained on the CP reconstruction loss of the core,
+//     L = ||G/||G|| - [[V_1, ..., V_N]]||^2,
+// whose gradient with respect to V_n is eq. (5) applied to the core
+// (FFCP on an orthonormal Tucker format is CP of the core, eq. (17)):
+//     dL/dV_n = 2 (V_n hadamard_{p != n} V_p^T V_p - Ghat_(n) KR_{p != n} V_p).
+// FFCP starts from V_n ||G||^(1/N) (A_n = U_n V_n).
+//
+// Every matrix product runs on v_mfma_f32_32x32x16_bf16: BF16 operands
+// (weights, activations, and in the backward pass the output and
+// pre-activation gradients), FP32 accumulation; master weights, biases and
+// Adam moments are FP32.  The core loss and its gradient are computed in
+// FP32, one workgroup per core.
+#include <cmath>
+
+#include "../../include/rtucker.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kTM = 64, kTK = 32, kLdsK = 40;   // GEMM tile (M = N = 64, K = 32)
+
+enum { kEpiStore = 0, kEpiBiasGelu = 1, kEpiBias = 2, kEpiDGelu = 3 };
+
+struct GemmArgs {
+  int M, N, K;
+  const uint16_t* A;
+  int lda;
+  const uint16_t* B;
+  int ldb;
+  float* C;          // FP32 result (ldc)
+  int ldc;
+  uint16_t* Cb;      // BF16 result (same layout), or null
+  const float* bias;  // per column n
+  const float* Zin;   // pre-activation (ldc layout) for the GELU derivative
+};
+
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
+  return cdf + z * pdf;
+}
+
+// 8 consecutive BF16 values at p (elements e0.. of a row of length `len`);
+// entries past `len` or past the matrix are zero.
+__device__ __forceinline__ uint4 load8(const uint16_t* row, int e0, int len, bool rowok) {
+  if (rowok && e0 + 8 <= len) return *reinterpret_cast<const uint4*>(row + e0);
+  uint16_t h[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = (rowok && e0 + j < len) ? row[e0 + j] : 0;
+  return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                    h[6] | (h[7] << 16));
+}
+
+__device__ __forceinline__ uint16_t half_of(const uint4& u, int j) {
+  const uint32_t w = j < 2 ? u.x : (j < 4 ? u.y : (j < 6 ? u.z : u.w));
+  return static_cast<uint16_t>(w >> (16 * (j & 1)));
+}
+
+// C (M x N) = op(A) op(B); op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k],
+// op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64 x 64 tiles staged in
+// LDS with K contiguous; four wavefronts, one 32 x 32 MFMA block each.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[kTM * kLdsK];
+  __shared__ __align__(16) uint16_t Bs[kTM * kLdsK];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1, lr = lane & 31, gq = lane >> 5;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTM;
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+    __syncthreads();
+    if (!TA) {  // A rows are m: 64 rows x 32 k, 16 bytes per thread
+      const int m = t >> 2, k8 = (t & 3) * 8;
+      const uint4 u = load8(g.A + static_cast<int64_t>(m0 + m) * g.lda, k0 + k8, g.K,
+                            m0 + m < g.M);
+      *reinterpret_cast<uint4*>(As + m * kLdsK + k8) = u;
+    } else {    // A rows are k: 32 rows x 64 m, transposed into As
+      const int k = t >> 3, m8 = (t & 7) * 8;
+      const uint4 u = load8(g.A + static_cast<int64_t>(k0 + k) * g.lda, m0 + m8, g.M,
+                            k0 + k < g.K);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[(m8 + j) * kLdsK + k] = half_of(u, j);
+    }
+    if (TB) {   // B rows are n
+      const int n = t >> 2, k8 = (t & 3) * 8;
+      const uint4 u = load8(g.B + static_cast<int64_t>(n0 + n) * g.ldb, k0 + k8, g.K,
+                            n0 + n < g.N);
+      *reinterpret_cast<uint4*>(Bs + n * kLdsK + k8) = u;
+    } else {    // B rows are k
+      const int k = t >> 3, n8 = (t & 7) * 8;
+      const uint4 u = load8(g.B + static_cast<int64_t>(k0 + k) * g.ldb, n0 + n8, g.N,
+                            k0 + k < g.K);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[(n8 + j) * kLdsK + k] = half_of(u, j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      const v8bf a = __builtin_bit_cast(
+          v8bf, *reinterpret_cast<const uint4*>(As + (wm * 32 + lr) * kLdsK + kk + 8 * gq));
+      const v8bf b = __builtin_bit_cast(
+          v8bf, *reinterpret_cast<const uint4*>(Bs + (wn * 32 + lr) * kLdsK + kk + 8 * gq));
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+  }
+  const int n = n0 + wn * 32 + lr;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
+    if (m < g.M && n < g.N) {
+      const int64_t o = static_cast<int64_t>(m) * g.ldc + n;
+      float x = acc[v];
+      if (EPI == kEpiBias || EPI == kEpiBiasGelu) x += g.bias[n];
+      if (EPI == kEpiBiasGelu) {
+        g.C[o] = x;                               // pre-activation
+        g.Cb[o] = f32_to_bf16_rne(gelu_f(x));     // activation (BF16)
+      } else if (EPI == kEpiDGelu) {
+        const float d = x * gelu_grad_f(g.Zin[o]);
+        g.C[o] = d;
+        g.Cb[o] = f32_to_bf16_rne(d);
+      } else {
+        g.C[o] = x;
+        if (g.Cb) g.Cb[o] = f32_to_bf16_rne(x);
+      }
+    }
+  }
+}
+
+template <bool TA, bool TB, int EPI>
+int gemm(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid((g.N + kTM - 1) / kTM, (g.M + kTM - 1) / kTM);
+  hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  RT_LAUNCH_CHECK("mlp gemm");
+  return kOk;
+}
+
+// Per core: ||G|| and x = bf16(G / ||G||).
+__global__ __launch_bounds__(256) void mlp_prep_kernel(const float* G, int d0,
+                                                       uint16_t* X, float* norms) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const float* g = G + static_cast<int64_t>(b) * d0;
+  double s = 0.0;
+  for (int i = t; i < d0; i += 256) s += static_cast<double>(g[i]) * g[i];
+  s = block_sum(s, red);
+  const float nrm = static_cast<float>(sqrt(s));
+  const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;
+  for (int i = t; i < d0; i += 256)
+    X[static_cast<int64_t>(b) * d0 + i] = f32_to_bf16_rne(g[i] * inv);
+  if (t == 0) norms[b] = nrm;
+}
+
+struct LossArgs {
+  const float* G;      // batch x d0 (unnormalized cores)
+  const float* norms;  // batch
+  const float* Y;      // batch x d3 (network output)
+  float* dY;           // batch x d3, dL/dy / batch
+  uint16_t* dYb;       // BF16 copy
+  float* loss;         // batch (per-core loss)
+  int d0, d3, R, B;
+  int n0, n1, n2;      // core dims (order 3)
+};
+
+// CP loss of one normalized core and its gradient (eq. (5) on the core),
+// one workgroup per core; FP32.
+__global__ __launch_bounds__(256) void mlp_loss_kernel(LossArgs a) {
+  extern __shared__ __align__(16) float sm[];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int R = a.R, n0 = a.n0, n1 = a.n1, n2 = a.n2;
+  float* gh = sm;                        // core, n0 x n1 x n2
+  float* T = gh + a.d0;                  // n0 x max(n1, n2) x R
+  float* V0 = T + n0 * (n1 > n2 ? n1 : n2) * R;
+  float* V1 = V0 + n0 * R;
+  float* V2 = V1 + n1 * R;
+  float* Gm = V2 + n2 * R;               // 3 x R x R
+  float* H = Gm + 3 * R * R;             // (n0 + n1 + n2) x R
+  __shared__ double red[4];
+  const float inv = a.norms[b] > 0.0f ? 1.0f / a.norms[b] : 0.0f;
+  const float* gb = a.G + static_cast<int64_t>(b) * a.d0;
+  const float* yb = a.Y + static_cast<int64_t>(b) * a.d3;
+  double gsq = 0.0;
+  for (int i = t; i < a.d0; i += 256) {
+    const float x = gb[i] * inv;
+    gh[i] = x;
+    gsq += static_cast<double>(x) * x;
+  }
+  for (int i = t; i < (n0 + n1 + n2) * R; i += 256) V0[i] = yb[i];
+  __syncthreads();
+  const float* Vs[3] = {V0, V1, V2};
+  const int ns[3] = {n0, n1, n2};
+  for (int l = t; l < 3 * R * R; l += 256) {
+    const int n = l / (R * R), i = (l / R) % R, j = l % R;
+    float s = 0.0f;
+    for (int q = 0; q < ns[n]; ++q) s += Vs[n][q * R + i] * Vs[n][q * R + j];
+    Gm[l] = s;
+  }
+  // T[j0, j1, r] = sum_j2 G[j0, j1, j2] V2[j2, r]
+  for (int l = t; l < n0 * n1 * R; l += 256) {
+    const int r = l % R, j01 = l / R;
+    float s = 0.0f;
+    for (int j2 = 0; j2 < n2; ++j2) s += gh[j01 * n2 + j2] * V2[j2 * R + r];
+    T[l] = s;
+  }
+  __syncthreads();
+  float* H0 = H;
+  float* H1 = H0 + n0 * R;
+  float* H2 = H1 + n1 * R;
+  for (int l = t; l < n0 * R; l += 256) {   // H0[j0, r] = sum_j1 T[j0, j1, r] V1[j1, r]
+    const int j0 = l / R, r = l % R;
+    float s = 0.0f;
+    for (int j1 = 0; j1 < n1; ++j1) s += T[(j0 * n1 + j1) * R + r] * V1[j1 * R + r];
+    H0[l] = s;
+  }
+  for (int l = t; l < n1 * R; l += 256) {   // H1[j1, r] = sum_j0 T[j0, j1, r] V0[j0, r]
+    const int j1 = l / R, r = l % R;
+    float s = 0.0f;
+    for (int j0 = 0; j0 < n0; ++j0) s += T[(j0 * n1 + j1) * R + r] * V0[j0 * R + r];
+    H1[l] = s;
+  }
+  __syncthreads();
+  // T[j0, j2, r] = sum_j1 G[j0, j1, j2] V1[j1, r]
+  for (int l = t; l < n0 * n2 * R; l += 256) {
+    const int r = l % R, j02 = l / R, j0 = j02 / n2, j2 = j02 % n2;
+    float s = 0.0f;
+    for (int j1 = 0; j1 < n1; ++j1) s += gh[(j0 * n1 + j1) * n2 + j2] * V1[j1 * R + r];
+    T[l] = s;
+  }
+  __syncthreads();
+  for (int l = t; l < n2 * R; l += 256) {   // H2[j2, r] = sum_j0 T[j0, j2, r] V0[j0, r]
+    const int j2 = l / R, r = l % R;
+    float s = 0.0f;
+    for (int j0 = 0; j0 < n0; ++j0) s += T[(j0 * n2 + j2) * R + r] * V0[j0 * R + r];
+    H2[l] = s;
+  }
+  __syncthreads();
+  // loss = ||Ghat||^2 - 2 <H0, V0> + 1^T (had Gram) 1
+  double p = 0.0;
+  for (int l = t; l < n0 * R; l += 256) p += static_cast<double>(H0[l]) * V0[l];
+  for (int l = t; l < R * R; l += 256)
+    p -= 0.5 * static_cast<double>(Gm[l]) * Gm[R * R + l] * Gm[2 * R * R + l];
+  const double gs = block_sum(gsq, red);
+  const double ps = block_sum(p, red);
+  if (t == 0) a.loss[b] = static_cast<float>(gs - 2.0 * ps);
+  // dV_n = 2 (V_n T_n - H_n) / B, T_n = hadamard of the other Grams
+  const float scale = 2.0f / static_cast<float>(a.B);
+  const float* Hs[3] = {H0, H1, H2};
+  int off = 0;
+  for (int n = 0; n < 3; ++n) {
+    const float* Ga = Gm + (n == 0 ? 1 : 0) * R * R;
+    const float* Gb2 = Gm + (n == 2 ? 1 : 2) * R * R;
+    for (int l = t; l < ns[n] * R; l += 256) {
+      const int j = l / R, r = l % R;
+      float s = 0.0f;
+      for (int q = 0; q < R; ++q) s += Vs[n][j * R + q] * (Ga[q * R + r] * Gb2[q * R + r]);
+      const float d = scale * (s - Hs[n][l]);
+      const int64_t o = static_cast<int64_t>(b) * a.d3 + off + l;
+      a.dY[o] = d;
+      a.dYb[o] = f32_to_bf16_rne(d);
+    }
+    off += ns[n] * R;
+  }
+}
+
+// db[n] = sum_b dZ[b][n]
+__global__ void colsum_kernel(const float* dZ, int B, int N, float* db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += dZ[static_cast<int64_t>(b) * N + n];
+  db[n] = s;
+}
+
+// Adam (Kingma & Ba, bias-corrected) on FP32 master values; optional BF16
+// copy of the updated values.
+__global__ void adam_kernel(float* w, float* m, float* v, const float* g, int64_t n,
+                            float lr, float c1, float c2, uint16_t* wb) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float wi = w[i] - lr * mh / (sqrtf(vh) + 1e-8f);
+  w[i] = wi;
+  if (wb) wb[i] = f32_to_bf16_rne(wi);
+}
+
+__global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f32_to_bf16_rne(x[i]);
+}
+
+// V_out[b][i] = y[b][i] * ||G_b||^(1/N)
+__global__ void scale_out_kernel(const float* Y, const float* norms, int d3, int N,
+                                 int B, float* V) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(B) * d3) return;
+  const int b = static_cast<int>(i / d3);
+  V[i] = Y[i] * powf(norms[b], 1.0f / static_cast<float>(N));
+}
+
+struct MlpDims {
+  int B, N, R, d0, d1, d2, d3;
+  int cd[RT_MAX_MODES];
+};
+
+int mlp_dims(const rt_mlp_desc* d, MlpDims* m) {
+  if (!d) {
+    set_error("desc is NULL");
+    return kErrInvalid;
+  }
+  if (d->N != 3) {
+    set_error("learned initializer: core order %d (order 3 only)", d->N);
+    return kErrUnsupported;
+  }
+  if (d->batch < 1 || d->R < 1 || d->R > 32 || d->hidden1 < 8 || d->hidden2 < 8 ||
+      d->hidden1 % 8 || d->hidden2 % 8) {
+    set_error("learned initializer: batch %d, R %d, hidden %d/%d invalid", d->batch, d->R,
+              d->hidden1, d->hidden2);
+    return kErrInvalid;
+  }
+  m->B = d->batch;
+  m->N = d->N;
+  m->R = d->R;
+  m->d0 = 1;
+  int sum = 0;
+  for (int n = 0; n < d->N; ++n) {
+    if (d->core_dims[n] < 1 || d->core_dims[n] > 32) {
+      set_error("learned initializer: core dim %d outside 1..32", d->core_dims[n]);
+      return kErrInvalid;
+    }
+    m->cd[n] = d->core_dims[n];
+    m->d0 *= d->core_dims[n];
+    sum += d->core_dims[n];
+  }
+  m->d1 = d->hidden1;
+  m->d2 = d->hidden2;
+  m->d3 = d->R * sum;
+  if (m->d0 % 8 || m->d3 % 8) {
+    set_error("learned initializer: input %d and output %d widths must be multiples of 8",
+              m->d0, m->d3);
+    return kErrUnsupported;
+  }
+  return kOk;
+}
+
+size_t loss_lds_bytes(const MlpDims& m) {
+  const int n0 = m.cd[0], n1 = m.cd[1], n2 = m.cd[2], R = m.R;
+  const int64_t f = m.d0 + static_cast<int64_t>(n0) * (n1 > n2 ? n1 : n2) * R +
+                    static_cast<int64_t>(n0 + n1 + n2) * R + 3 * R * R +
+                    static_cast<int64_t>(n0 + n1 + n2) * R;
+  return static_cast<size_t>(f) * 4;
+}
+
+struct MlpPlan {
+  uint16_t* X;
+  float* norms;
+  float *Z1, *Z2, *Yo, *dY, *dZ1, *dZ2, *loss;
+  uint16_t *H1, *H2, *dYb, *dZ1b, *dZ2b;
+  float* gW[3];
+  float* gb[3];
+  size_t plan(const MlpDims& m, void* ws, bool grads) {
+    Arena ar(ws);
+    const int64_t B = m.B;
+    X = ar.take<uint16_t>(B * m.d0);
+    norms = ar.take<float>(B);
+    Z1 = ar.take<float>(B * m.d1);
+    Z2 = ar.take<float>(B * m.d2);
+    H1 = ar.take<uint16_t>(B * m.d1);
+    H2 = ar.take<uint16_t>(B * m.d2);
+    Yo = ar.take<float>(B * m.d3);
+    dY = ar.take<float>(B * m.d3);
+    dYb = ar.take<uint16_t>(B * m.d3);
+    dZ1 = ar.take<float>(B * m.d1);
+    dZ2 = ar.take<float>(B * m.d2);
+    dZ1b = ar.take<uint16_t>(B * m.d1);
+    dZ2b = ar.take<uint16_t>(B * m.d2);
+    loss = ar.take<float>(B);
+    const int dims[4] = {m.d0, m.d1, m.d2, m.d3};
+    for (int l = 0; l < 3; ++l) {
+      gW[l] = grads ? ar.take<float>(static_cast<int64_t>(dims[l]) * dims[l + 1]) : nullptr;
+      gb[l] = grads ? ar.take<float>(dims[l + 1]) : nullptr;
+    }
+    return ar.need;
+  }
+};
+
+int check_params(const rt_mlp_params* p, bool train) {
+  if (!p) {
+    set_error("params is NULL");
+    return kErrInvalid;
+  }
+  for (int l = 0; l < 3; ++l) {
+    if (!p->Wb[l] || !p->b[l] || (train && (!p->W[l] || !p->mW[l] || !p->vW[l] ||
+                                           !p->mb[l] || !p->vb[l]))) {
+      set_error("params: layer %d pointers missing", l);
+      return kErrInvalid;
+    }
+  }
+  return kOk;
+}
+
+// Forward pass on the workspace buffers (X and norms filled first).
+int forward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& P,
+            hipStream_t s) {
+  hipLaunchKernelGGL(mlp_prep_kernel, dim3(m.B), dim3(256), 0, s, G, m.d0, P.X, P.norms);
+  RT_LAUNCH_CHECK("mlp prep");
+  GemmArgs g{};
+  g.M = m.B; g.N = m.d1; g.K = m.d0;
+  g.A = P.X; g.lda = m.d0; g.B = p->Wb[0]; g.ldb = m.d1;
+  g.C = P.Z1; g.ldc = m.d1; g.Cb = P.H1; g.bias = p->b[0];
+  RT_TRY((gemm<false, false, kEpiBiasGelu>(g, s)));
+  g.N = m.d2; g.K = m.d1; g.A = P.H1; g.lda = m.d1; g.B = p->Wb[1]; g.ldb = m.d2;
+  g.C = P.Z2; g.ldc = m.d2; g.Cb = P.H2; g.bias = p->b[1];
+  RT_TRY((gemm<false, false, kEpiBiasGelu>(g, s)));
+  g.N = m.d3; g.K = m.d2; g.A = P.H2; g.lda = m.d2; g.B = p->Wb[2]; g.ldb = m.d3;
+  g.C = P.Yo; g.ldc = m.d3; g.Cb = nullptr; g.bias = p->b[2];
+  RT_TRY((gemm<false, false, kEpiBias>(g, s)));
+  return kOk;
+}
+
+// Loss and gradients into P.gW / P.gb (FP32).
+int backward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& P,
+             float* const* gW, float* const* gb, hipStream_t s) {
+  LossArgs la{};
+  la.G = G; la.norms = P.norms; la.Y = P.Yo; la.dY = P.dY; la.dYb = P.dYb;
+  la.loss = P.loss; la.d0 = m.d0; la.d3 = m.d3; la.R = m.R; la.B = m.B;
+  la.n0 = m.cd[0]; la.n1 = m.cd[1]; la.n2 = m.cd[2];
+  const size_t lds = loss_lds_bytes(m);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_loss_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return hip_fail(e, "mlp loss LDS attribute");
+  }
+  hipLaunchKernelGGL(mlp_loss_kernel, dim3(m.B), dim3(256), lds, s, la);
+  RT_LAUNCH_CHECK("mlp loss");
+  GemmArgs g{};
+  // layer 3: gW3 = H2^T dY, gb3 = colsum(dY), dZ2 = (dY W3^T) * gelu'(Z2)
+  g.M = m.d2; g.N = m.d3; g.K = m.B;
+  g.A = P.H2; g.lda = m.d2; g.B = P.dYb; g.ldb = m.d3; g.C = gW[2]; g.ldc = m.d3;
+  RT_TRY((gemm<true, false, kEpiStore>(g, s)));
+  hipLaunchKernelGGL(colsum_kernel, dim3((m.d3 + 255) / 256), dim3(256), 0, s, P.dY, m.B,
+                     m.d3, gb[2]);
+  RT_LAUNCH_CHECK("mlp colsum");
+  g = GemmArgs{};
+  g.M = m.B; g.N = m.d2; g.K = m.d3;
+  g.A = P.dYb; g.lda = m.d3; g.B = p->Wb[2]; g.ldb = m.d3; g.C = P.dZ2; g.ldc = m.d2;
+  g.Cb = P.dZ2b; g.Zin = P.Z2;
+  RT_TRY((gemm<false, true, kEpiDGelu>(g, s)));
+  // layer 2
+  g = GemmArgs{};
+  g.M = m.d1; g.N = m.d2; g.K = m.B;
+  g.A = P.H1; g.lda = m.d1; g.B = P.dZ2b; g.ldb = m.d2; g.C = gW[1]; g.ldc = m.d2;
+  RT_TRY((gemm<true, false, kEpiStore>(g, s)));
+  hipLaunchKernelGGL(colsum_kernel, dim3((m.d2 + 255) / 256), dim3(256), 0, s, P.dZ2, m.B,
+                     m.d2, gb[1]);
+  RT_LAUNCH_CHECK("mlp colsum");
+  g = GemmArgs{};
+  g.M = m.B; g.N = m.d1; g.K = m.d2;
+  g.A = P.dZ2b; g.lda = m.d2; g.B = p->Wb[1]; g.ldb = m.d2; g.C = P.dZ1; g.ldc = m.d1;
+  g.Cb = P.dZ1b; g.Zin = P.Z1;
+  RT_TRY((gemm<false, true, kEpiDGelu>(g, s)));
+  // layer 1
+  g = GemmArgs{};
+  g.M = m.d0; g.N = m.d1; g.K = m.B;
+  g.A = P.X; g.lda = m.d0; g.B = P.dZ1b; g.ldb = m.d1; g.C = gW[0]; g.ldc = m.d1;
+  RT_TRY((gemm<true, false, kEpiStore>(g, s)));
+  hipLaunchKernelGGL(colsum_kernel, dim3((m.d1 + 255) / 256), dim3(256), 0, s, P.dZ1, m.B,
+                     m.d1, gb[0]);
+  RT_LAUNCH_CHECK("mlp colsum");
+  return kOk;
+}
+
+int mlp_setup(const rt_mlp_desc* desc, const rt_mlp_params* p, const void* G, void* ws,
+              size_t ws_bytes, bool train, MlpDims* m, MlpPlan* P) {
+  RT_TRY(mlp_dims(desc, m));
+  RT_TRY(check_params(p, train));
+  if (!G || !ws) {
+    set_error("G and ws must not be NULL");
+    return kErrInvalid;
+  }
+  const size_t need = P->plan(*m, ws, train);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return kErrWorkspace;
+  }
+  if (loss_lds_bytes(*m) > 160 * 1024 - 64) {
+    set_error("learned initializer: core too large for one workgroup");
+    return kErrUnsupported;
+  }
+  return kOk;
+}
+
+}  // namespace
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+int rt_mlp_workspace(const rt_mlp_desc* desc, size_t* bytes) {
+  MlpDims m;
+  RT_TRY(mlp_dims(desc, &m));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return kErrInvalid;
+  }
+  MlpPlan P;
+  *bytes = P.plan(m, nullptr, true);
+  return kOk;
+}
+
+int rt_mlp_sync_bf16(const rt_mlp_desc* desc, const rt_mlp_params* p, void* stream) {
+  MlpDims m;
+  RT_TRY(mlp_dims(desc, &m));
+  RT_TRY(check_params(p, false));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dims[4] = {m.d0, m.d1, m.d2, m.d3};
+  for (int l = 0; l < 3; ++l) {
+    if (!p->W[l]) {
+      set_error("params: W[%d] missing", l);
+      return kErrInvalid;
+    }
+    const int64_t n = static_cast<int64_t>(dims[l]) * dims[l + 1];
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p->W[l],
+                       p->Wb[l], n);
+    RT_LAUNCH_CHECK("mlp bf16 copy");
+  }
+  return kOk;
+}
+
+int rt_mlp_forward(const rt_mlp_desc* desc, const rt_mlp_params* p, const float* G,
+                   float* V, void* ws, size_t ws_bytes, void* stream) {
+  MlpDims m;
+  MlpPlan P;
+  RT_TRY(mlp_setup(desc, p, G, ws, ws_bytes, false, &m, &P));
+  if (!V) {
+    set_error("V is NULL");
+    return kErrInvalid;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RT_TRY(forward(m, p, G, P, s));
+  const int64_t n = static_cast<int64_t>(m.B) * m.d3;
+  hipLaunchKernelGGL(scale_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, P.Yo,
+                     P.norms, m.d3, m.N, m.B, V);
+  RT_LAUNCH_CHECK("mlp scale");
+  return kOk;
+}
+
+int rt_mlp_grad(const rt_mlp_desc* desc, const rt_mlp_params* p, const float* G,
+                float* const* gW, float* const* gb, float* loss, void* ws,
+                size_t ws_bytes, void* stream) {
+  MlpDims m;
+  MlpPlan P;
+  RT_TRY(mlp_setup(desc, p, G, ws, ws_bytes, false, &m, &P));
+  if (!gW || !gb || !loss) {
+    set_error("gW, gb and loss must not be NULL");
+    return kErrInvalid;
+  }
+  for (int l = 0; l < 3; ++l)
+    if (!gW[l] || !gb[l]) {
+      set_error("gW[%d] / gb[%d] is NULL", l, l);
+      return kErrInvalid;
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RT_TRY(forward(m, p, G, P, s));
+  RT_TRY(backward(m, p, G, P, gW, gb, s));
+  if (hipMemcpyAsync(loss, P.loss, m.B * sizeof(float), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess)
+    return hip_fail(hipGetLastError(), "loss copy");
+  return kOk;
+}
+
+int rt_mlp_train_step(const rt_mlp_desc* desc, const rt_mlp_params* p, const float* G,
+                      float lr, int32_t step, float* loss, void* ws, size_t ws_bytes,
+                      void* stream) {
+  MlpDims m;
+  MlpPlan P;
+  RT_TRY(mlp_setup(desc, p, G, ws, ws_bytes, true, &m, &P));
+  if (step < 1 || !(lr > 0.0f)) {
+    set_error("train step: step %d must be >= 1 and lr > 0", step);
+    return kErrInvalid;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RT_TRY(forward(m, p, G, P, s));
+  RT_TRY(backward(m, p, G, P, P.gW, P.gb, s));
+  const float c1 = 1.0f - powf(0.9f, static_cast<float>(step));
+  const float c2 = 1.0f - powf(0.999f, static_cast<float>(step));
+  const int dims[4] = {m.d0, m.d1, m.d2, m.d3};
+  for (int l = 0; l < 3; ++l) {
+    const int64_t nw = static_cast<int64_t>(dims[l]) * dims[l + 1];
+    hipLaunchKernelGGL(adam_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, p->W[l],
+                       p->mW[l], p->vW[l], P.gW[l], nw, lr, c1, c2, p->Wb[l]);
+    RT_LAUNCH_CHECK("mlp adam");
+    hipLaunchKernelGGL(adam_kernel, dim3((dims[l + 1] + 255) / 256), dim3(256), 0, s,
+                       p->b[l], p->mb[l], p->vb[l], P.gb[l],
+                       static_cast<int64_t>(dims[l + 1]), lr, c1, c2,
+                       static_cast<uint16_t*>(nullptr));
+    RT_LAUNCH_CHECK("mlp adam");
+  }
+  if (loss && hipMemcpyAsync(loss, P.loss, m.B * sizeof(float), hipMemcpyDeviceToDevice,
+                             s) != hipSuccess)
+    return hip_fail(hipGetLastError(), "loss copy");
+  return kOk;
+}
+
+}  // extern "C"

@@ -227,3 +227,15 @@ def cp_congruent_device(case, dims, R, c_lo, c_hi, snr_db, ranks_tilde,
     del E
     return {"Y": Y, "A_true": A, "omegas": om, "omega_tildes": omt,
             "init_rng": g["init"]}
+
+
+def mlp_weights(case, dims):
+    """He-initialized weights of the learned initializer: W_l ~ N(0, 2/fan_in)
+    (d_l x d_{l+1}), zero biases; FP32 values (returned as float32 arrays)."""
+    rng = rngs(case)["init"]
+    W, b = [], []
+    for l in range(len(dims) - 1):
+        W.append((rng.standard_normal((dims[l], dims[l + 1])) *
+                  np.sqrt(2.0 / dims[l])).astype(np.float32))
+        b.append(np.zeros(dims[l + 1], dtype=np.float32))
+    return W, b

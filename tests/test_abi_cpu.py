@@ -129,3 +129,15 @@ def test_workspace_too_small_reported():
     rc = P.lib().rt_tucker_rand(ctypes.byref(d), vp(4096), arr, arr, vp(8192), 16,
                                 arr, vp(12288), None, None, None, None)
     assert rc == -3 and "workspace" in P.last_error()
+
+
+def test_mlp_descriptor_validation():
+    n = ctypes.c_size_t(0)
+    d = P.mlp_desc(16, (20, 20, 20), 20)
+    assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == 0 and n.value > 0
+    d = P.mlp_desc(16, (20, 20, 20, 20), 20)          # order 4
+    assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == -2
+    d = P.mlp_desc(16, (20, 20, 20), 40)              # R > 32
+    assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1
+    d = P.mlp_desc(16, (20, 20, 20), 20, hidden=(100, 64))   # width not a multiple of 8
+    assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1

@@ -1,0 +1,116 @@
+"""GPU parity of the learned FFCP initializer (rt_mlp_*) against the FP64
+oracle (oracle/mlp.py), with the oracle rounding to BF16 exactly where the
+GPU does (every operand of a matrix product).
+
+Tolerances: the remaining differences are FP32 accumulation and FP32 vs FP64
+pre-activations that occasionally round to a neighbouring BF16 value (one
+BF16 ulp, 2^-8 relative, on a fraction ~1e-4 of the entries), so whole
+tensors agree to a relative Frobenius error of 2e-3.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1412_1885_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.lib()
+    return P
+
+
+def bf16_round(x):
+    """Round to the nearest BF16 (ties to even), through FP32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cores(case, B, dims):
+    rng = synth.rngs(case)["factors"]
+    return rng.standard_normal((B,) + tuple(dims)).astype(np.float32)
+
+
+def setup(P, case, B, core_dims, R, hidden):
+    G = cores(case, B, core_dims)
+    net = P.MLP(core_dims, R, hidden)
+    W, b = synth.mlp_weights(case, net.dims)
+    net.load(W, b)
+    params = {f"W{l + 1}": W[l].astype(np.float64) for l in range(3)}
+    params.update({f"b{l + 1}": b[l].astype(np.float64) for l in range(3)})
+    return G, net, params
+
+
+def normalized(G):
+    G = G.astype(np.float64)
+    n = np.sqrt((G.reshape(G.shape[0], -1) ** 2).sum(axis=1))
+    return G / n.reshape((-1,) + (1,) * (G.ndim - 1)), n
+
+
+@pytest.mark.parametrize("hidden", [(128, 96), (1024, 1024)])
+def test_mlp_forward_matches_oracle(P, hidden):
+    G, net, params = setup(P, 501, 12, (20, 20, 20), 20, hidden)
+    V = net.forward(torch.from_numpy(G).cuda()).cpu().numpy().astype(np.float64)
+    Gh, nrm = normalized(G)
+    Y, _ = M.forward(params, Gh.reshape(12, -1), bf16=bf16_round)
+    want = Y * (nrm ** (1.0 / 3.0))[:, None]
+    assert rel(V, want) <= 2e-3
+
+
+def test_mlp_gradients_match_oracle(P):
+    B, cd, R = 16, (20, 20, 20), 20
+    G, net, params = setup(P, 502, B, cd, R, (128, 96))
+    loss, gW, gb = net.grad(torch.from_numpy(G).cuda())
+    Gh, _ = normalized(G)
+    ref_loss, g = M.loss_and_backward(params, Gh, bf16=bf16_round)
+    assert abs(float(loss.mean()) - ref_loss) <= 1e-4 * abs(ref_loss)
+    for l in range(3):
+        assert rel(gW[l].cpu().numpy(), g[f"W{l + 1}"]) <= 2e-3, ("W", l)
+        assert rel(gb[l].cpu().numpy(), g[f"b{l + 1}"]) <= 2e-3, ("b", l)
+
+
+def test_mlp_loss_is_cp_objective_of_the_core(P):
+    """Per-core loss equals ||Ghat - [[V]]||^2 of the network's own output
+    (dense reconstruction in FP64 from the returned factors)."""
+    B, cd, R = 6, (8, 9, 10), 8
+    G, net, params = setup(P, 503, B, cd, R, (64, 64))
+    loss, _, _ = net.grad(torch.from_numpy(G).cuda())
+    V = net.forward(torch.from_numpy(G).cuda())
+    Gh, nrm = normalized(G)
+    for b, Vs in enumerate(zip(*[v.cpu().numpy() for v in net.split(V)])):
+        Vs = [v.astype(np.float64) / nrm[b] ** (1.0 / 3.0) for v in Vs]
+        rec = np.einsum("ir,jr,kr->ijk", *Vs)
+        assert abs(float(loss[b]) - np.sum((Gh[b] - rec) ** 2)) <= \
+            1e-4 * np.sum(Gh[b] ** 2)
+
+
+def test_mlp_adam_step_matches_oracle(P):
+    B, cd, R, lr = 8, (20, 20, 20), 20, 1e-3
+    G, net, params = setup(P, 504, B, cd, R, (128, 96))
+    net.train_step(torch.from_numpy(G).cuda(), lr)
+    Gh, _ = normalized(G)
+    _, g = M.loss_and_backward(params, Gh, bf16=bf16_round)
+    state = {}
+    new = M.adam_step(dict(params), g, state, lr)
+    for l in range(3):
+        w = net.W[l].cpu().numpy().astype(np.float64)
+        # first Adam step moves each weight by about lr * sign(g): compare the
+        # update, entries whose gradient is tiny excluded by the tolerance
+        dw, dref = w - params[f"W{l + 1}"], new[f"W{l + 1}"] - params[f"W{l + 1}"]
+        assert np.mean(np.abs(dw - dref) <= 0.05 * lr) >= 0.99, l
+    w0 = net.W[0].cpu().numpy()
+    u = w0.view(np.uint32).astype(np.uint64)
+    want = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+    assert np.array_equal(net.Wb[0].cpu().numpy().view(np.uint16), want)
