@@ -181,8 +181,13 @@ typedef enum {
 
 typedef enum {
   RT_INIT_USER = 0,  /* A_init given                                      */
-  RT_INIT_HOSVD = 1  /* V_n = top-R eigenvectors of G_(n) G_(n)^T, padded
+  RT_INIT_HOSVD = 1, /* V_n = top-R eigenvectors of G_(n) G_(n)^T, padded
                         with the caller's `pad` columns when R > R_n      */
+  RT_INIT_COEFF = 2, /* A_init holds N device FP32 R_n x R coefficient
+                        matrices V_n (e.g. rt_mlp_forward): A_n = U_n V_n  */
+  RT_INIT_COEFF_GUARDED = 3 /* as RT_INIT_COEFF, but the HOSVD start is
+                        built too and the one with the higher initial fit
+                        is used (ALS without l1; other rules: as COEFF)   */
 } rt_init;
 
 /*
@@ -218,7 +223,8 @@ typedef struct {
   int32_t converged;  /* 1 if the tolerance test stopped the loop        */
   int32_t ridged;     /* 1 if a Cholesky failed and the ridge
                          1e-12 tr(T)/R was added                         */
-  int32_t reserved;
+  int32_t init_used;  /* RT_INIT_COEFF_GUARDED: 1 if the caller's start
+                         was kept, 0 if the HOSVD start was; else 0      */
   double fit;         /* final Fit = 1 - ||Yt - Yhat|| / ||Yt||           */
   double fit_prev;    /* fit of the previous iteration                   */
 } rt_ffcp_info;
@@ -239,7 +245,9 @@ int rt_ffcp_workspace(const rt_ffcp_desc* desc, size_t* bytes);
  *
  *   U        host array of N device FP32 matrices I_n x R_n.
  *   G        device FP32 core R_1 x ... x R_N.
- *   A_init   host array of N device FP32 I_n x R (RT_INIT_USER), else NULL.
+ *   A_init   host array of N device FP32 I_n x R (RT_INIT_USER), or
+ *            R_n x R coefficient matrices (RT_INIT_COEFF[_GUARDED]), else
+ *            NULL.
  *   pad      RT_INIT_HOSVD with R > R_n: host array of N device FP32
  *            R_n x (R - R_n) matrices (entries for modes with R <= R_n are
  *            ignored and may be NULL); NULL otherwise.

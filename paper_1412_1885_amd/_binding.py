@@ -19,7 +19,9 @@ RT_MAX_SKETCH = 64
 RT_F32, RT_BF16_MIXED, RT_F64 = 0, 1, 2
 RT_FLAG_NO_TRUNCATE, RT_FLAG_BF16_INPUT, RT_FLAG_GAUSS_SEIDEL = 1, 2, 4
 RT_ALS, RT_HALS, RT_MU = 0, 1, 2
-RT_INIT_USER, RT_INIT_HOSVD = 0, 1
+RT_INIT_USER, RT_INIT_HOSVD, RT_INIT_COEFF, RT_INIT_COEFF_GUARDED = 0, 1, 2, 3
+INITS = {"user": RT_INIT_USER, "hosvd": RT_INIT_HOSVD, "coeff": RT_INIT_COEFF,
+         "coeff_guarded": RT_INIT_COEFF_GUARDED}
 PRECISIONS = {"f32": RT_F32, "bf16": RT_BF16_MIXED, "f64": RT_F64}
 UPDATES = {"als": RT_ALS, "hals": RT_HALS, "mu": RT_MU}
 
@@ -62,7 +64,7 @@ class MlpParams(ctypes.Structure):
 
 
 FFCP_INFO_DTYPE = np.dtype([("iterations", "<i4"), ("converged", "<i4"),
-                            ("ridged", "<i4"), ("reserved", "<i4"),
+                            ("ridged", "<i4"), ("init_used", "<i4"),
                             ("fit", "<f8"), ("fit_prev", "<f8")])
 
 _lib_handle = None
@@ -264,7 +266,7 @@ def ffcp_desc(dims, ranks, R, update="als", init="user", max_it=1000, tol=1e-6,
     d.N = len(dims)
     d.R = int(R)
     d.update = UPDATES[update]
-    d.init = RT_INIT_USER if init == "user" else RT_INIT_HOSVD
+    d.init = INITS[init]
     d.max_it = int(max_it)
     d.tol = float(tol)
     d.l1 = float(l1)
@@ -286,8 +288,10 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
          stream=None, sync=True):
     """rt_ffcp on a Tucker format.  U: N device float32 I_n x R_n; G: device
     float32 core.  A_init (list of device float32 I_n x R) selects the user
-    init; otherwise init="hosvd" (pad: list of R_n x (R - R_n) matrices for
-    modes with R > R_n)."""
+    init; init="coeff" / "coeff_guarded" takes A_init as R_n x R coefficient
+    matrices (A_n = U_n V_n; the guarded form keeps them only if their
+    initial fit is at least the HOSVD start's); init="hosvd" (pad: list of
+    R_n x (R - R_n) matrices for modes with R > R_n)."""
     torch = _torch()
     N = len(U)
     dims = [int(u.shape[0]) for u in U]

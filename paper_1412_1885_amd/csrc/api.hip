@@ -451,7 +451,7 @@ int validate_ffcp(const rt_ffcp_desc* d) {
     set_error("unknown update rule %d", d->update);
     return kErrInvalid;
   }
-  if (d->init < 0 || d->init > 1) {
+  if (d->init < 0 || d->init > 3) {
     set_error("unknown init %d", d->init);
     return kErrInvalid;
   }
@@ -493,6 +493,7 @@ struct FfcpPlan {
   double* W2;
   double* scal;
   double* Vinit[RT_MAX_MODES];
+  double* Valt[RT_MAX_MODES];
   double* hgram[RT_MAX_MODES];
   size_t plan(const rt_ffcp_desc* d, void* ws) {
     Arena ar(ws);
@@ -515,6 +516,7 @@ struct FfcpPlan {
       Gram[n] = ar.take<double>(R * R);
       U64[n] = ar.take<double>(d->dims[n] * d->ranks[n]);
       Vinit[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * R);
+      Valt[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * R);
       hgram[n] = ar.take<double>(static_cast<int64_t>(d->ranks[n]) * d->ranks[n]);
     }
     G64 = ar.take<double>(core);
@@ -637,13 +639,16 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
     RT_TRY(check_ptr(U[n], "U[n]"));
     RT_TRY(check_ptr(A[n], "A[n]"));
   }
-  if (desc->init == RT_INIT_USER) {
+  const bool coeff = desc->init == RT_INIT_COEFF || desc->init == RT_INIT_COEFF_GUARDED;
+  const bool hosvd = desc->init == RT_INIT_HOSVD || desc->init == RT_INIT_COEFF_GUARDED;
+  if (desc->init == RT_INIT_USER || coeff) {
     if (!A_init) {
-      set_error("A_init is NULL with RT_INIT_USER");
+      set_error("A_init is NULL with RT_INIT_USER / RT_INIT_COEFF");
       return kErrInvalid;
     }
     for (int n = 0; n < N; ++n) RT_TRY(check_ptr(A_init[n], "A_init[n]"));
-  } else {
+  }
+  if (hosvd) {
     for (int n = 0; n < N; ++n) {
       if (R > desc->ranks[n]) {
         if (!pad || !pad[n]) {
@@ -688,6 +693,7 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
     a.U64[n] = P.U64[n];
     a.A_init[n] = desc->init == RT_INIT_USER ? A_init[n] : nullptr;
     a.V_init[n] = P.Vinit[n];
+    a.V_alt[n] = desc->init == RT_INIT_COEFF_GUARDED ? P.Valt[n] : nullptr;
   }
   a.G64 = P.G64;
   a.H = P.H;
@@ -696,9 +702,17 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
   a.W1 = P.W1;
   a.W2 = P.W2;
   a.scal = P.scal;
-  if (desc->init == RT_INIT_HOSVD) {
+  if (coeff) {
+    // the caller's coefficient matrices (FP32 R_n x R) as the FP64 start
+    for (int n = 0; n < N; ++n)
+      RT_TRY((launch_convert<float, double>(
+          A_init[n], P.Vinit[n], static_cast<int64_t>(desc->ranks[n]) * R, s)));
+  }
+  if (hosvd) {
     // V_n = top-min(R, R_n) eigenvectors of G_(n) G_(n)^T, padded with the
     // caller's columns when R > R_n; the kernel then forms A_n = U_n V_n.
+    // With the guarded start this is the alternative the kernel compares.
+    double* const* dstV = desc->init == RT_INIT_COEFF_GUARDED ? P.Valt : P.Vinit;
     int64_t core = 1;
     for (int n = 0; n < N; ++n) core *= desc->ranks[n];
     int64_t Apre = 1;
@@ -720,7 +734,7 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
       one.evals[0] = nullptr;
       RT_TRY(launch_eig(one, s));
       hipLaunchKernelGGL(hosvd_pad_kernel, dim3((Rn * R + 255) / 256), dim3(256),
-                         0, s, P.H, (k < R) ? pad[n] : nullptr, P.Vinit[n], Rn,
+                         0, s, P.H, (k < R) ? pad[n] : nullptr, dstV[n], Rn,
                          k, R);
       RT_LAUNCH_CHECK("hosvd pad");
     }

@@ -30,7 +30,7 @@ constexpr int kFWaves = kFThreads / 64;
 constexpr int kRMax = 64;
 
 struct InfoDev {
-  int32_t iterations, converged, ridged, reserved;
+  int32_t iterations, converged, ridged, init_used;
   double fit, fit_prev;
 };
 
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
     info->iterations = it;
     info->converged = converged;
     info->ridged = ridged;
-    info->reserved = 0;
+    info->init_used = 0;
     info->fit = fit;
     info->fit_prev = fit_prev;
   }

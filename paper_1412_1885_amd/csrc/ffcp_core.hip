@@ -30,7 +30,7 @@ namespace {
 constexpr int kLdsMax = 160 * 1024;
 
 struct InfoDev {
-  int32_t iterations, converged, ridged, reserved;
+  int32_t iterations, converged, ridged, init_used;
   double fit, fit_prev;
 };
 
@@ -210,18 +210,23 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
       cross_rows<NT>(a.U[n], Rn, a.A_init[n], R, a.I[n], D(c.oV[n]), RP, stage);
       cross_rows<NT>(a.A_init[n], R, a.A_init[n], R, a.I[n], D(c.oGram[n]), RP,
                      stage);
-    } else {
-      // HOSVD (or caller) coefficients: A_n = U_n V_init
+    }
+  }
+  __syncthreads();
+  // coefficient starts (HOSVD or the caller's): A_n = U_n Vc_n
+  auto load_coeffs = [&](const double* const* Vc) {
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
       double* Vh = D(c.oVh[n]);
-      for (int l = t; l < Rn * R; l += NT) Vh[(l / R) * RP + l % R] = a.V_init[n][l];
+      for (int l = t; l < Rn * R; l += NT) Vh[(l / R) * RP + l % R] = Vc[n][l];
       __syncthreads();
       small_mm<NT>(D(c.oM[n]), Rn, false, Vh, RP, D(c.oV[n]), RP, Rn, Rn, R);
       __syncthreads();
       small_mm<NT>(Vh, RP, true, D(c.oV[n]), RP, D(c.oGram[n]), RP, R, Rn, R);
       __syncthreads();
     }
-  }
-  __syncthreads();
+  };
+  if (!a.A_init[0]) load_coeffs(a.V_init);
 
   // ||Yt||^2 = <G, G x_1 M_1 ... x_N M_N> unless given (global scratch)
   double nrm2 = a.normY2;
@@ -266,122 +271,166 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
   double* Pm = D(c.oP);
   double* G0 = D(c.oG0);
   double* Hlast = D(c.oH);
+
+  // H_n = G_(n) [KR_{p != n} V_p] into Hlast (returns it)
+  auto mttkrp = [&](int n) -> const double* {
+    // H = G_(n) [KR_{p != n} V_p]: contract the last remaining mode != n
+    // (schedule precomputed on the host: mode, leading and trailing sizes).
+    // The first step of modes 0..N-2 contracts mode N-1 with V_{N-1},
+    // which only mode N-1 updates: it is computed once per iteration (X1).
+    const double* src = nullptr;
+    for (int st = 0; st < N - 1; ++st) {
+      const int m = c.sm[n][st];
+      const int Apre = c.sApre[n][st], Cpost = c.sCpost[n][st];
+      const bool last = st == N - 2;
+      const int Rm = a.Rn[m];
+      const double* Vm = D(c.oV[m]);
+      double* dst = last ? Hlast : (st == 0 ? X1 : (((st - 1) & 1) ? W2 : W1));
+      const bool reuse = st == 0 && !last && n > 0 && n < N - 1;
+      if (!reuse && src == nullptr) {
+        // first step from the FP32 core: 4 consecutive (a, c) x 4 r per item
+        const int nac = Apre * Cpost;
+        const int total = ((nac + 3) / 4) * R4;
+        for (int item = t; item < total; item += NT) {
+          const int rq = item % R4;
+          const int ab = item / R4;
+          int off[4];
+          bool val[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ac = 4 * ab + u;
+            val[u] = ac < nac;
+            const int acc_ = val[u] ? ac : nac - 1;   // clamped, in bounds
+            const int cc = acc_ % Cpost, aa = acc_ / Cpost;
+            off[u] = aa * Rm * Cpost + cc;
+          }
+          double acc[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+          const double* vp = Vm + 4 * rq;
+          // operands of 4 consecutive j are loaded before any is used, so
+          // four LDS round trips overlap (tail j clamped, weight zero)
+          for (int j0 = 0; j0 < Rm; j0 += 4) {
+            double2 v01[4], v23[4];
+            float g[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+              v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
+              v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) g[q][u] = G[off[u] + j * Cpost];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const bool in = j0 + q < Rm;
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const double gv = in ? static_cast<double>(g[q][u]) : 0.0;
+                acc[u][0] += gv * v01[q].x;
+                acc[u][1] += gv * v01[q].y;
+                acc[u][2] += gv * v23[q].x;
+                acc[u][3] += gv * v23[q].y;
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (val[u]) {
+              double* dp = dst + (4 * ab + u) * RP + 4 * rq;
+              *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
+              *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
+            }
+          }
+        }
+        __syncthreads();
+      } else if (!reuse) {
+        const int total = Apre * Cpost * R4;
+        for (int item = t; item < total; item += NT) {
+          const int rq = item % R4;
+          const int ac = item / R4;
+          const int cc = ac % Cpost, aa = ac / Cpost;
+          double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+          const double* vp = Vm + 4 * rq;
+          const double* sp = src + (aa * Rm * Cpost + cc) * RP + 4 * rq;
+          const int sj = Cpost * RP;
+          for (int j0 = 0; j0 < Rm; j0 += 4) {
+            double2 s01[4], s23[4], v01[4], v23[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+              s01[q] = *reinterpret_cast<const double2*>(sp + j * sj);
+              s23[q] = *reinterpret_cast<const double2*>(sp + j * sj + 2);
+              v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
+              v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (j0 + q < Rm) {
+                acc0 += s01[q].x * v01[q].x;
+                acc1 += s01[q].y * v01[q].y;
+                acc2 += s23[q].x * v23[q].x;
+                acc3 += s23[q].y * v23[q].y;
+              }
+            }
+          }
+          double* dp = dst + ac * RP + 4 * rq;
+          *reinterpret_cast<double2*>(dp) = make_double2(acc0, acc1);
+          *reinterpret_cast<double2*>(dp + 2) = make_double2(acc2, acc3);
+        }
+        __syncthreads();
+      }
+      src = dst;
+    }
+    return src;
+  };
+
+  // closed-form fit of the current factors; uses the MTTKRP of the last
+  // mode, which must be in Hlast (computed here when `fresh`)
+  auto fit_of_state = [&](bool fresh = false) -> double {
+    if (fresh) mttkrp(N - 1);
+    const int Rl = a.Rn[N - 1];
+    const double* Vl = D(c.oV[N - 1]);
+    double p = 0.0;
+    for (int l = t; l < Rl * R; l += NT) {
+      const int j = l / R, r = l % R;
+      p += Hlast[j * RP + r] * Vl[j * RP + r];
+    }
+    const double inner = block_sum(p, red);
+    double q = 0.0;
+    for (int l = t; l < R * R; l += NT) {
+      const int i = l / R, j = l % R;
+      double v = 1.0;
+      for (int pp = 0; pp < N; ++pp) v *= D(c.oGram[pp])[i * RP + j];
+      q += v;
+    }
+    const double yh2 = block_sum(q, red);
+    double res2 = nrm2 - 2.0 * inner + yh2;
+    res2 = res2 > 0.0 ? res2 : 0.0;
+    return 1.0 - sqrt(res2) / sqrt(nrm2);
+  };
+
+  // guarded start: keep the caller's coefficients only if their fit is at
+  // least that of the HOSVD start
+  int init_used = 0;
+  if (!a.A_init[0] && a.V_alt[0]) {
+    const double f_user = fit_of_state(true);
+    load_coeffs(a.V_alt);
+    const double f_hosvd = fit_of_state(true);
+    if (f_user >= f_hosvd) {
+      load_coeffs(a.V_init);
+      init_used = 1;
+    }
+  }
+
   double fit_prev = 0.0, fit = 0.0;
   int it = 0, converged = 0, ridged = 0;
   for (it = 1; it <= a.max_it; ++it) {
     for (int n = 0; n < N; ++n) {
       const int Rn = a.Rn[n];
-      // H = G_(n) [KR_{p != n} V_p]: contract the last remaining mode != n
-      // (schedule precomputed on the host: mode, leading and trailing sizes).
-      // The first step of modes 0..N-2 contracts mode N-1 with V_{N-1},
-      // which only mode N-1 updates: it is computed once per iteration (X1).
-      const double* src = nullptr;
-      for (int st = 0; st < N - 1; ++st) {
-        const int m = c.sm[n][st];
-        const int Apre = c.sApre[n][st], Cpost = c.sCpost[n][st];
-        const bool last = st == N - 2;
-        const int Rm = a.Rn[m];
-        const double* Vm = D(c.oV[m]);
-        double* dst = last ? Hlast : (st == 0 ? X1 : (((st - 1) & 1) ? W2 : W1));
-        const bool reuse = st == 0 && !last && n > 0 && n < N - 1;
-        if (!reuse && src == nullptr) {
-          // first step from the FP32 core: 4 consecutive (a, c) x 4 r per item
-          const int nac = Apre * Cpost;
-          const int total = ((nac + 3) / 4) * R4;
-          for (int item = t; item < total; item += NT) {
-            const int rq = item % R4;
-            const int ab = item / R4;
-            int off[4];
-            bool val[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int ac = 4 * ab + u;
-              val[u] = ac < nac;
-              const int acc_ = val[u] ? ac : nac - 1;   // clamped, in bounds
-              const int cc = acc_ % Cpost, aa = acc_ / Cpost;
-              off[u] = aa * Rm * Cpost + cc;
-            }
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-            const double* vp = Vm + 4 * rq;
-            // operands of 4 consecutive j are loaded before any is used, so
-            // four LDS round trips overlap (tail j clamped, weight zero)
-            for (int j0 = 0; j0 < Rm; j0 += 4) {
-              double2 v01[4], v23[4];
-              float g[4][4];
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
-                v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
-                v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) g[q][u] = G[off[u] + j * Cpost];
-              }
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const bool in = j0 + q < Rm;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  const double gv = in ? static_cast<double>(g[q][u]) : 0.0;
-                  acc[u][0] += gv * v01[q].x;
-                  acc[u][1] += gv * v01[q].y;
-                  acc[u][2] += gv * v23[q].x;
-                  acc[u][3] += gv * v23[q].y;
-                }
-              }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              if (val[u]) {
-                double* dp = dst + (4 * ab + u) * RP + 4 * rq;
-                *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
-                *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
-              }
-            }
-          }
-          __syncthreads();
-        } else if (!reuse) {
-          const int total = Apre * Cpost * R4;
-          for (int item = t; item < total; item += NT) {
-            const int rq = item % R4;
-            const int ac = item / R4;
-            const int cc = ac % Cpost, aa = ac / Cpost;
-            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-            const double* vp = Vm + 4 * rq;
-            const double* sp = src + (aa * Rm * Cpost + cc) * RP + 4 * rq;
-            const int sj = Cpost * RP;
-            for (int j0 = 0; j0 < Rm; j0 += 4) {
-              double2 s01[4], s23[4], v01[4], v23[4];
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
-                s01[q] = *reinterpret_cast<const double2*>(sp + j * sj);
-                s23[q] = *reinterpret_cast<const double2*>(sp + j * sj + 2);
-                v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
-                v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
-              }
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                if (j0 + q < Rm) {
-                  acc0 += s01[q].x * v01[q].x;
-                  acc1 += s01[q].y * v01[q].y;
-                  acc2 += s23[q].x * v23[q].x;
-                  acc3 += s23[q].y * v23[q].y;
-                }
-              }
-            }
-            double* dp = dst + ac * RP + 4 * rq;
-            *reinterpret_cast<double2*>(dp) = make_double2(acc0, acc1);
-            *reinterpret_cast<double2*>(dp + 2) = make_double2(acc2, acc3);
-          }
-          __syncthreads();
-        }
-        src = dst;
-      }
-      const double* H = src;  // Rn x RP (Hlast)
+      const double* H = mttkrp(n);  // Rn x RP (Hlast)
 
       // T = hadamard of the other Grams
       for (int l = t; l < R * R; l += NT) {
@@ -478,27 +527,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
       __syncthreads();
     }
     // ---- fit (the last mode's H is still in Hlast) -------------------------
-    {
-      const int Rl = a.Rn[N - 1];
-      const double* Vl = D(c.oV[N - 1]);
-      double p = 0.0;
-      for (int l = t; l < Rl * R; l += NT) {
-        const int j = l / R, r = l % R;
-        p += Hlast[j * RP + r] * Vl[j * RP + r];
-      }
-      const double inner = block_sum(p, red);
-      double q = 0.0;
-      for (int l = t; l < R * R; l += NT) {
-        const int i = l / R, j = l % R;
-        double v = 1.0;
-        for (int pp = 0; pp < N; ++pp) v *= D(c.oGram[pp])[i * RP + j];
-        q += v;
-      }
-      const double yh2 = block_sum(q, red);
-      double res2 = nrm2 - 2.0 * inner + yh2;
-      res2 = res2 > 0.0 ? res2 : 0.0;
-      fit = 1.0 - sqrt(res2) / sqrt(nrm2);
-    }
+    fit = fit_of_state();
     if (t == 0 && a.fit_trace) a.fit_trace[it - 1] = fit;
     if (it >= 2 && fabs(fit - fit_prev) < a.tol) {
       converged = 1;
@@ -540,7 +569,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
     info->iterations = it;
     info->converged = converged;
     info->ridged = ridged_any;
-    info->reserved = 0;
+    info->init_used = init_used;
     info->fit = fit;
     info->fit_prev = fit_prev;
   }

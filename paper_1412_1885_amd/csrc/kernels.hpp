@@ -120,7 +120,8 @@ struct FfcpArgs {
   const float* U[8];
   const float* G;
   const float* A_init[8];  // user init (null when HOSVD)
-  const double* V_init[8]; // HOSVD: R_n x R in FP64 (already padded)
+  const double* V_init[8]; // coefficient start R_n x R in FP64 (HOSVD, padded, or caller's)
+  const double* V_alt[8];  // guarded start: the HOSVD alternative, or null
   float* A_out[8];
   float* lambda;
   double* fit_trace;

@@ -256,6 +256,52 @@ def test_ffcp_hosvd_init_with_padding(P):
         assert rel(host(out["A"][n]), ref["A"][n]) <= 1e-6
 
 
+def test_ffcp_coefficient_start(P):
+    """init="coeff": A_n = U_n V_n from caller coefficients, iterates equal to
+    the oracle started from A_n = U_n V_n."""
+    G, U, g = _tucker_format(81, (40, 41, 42), (5, 6, 4))
+    R = 4
+    V = [synth.f32(g.standard_normal((r, R))).astype(np.float64) for r in (5, 6, 4)]
+    out = P.ffcp([dev(u) for u in U], dev(G), R, update="als", init="coeff",
+                 A_init=[dev(v) for v in V], max_it=8, tol=0.0, fit_trace=True)
+    ref = F.ffcp(U, G, [u @ v for u, v in zip(U, V)], update="als", max_it=8, tol=0.0)
+    np.testing.assert_allclose(out["fits"], ref["fits"], rtol=0, atol=1e-9)
+    for n in range(3):
+        assert rel(host(out["A"][n]), ref["A"][n]) <= 1e-6
+
+
+@pytest.mark.parametrize("good", [True, False])
+def test_ffcp_guarded_start(P, good):
+    """init="coeff_guarded" keeps the caller's start only when its initial fit
+    is at least the HOSVD start's: a near-exact start is kept, a poor one is
+    replaced, and the run then equals the oracle from the chosen start."""
+    dims, R = (30, 31, 32), 4
+    rng = np.random.default_rng(82)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    Y = T.kruskal_full(A)
+    ref_t = RT.rand_tucker(Y, [rng.standard_normal((I, 6)) for I in dims],
+                           [[rng.standard_normal((36, 6)) for _ in dims]], ranks=(4, 4, 4))
+    U = [synth.f32(u).astype(np.float64) for u in ref_t["U"]]
+    G = synth.f32(ref_t["G"]).astype(np.float64)
+    if good:   # the compressed true factors, slightly perturbed
+        V = [u.T @ a + 1e-3 * rng.standard_normal((4, R)) for u, a in zip(U, A)]
+    else:      # an unrelated start
+        V = [rng.standard_normal((4, R)) for _ in dims]
+    V = [synth.f32(v).astype(np.float64) for v in V]
+    out = P.ffcp([dev(u) for u in U], dev(G), R, update="als", init="coeff_guarded",
+                 A_init=[dev(v) for v in V], max_it=5, tol=0.0, fit_trace=True)
+    A_user = [u @ v for u, v in zip(U, V)]
+    A_hosvd = F.hosvd_init(U, G, R)
+    assert out["info"]["init_used"] == (1 if good else 0)
+    start = A_user if good else A_hosvd
+    ref = F.ffcp(U, G, start, update="als", max_it=5, tol=0.0)
+    # near an exact fit the closed form 1 - sqrt(||Yt||^2 - 2<Yt,Yhat> +
+    # ||Yhat||^2)/||Yt|| cancels: an FP64 rounding of the bracket moves the
+    # fit by about sqrt(eps) ~ 1e-8, so the good start is compared at 1e-7
+    np.testing.assert_allclose(out["fits"], ref["fits"], rtol=0,
+                               atol=1e-7 if good else 1e-9)
+
+
 def test_ffcp_ridge_flag(P):
     G, U, g = _tucker_format(78, (20, 21, 22), (3, 3, 3))
     A0 = [g.standard_normal((I, 3)) for I in (20, 21, 22)]
