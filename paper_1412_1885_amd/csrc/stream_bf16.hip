@@ -99,21 +99,35 @@ __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArg
                                           TileRaw<SRC_F32>& t) {
   constexpr int kEl = SRC_F32 ? 4 : 2;
   const int r = rb * 32 + lr;
+  const bool tail4 = (a.I2 & 7) != 0;   // I2 % 8 == 4: the last chunk of a row is half
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = c0 + 16 * q + 8 * g;
-    const bool ok = r < a.I1 && c < a.I2;   // I2 % 8 == 0
+    const bool ok = r < a.I1 && c < a.I2;   // I2 % 4 == 0
+    const bool half = ok && c + 8 > a.I2;   // only 4 of the 8 columns exist
     const int off = ok ? (r * a.I2 + c) * kEl : 0x7ffffff0;
     if constexpr (SRC_F32) {
+      // rows start 16-byte aligned (I2 % 4 == 0)
       const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? off + 16 : off, 0, 0);
+      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, ok && !half ? off + 16
+                                                                            : 0x7ffffff0,
+                                                           0, 0);
       t.v[2 * q] = make_float4(__uint_as_float(lo.x), __uint_as_float(lo.y),
                                __uint_as_float(lo.z), __uint_as_float(lo.w));
       t.v[2 * q + 1] = make_float4(__uint_as_float(hi.x), __uint_as_float(hi.y),
                                    __uint_as_float(hi.z), __uint_as_float(hi.w));
-    } else {
+    } else if (!tail4) {
       const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       t.v[q] = make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+      // rows start 8-byte aligned: two 8-byte loads, the second absent in
+      // a half chunk
+      typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+      const v2u lo = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+      const v2u hi = __builtin_amdgcn_raw_buffer_load_b64(rs, ok && !half ? off + 8
+                                                                          : 0x7ffffff0,
+                                                          0, 0);
+      t.v[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
     }
   }
 }
@@ -190,9 +204,16 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
               yv[q].z = pack2(hi.x * down, hi.y * down);
               yv[q].w = pack2(hi.z * down, hi.w * down);
               const int r = rb * 32 + lr, c = c0 + 16 * q + 8 * g;
-              if (r < a.I1 && c < a.I2)
-                *reinterpret_cast<uint4*>(a.Yb + base + static_cast<int64_t>(r) * a.I2 + c) =
-                    yv[q];
+              if (r < a.I1 && c < a.I2) {
+                uint16_t* dst = a.Yb + base + static_cast<int64_t>(r) * a.I2 + c;
+                if (c + 8 <= a.I2 && (a.I2 & 7) == 0) {
+                  *reinterpret_cast<uint4*>(dst) = yv[q];
+                } else {   // 8-byte aligned rows; a half chunk stores 4 values
+                  *reinterpret_cast<uint2*>(dst) = make_uint2(yv[q].x, yv[q].y);
+                  if (c + 8 <= a.I2)
+                    *reinterpret_cast<uint2*>(dst + 4) = make_uint2(yv[q].z, yv[q].w);
+                }
+              }
             } else {
               yv[q] = cur.v[q];
             }
@@ -374,8 +395,8 @@ size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
 }
 
 int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
-  if (I1 > kMaxI1 || I2 % 8 != 0 || K1 > 32 || K2 > 32 || I2 > (1 << 30)) {
-    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 8 == 0 and "
+  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 || I2 > (1 << 30)) {
+    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0 and "
               "sketch widths <= 32 (got %lld, %lld, %d, %d)",
               kMaxI1, (long long)I1, (long long)I2, K1, K2);
     return kErrUnsupported;

@@ -95,7 +95,9 @@ def run(P, Y32, om32, omt32, ranks, sweeps, **kw):
 SHAPES = [((12, 70, 104), (8, 9, 10)),     # ragged row block, partial column tile
           ((5, 300, 96), (5, 16, 30)),     # several row blocks per wave
           ((3, 33, 64), (3, 5, 32)),       # exactly one column tile, R~ = 32
-          ((4, 5, 40, 48), (4, 5, 6, 7))]  # 4-way: slabs over two modes
+          ((4, 5, 40, 48), (4, 5, 6, 7)),  # 4-way: slabs over two modes
+          ((6, 50, 60), (6, 8, 9)),        # I_N % 8 == 4: half chunks at row ends
+          ((3, 40, 300), (3, 10, 30))]     # the learned-init workload's width
 
 
 @pytest.mark.parametrize("dims,rt", SHAPES)
