@@ -5,9 +5,12 @@ One step is one pass of the whole path over a resident synthetic tensor, in
 the precision form: rt_tucker_rand with BF16 streaming passes (statistics,
 FP32 read + BF16 copy fused into the first sketch sweep, one power sweep,
 the core pass on the BF16 copy; FP64 sketch QR; truncation to the Tucker
-ranks) followed by rt_ffcp (CP-ALS through the compressed core, HOSVD
-initialization, run to the stated fit-change tolerance).  The plain FP32
-path (one sweep) is timed beside it on the same tensor.
+ranks) followed by rt_ffcp (CP-ALS through the compressed core, started
+from the learned initializer's factors, guarded by the HOSVD start, run to
+the stated fit-change tolerance).  The plain FP32 path (the same two sweeps,
+HOSVD start) is timed beside it on the same tensor, and one FP32 sweep for
+context.  The initializer is trained before the timed region on cores the
+pipeline makes from seeded 300^3 CP tensors.
 
 Workload (synthetic, seeded): 1000 x 1000 x 1000 FP32 CP tensor of rank 20
 with per-mode column congruence drawn from U[0.5, 0.95], Gaussian noise at
@@ -56,6 +59,10 @@ def parse():
                     help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-slab", type=int, default=1000,
                     help="mode-3 slab of the tensor the oracle runs on")
+    ap.add_argument("--train-cores", type=int, default=2048,
+                    help="pipeline cores the learned initializer trains on "
+                         "(0: precision form starts from HOSVD)")
+    ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
                     help="also run K plain device copies of Y (HBM counter "
                          "calibration under a profiler)")
@@ -109,9 +116,9 @@ def cpu_baseline(Y, omegas, omega_tildes, ranks, slab, sweeps, bytes_per_elem):
 
 
 def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
-             warmup, tol, max_it, ybf16):
-    """Time `steps` calls of tucker_rand + ffcp in one form; returns timings,
-    the last outputs and the per-stage event totals."""
+             warmup, tol, max_it, ybf16, net=None):
+    """Time `steps` calls of tucker_rand [+ MLP start] + ffcp in one form;
+    returns timings, the last outputs and the per-stage event totals."""
     stream = torch.cuda.current_stream()
 
     def step(tws, fws, ev):
@@ -120,12 +127,18 @@ def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
                             precision=precision, workspace=tws, ybf16=ybf16,
                             sync=False)
         ev[1].record(stream)
-        f = P.ffcp(out["U"], out["G"], R, update="als", init="hosvd",
-                   max_it=max_it, tol=tol, workspace=fws, sync=False)
+        if net is not None:     # learned start, kept only if it beats HOSVD's
+            V = net.forward(out["G"].reshape((1,) + tuple(ranks)))
+            init = dict(init="coeff_guarded", A_init=[v[0] for v in net.split(V)])
+        else:
+            init = dict(init="hosvd")
         ev[2].record(stream)
+        f = P.ffcp(out["U"], out["G"], R, update="als", max_it=max_it, tol=tol,
+                   workspace=fws, sync=False, **init)
+        ev[3].record(stream)
         return out, f
 
-    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     tws = fws = None
     for _ in range(max(warmup, 1)):      # the first call sizes the workspaces
         out, f = step(tws, fws, mk())
@@ -147,12 +160,57 @@ def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
     fit_y = P.cp_fit_dense(Y, f["A"], f["lam"])[0]
     return {
         "tucker_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
-        "ffcp_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+        "init_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+        "ffcp_ms": float(np.mean([e[2].elapsed_time(e[3]) for e in evs])),
         "wall_ms": wall / steps * 1e3,
         "prof": prof, "iterations": int(finfo["iterations"]),
         "converged": int(finfo["converged"]), "fit_core": float(finfo["fit"]),
+        "init_used": int(finfo["init_used"]),
         "fit_y": float(fit_y), "normY2": float(tinfo["normY2"]),
     }
+
+
+def train_learned_init(P, torch, synth, cores, epochs, I=300, R=20, rt=30):
+    """Untimed setup: cores from the pipeline itself (seeded I^3 CP tensors,
+    rank R, congruence U[0.5, 0.95], SNR U[20, 40] dB, precision form with two
+    sweeps), then Adam on rt_mlp_train_step (batch 256, lr 1e-3 halved every
+    quarter of the epochs)."""
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    Gs = []
+    for k in range(cores):
+        snr = synth.rngs((5, k))["noise"].uniform(20.0, 40.0)
+        d = synth.cp_congruent_device((5, k), (I, I, I), R, 0.5, 0.95, snr, (rt,) * 3,
+                                      sweeps=2, device=dev)
+        om = [torch.from_numpy(o).to(dev) for o in synth.f32(d["omegas"])]
+        omt = [[torch.from_numpy(o).to(dev) for o in synth.f32(lst)]
+               for lst in d["omega_tildes"]]
+        Gs.append(P.tucker_rand(d["Y"], om, omt, ranks=(R, R, R), sweeps=2,
+                                precision="bf16", sync=False)["G"])
+    Gtr = torch.stack(Gs)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    net = P.MLP((R, R, R), R, (1024, 1024))
+    W, b = synth.mlp_weights(77, net.dims)
+    W[2] = W[2] * 0.1
+    net.load(W, b)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    t0 = time.perf_counter()
+    first = last = None
+    for ep in range(epochs):
+        perm = torch.randperm(cores, device=dev, generator=gen)
+        lr = 1e-3 * 0.5 ** (ep // max(1, epochs // 4))
+        ls = [net.train_step(Gtr[perm[i:i + 256]].contiguous(), lr)
+              for i in range(0, cores - 255, 256)]
+        m = float(torch.cat(ls).mean())
+        first = m if first is None else first
+        last = m
+    torch.cuda.synchronize()
+    return net, {"cores": cores, "core_tensor": f"{I}^3 CP rank {R}", "epochs": epochs,
+                 "steps": net.step, "generate_s": round(t_gen, 2),
+                 "train_s": round(time.perf_counter() - t0, 2),
+                 "loss_first_epoch": round(first, 5), "loss_last_epoch": round(last, 5)}
 
 
 def main():
@@ -185,21 +243,38 @@ def main():
     ybf16 = torch.empty(dims, dtype=torch.int16, device=dev)
     torch.cuda.synchronize()
 
-    forms = {"bf16": 2, "f32": 1}
+    net, learned = None, None
+    if args.train_cores > 0:
+        net, learned = train_learned_init(P, torch, synth, args.train_cores,
+                                          args.train_epochs)
+
+    # (precision, sweeps, learned start).  The plain FP32 path runs the same
+    # two sweeps as the precision form, so both reach the same subspaces and
+    # the same fit; one FP32 sweep is timed as well, for context (on this
+    # workload its subspaces, and so its fit, are clearly worse).
+    forms = {"bf16": ("bf16", 2, True), "f32": ("f32", 2, False),
+             "f32_one_sweep": ("f32", 1, False)}
     main_form = args.precision
-    other = "f32" if main_form == "bf16" else "bf16"
+    order = [f for f in forms if f != main_form] + [main_form]   # the step's form last
     res = {}
-    for form in (other, main_form):      # the step's form runs last
-        res[form] = run_form(P, torch, Y, om_d, omt_d, ranks, R, form, forms[form],
-                             args.steps, args.warmup, args.tol, args.max_it, ybf16)
+    for form in order:
+        prec, sw, learned_start = forms[form]
+        res[form] = run_form(P, torch, Y, om_d, omt_d, ranks, R, prec, sw,
+                             args.steps, args.warmup, args.tol, args.max_it, ybf16,
+                             net if learned_start else None)
     m = res[main_form]
 
     # algorithmic HBM bytes of the Tucker stage (each pass reads Y once):
-    # plain FP32, one sweep: sweep + core = 2 x 4 B per element; precision
-    # form, two sweeps: FP32 read + BF16 write (first sweep) + two BF16 reads
+    # plain FP32: 4 B per element per sweep + 4 B for the core pass;
+    # precision form: FP32 read + BF16 write (first sweep), then 2 B per
+    # element per later sweep and for the core pass
     n = Y.numel()
-    alg_bytes = {"f32": 2 * 4 * n, "bf16": (4 + 2 + 2 + 2) * n}
-    value = alg_bytes[main_form] / (m["tucker_ms"] * 1e-3) / 1e9
+
+    def alg_bytes(form):
+        prec, sw, _ = forms[form]
+        return (4 * (sw + 1) if prec == "f32" else 4 + 2 + 2 * sw) * n
+
+    value = alg_bytes(main_form) / (m["tucker_ms"] * 1e-3) / 1e9
 
     # dominant kernel: the first sweep's streaming kernel
     ms_k, n_k = m["prof"]["first_pass"]
@@ -237,15 +312,20 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab, forms[main_form],
-                           alg_bytes[main_form] // n)
+        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab, forms[main_form][1],
+                           alg_bytes(main_form) // n)
 
     def summary(form):
         r = res[form]
-        return {"sweeps": forms[form], "tucker_ms": round(r["tucker_ms"], 4),
-                "tucker_gbs": round(alg_bytes[form] / (r["tucker_ms"] * 1e-3) / 1e9, 1),
+        learned_start = forms[form][2] and net is not None
+        return {"precision": forms[form][0], "sweeps": forms[form][1],
+                "tucker_ms": round(r["tucker_ms"], 4),
+                "tucker_gbs": round(alg_bytes(form) / (r["tucker_ms"] * 1e-3) / 1e9, 1),
+                "start": "learned (guarded by HOSVD)" if learned_start else "HOSVD",
+                "start_kept": r["init_used"] if learned_start else None,
+                "init_ms": round(r["init_ms"], 4),
                 "ffcp_ms": round(r["ffcp_ms"], 4),
-                "time_to_fit_ms": round(r["tucker_ms"] + r["ffcp_ms"], 4),
+                "time_to_fit_ms": round(r["tucker_ms"] + r["init_ms"] + r["ffcp_ms"], 4),
                 "ffcp_iterations": r["iterations"], "ffcp_converged": r["converged"],
                 "fit_core": r["fit_core"], "fit_y": r["fit_y"],
                 "stages_ms": {k: round(v[0] / max(v[1], 1), 4)
@@ -269,15 +349,20 @@ def main():
             "description": (f"{I}^3 FP32 CP rank {R}, column congruence "
                             "U[0.5,0.95], SNR 30 dB; Omega_n "
                             f"{I}x{rt}, Omega~_n {rt * rt}x{rt}; Tucker ranks "
-                            f"{ranks}; FFCP ALS R={R}, HOSVD init, tol {args.tol}"),
+                            f"{ranks}; FFCP ALS R={R}, tol {args.tol}; precision "
+                            "form: BF16 passes, two sweeps, learned start; plain "
+                            "FP32: two sweeps, HOSVD start"),
             "dims": list(dims), "ranks": list(ranks), "ranks_tilde": [rt] * 3,
-            "sweeps": forms[main_form], "R": R, "update": "als",
+            "sweeps": forms[main_form][1], "R": R, "update": "als",
         },
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
-        main_form: summary(main_form),
-        other: summary(other),
+        **{f: summary(f) for f in forms},
         "fit_y_rel_diff_mixed_vs_plain": abs(res["bf16"]["fit_y"] - res["f32"]["fit_y"]) /
             max(abs(res["f32"]["fit_y"]), 1e-300),
+        "time_to_fit_mixed_over_plain": round(
+            (res["bf16"]["tucker_ms"] + res["bf16"]["init_ms"] + res["bf16"]["ffcp_ms"]) /
+            (res["f32"]["tucker_ms"] + res["f32"]["init_ms"] + res["f32"]["ffcp_ms"]), 4),
+        "learned_init": learned,
         "normY2": m["normY2"],
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -302,6 +302,10 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
     for n in range(N):
         _require_device(U[n], f"U[{n}]", torch.float32)
     _require_device(G, "G", torch.float32)
+    if A_init is not None:
+        for n, a in enumerate(A_init):
+            if a is not None:
+                _require_device(a, f"A_init[{n}]", torch.float32)
     dev = G.device
     A = [torch.empty((dims[n], R), dtype=torch.float32, device=dev) for n in range(N)]
     lam = torch.empty(R, dtype=torch.float32, device=dev)
