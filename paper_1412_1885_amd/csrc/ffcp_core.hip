@@ -112,6 +112,80 @@ __device__ __forceinline__ bool gj_inverse_wave(const double* T, int RP, int R,
   return ok;
 }
 
+// Wave-level Gauss-Jordan solve of X (T + delta I) = H for X (Rn x R), T
+// symmetric positive definite (R x R) and H (Rn x R), all with row stride
+// RP.  The wave holds the augmented matrix [T + delta I | H^T] (R rows),
+// lane c column c (R + Rn <= 64).  The T block is eliminated in the
+// symmetric (sweep) form: pivot k scales column k by 1/d and sets the pivot
+// to -1/d, so the block stays symmetric and the pivot column equals row k,
+// which lane i already holds as its entry k.  Each step therefore
+// publishes one value per lane in LDS (pcol), reads the column back as a
+// broadcast and applies R fused multiply-adds; the H^T columns see the
+// ordinary row operations.  After R steps lane R + i holds column i of
+// T^{-1} H^T, i.e. row i of X.  Without pivoting the pivots are the
+// Schur-complement diagonals: one <= 0 means T + delta I is not numerically
+// positive definite (returns false).
+template <int RMAX>
+__device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, double delta,
+                                              const double* H, int Rn, double* X,
+                                              double* pcol) {
+  static_assert(RMAX % 2 == 0 && RMAX <= 32, "pivot column in double2 steps");
+  const int c = threadIdx.x & 63;
+  const bool isT = c < R, isH = c >= R && c < R + Rn;
+  const int jt = isT ? c : 0, ih = isH ? c - R : 0;   // clamped: loads in bounds
+  double col[RMAX];
+#pragma unroll
+  for (int i = 0; i < RMAX; ++i) {
+    const int ic = i < R ? i : R - 1;
+    double v = 0.0;
+    if (isT)
+      v = T[ic * RP + jt] + (i == c ? delta : 0.0);
+    else if (isH)
+      v = H[ih * RP + ic];
+    col[i] = i < R ? v : 0.0;
+  }
+  if (c < RMAX) pcol[c] = 0.0;   // slots R..RMAX-1 stay zero
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k < R) {
+      if (isT) pcol[c] = col[k];   // row k = column k of the symmetric block
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double m[RMAX];
+#pragma unroll
+      for (int i = 0; i < RMAX; i += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(pcol + i);
+        m[i] = v.x;
+        m[i + 1] = v.y;
+      }
+      double p = m[k];
+      if (!(p > 0.0)) {
+        ok = false;
+        p = 1.0;
+      }
+      const double rp = recip(p);
+      const bool piv = c == k;
+      const double f = piv ? -rp : col[k] * rp;
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i)
+        if (i != k) col[i] = (piv ? 0.0 : col[i]) - m[i] * f;
+      col[k] = f;
+      // every lane has read pcol before the next step rewrites it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  if (isH) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) X[ih * RP + i] = col[i];
+  }
+  return ok;
+}
+
 // out (p x q, row stride ldo) = X^T Y over `rows` rows of the row-major
 // float matrices X (rows x p) and Y (rows x q); 64-row blocks staged in LDS
 // (st: 64 (p + q) doubles).  p, q <= 64.
@@ -166,13 +240,20 @@ __device__ void small_mm(const double* A, int lda, bool transA, const double* B,
 }
 
 template <int RMAX, int NT, bool GLDS>
-__global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
+__global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
   extern __shared__ __align__(16) char smem[];
-  const FfcpArgs& a = c.a;
+  // The argument is read in place from the kernel-argument segment: its
+  // arrays are indexed with (uniform) runtime indices, which a by-value copy
+  // would serve from per-thread scratch memory; here they are scalar loads.
+  (void)c_arg;
+  typedef const __attribute__((address_space(4))) CoreAlsArgs KArgs;
+  KArgs& c = *reinterpret_cast<KArgs*>(
+      reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr()));
+  auto& a = c.a;
   const int t = threadIdx.x;
   const int N = a.N, R = a.R, RP = c.RP, R4 = RP / 4;
   const int64_t core = c.core;
-  auto D = [&](int off) { return reinterpret_cast<double*>(smem + off); };
+  auto D = [&](int off) __attribute__((always_inline)) { return reinterpret_cast<double*>(smem + off); };
   InfoDev* info = static_cast<InfoDev*>(a.info);
 
   // ---- setup -------------------------------------------------------------
@@ -214,11 +295,13 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
   }
   __syncthreads();
   // coefficient starts (HOSVD or the caller's): A_n = U_n Vc_n
-  auto load_coeffs = [&](const double* const* Vc) {
+  // (alt: the HOSVD start kept beside the caller's, else the start)
+  auto load_coeffs = [&](bool alt) __attribute__((always_inline)) {
     for (int n = 0; n < N; ++n) {
       const int Rn = a.Rn[n];
       double* Vh = D(c.oVh[n]);
-      for (int l = t; l < Rn * R; l += NT) Vh[(l / R) * RP + l % R] = Vc[n][l];
+      const double* Vc = alt ? a.V_alt[n] : a.V_init[n];
+      for (int l = t; l < Rn * R; l += NT) Vh[(l / R) * RP + l % R] = Vc[l];
       __syncthreads();
       small_mm<NT>(D(c.oM[n]), Rn, false, Vh, RP, D(c.oV[n]), RP, Rn, Rn, R);
       __syncthreads();
@@ -226,7 +309,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
       __syncthreads();
     }
   };
-  if (!a.A_init[0]) load_coeffs(a.V_init);
+  if (!a.A_init[0]) load_coeffs(false);
 
   // ||Yt||^2 = <G, G x_1 M_1 ... x_N M_N> unless given (global scratch)
   double nrm2 = a.normY2;
@@ -273,7 +356,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
   double* Hlast = D(c.oH);
 
   // H_n = G_(n) [KR_{p != n} V_p] into Hlast (returns it)
-  auto mttkrp = [&](int n) -> const double* {
+  auto mttkrp = [&](int n) __attribute__((always_inline)) -> const double* {
     // H = G_(n) [KR_{p != n} V_p]: contract the last remaining mode != n
     // (schedule precomputed on the host: mode, leading and trailing sizes).
     // The first step of modes 0..N-2 contracts mode N-1 with V_{N-1},
@@ -388,9 +471,8 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
   };
 
   // closed-form fit of the current factors; uses the MTTKRP of the last
-  // mode, which must be in Hlast (computed here when `fresh`)
-  auto fit_of_state = [&](bool fresh = false) -> double {
-    if (fresh) mttkrp(N - 1);
+  // mode, which must be in Hlast
+  auto fit_of_state = [&]() __attribute__((always_inline)) -> double {
     const int Rl = a.Rn[N - 1];
     const double* Vl = D(c.oV[N - 1]);
     double p = 0.0;
@@ -416,11 +498,13 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
   // least that of the HOSVD start
   int init_used = 0;
   if (!a.A_init[0] && a.V_alt[0]) {
-    const double f_user = fit_of_state(true);
-    load_coeffs(a.V_alt);
-    const double f_hosvd = fit_of_state(true);
+    mttkrp(N - 1);
+    const double f_user = fit_of_state();
+    load_coeffs(true);
+    mttkrp(N - 1);
+    const double f_hosvd = fit_of_state();
     if (f_user >= f_hosvd) {
-      load_coeffs(a.V_init);
+      load_coeffs(false);
       init_used = 1;
     }
   }
@@ -443,8 +527,22 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
       __syncthreads();
 
       double* Vh = D(c.oVh[n]);
-      // L <- T^{-1} by wave 0 (ridge T + delta I when T is not numerically
-      // positive definite)
+      // Vh = H T^{-1} (ridge T + delta I when T is not numerically positive
+      // definite), by wave 0
+      if (RMAX <= 32 && R + Rn <= 64) {
+        if constexpr (RMAX <= 32) {
+          if (t < 64) {
+            if (!gj_solve_wave<RMAX>(T, RP, R, 0.0, H, Rn, Vh, L)) {
+              double tr = 0.0;
+              for (int k = 0; k < R; ++k) tr += T[k * RP + k];
+              gj_solve_wave<RMAX>(T, RP, R, 1e-12 * tr / R, H, Rn, Vh, L);
+              ridged = 1;
+            }
+          }
+        }
+        __syncthreads();
+      } else {
+      // L <- T^{-1}, then Vh = H L
       if (t < 64) {
         if (!gj_inverse_wave<RMAX>(T, RP, R, 0.0, L)) {
           double tr = 0.0;
@@ -454,7 +552,6 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
         }
       }
       __syncthreads();
-      // Vh = H T^{-1}
       for (int l = t; l < Rn * R4; l += NT) {
         const int i = l / R4, rq = l % R4;
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
@@ -472,6 +569,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c) {
         *reinterpret_cast<double2*>(vp + 2) = make_double2(acc2, acc3);
       }
       __syncthreads();
+      }
 
       // P = M_n Vh;  G0 = Vh^T P (Gram of the unnormalized factor)
       const double* M = D(c.oM[n]);
@@ -601,7 +699,7 @@ int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
     c.oGram[n] = take(8LL * R * c.RP);
   }
   c.oT = take(8LL * R * c.RP);
-  c.oL = take(8LL * R * c.RP);
+  c.oL = take(8LL * (R * c.RP > 64 ? R * c.RP : 64));   // also the pivot column
   c.oH = take(8LL * Rmax * c.RP);
   c.oP = take(8LL * Rmax * c.RP);
   c.oNrm = take(8LL * c.RP);
@@ -685,6 +783,7 @@ int launch_ffcp_als_core(const FfcpArgs& a, hipStream_t s) {
   CoreAlsArgs c{};
   c.a = a;
   if (a.R <= 16) return launch_r<16, 512>(c, s);
+  if (a.R <= 20) return launch_r<20, 512>(c, s);
   if (a.R <= 24) return launch_r<24, 512>(c, s);
   if (a.R <= 32) return launch_r<32, 512>(c, s);
   return launch_r<64, 512>(c, s);

@@ -72,6 +72,24 @@ __device__ __forceinline__ uint16_t half_of(const uint4& u, int j) {
   return static_cast<uint16_t>(w >> (16 * (j & 1)));
 }
 
+// Writes element (m, n) of the product x through the epilogue EPI.
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float x) {
+  const int64_t o = static_cast<int64_t>(m) * g.ldc + n;
+  if (EPI == kEpiBias || EPI == kEpiBiasGelu) x += g.bias[n];
+  if (EPI == kEpiBiasGelu) {
+    g.C[o] = x;                               // pre-activation
+    g.Cb[o] = f32_to_bf16_rne(gelu_f(x));     // activation (BF16)
+  } else if (EPI == kEpiDGelu) {
+    const float d = x * gelu_grad_f(g.Zin[o]);
+    g.C[o] = d;
+    g.Cb[o] = f32_to_bf16_rne(d);
+  } else {
+    g.C[o] = x;
+    if (g.Cb) g.Cb[o] = f32_to_bf16_rne(x);
+  }
+}
+
 // C (M x N) = op(A) op(B); op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k],
 // op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64 x 64 tiles staged in
 // LDS with K contiguous; four wavefronts, one 32 x 32 MFMA block each.
@@ -125,22 +143,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int m = m0 + wm * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
-    if (m < g.M && n < g.N) {
-      const int64_t o = static_cast<int64_t>(m) * g.ldc + n;
-      float x = acc[v];
-      if (EPI == kEpiBias || EPI == kEpiBiasGelu) x += g.bias[n];
-      if (EPI == kEpiBiasGelu) {
-        g.C[o] = x;                               // pre-activation
-        g.Cb[o] = f32_to_bf16_rne(gelu_f(x));     // activation (BF16)
-      } else if (EPI == kEpiDGelu) {
-        const float d = x * gelu_grad_f(g.Zin[o]);
-        g.C[o] = d;
-        g.Cb[o] = f32_to_bf16_rne(d);
-      } else {
-        g.C[o] = x;
-        if (g.Cb) g.Cb[o] = f32_to_bf16_rne(x);
-      }
-    }
+    if (m < g.M && n < g.N) epilogue<EPI>(g, m, n, acc[v]);
   }
 }
 
@@ -149,6 +152,91 @@ int gemm(const GemmArgs& g, hipStream_t s) {
   const dim3 grid((g.N + kTM - 1) / kTM, (g.M + kTM - 1) / kTM);
   hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
   RT_LAUNCH_CHECK("mlp gemm");
+  return kOk;
+}
+
+// Few rows (inference on a handful of cores): C = A B with A [M][K] (M <=
+// kGvMaxM) and B [K][N] row-major, N % 8 == 0.  The weight matrix is
+// streamed once, split over K across the grid: workgroup (x, s) owns 512
+// columns and the K rows of chunk s, one wavefront per row residue mod 4,
+// 8 columns per lane; the four waves' sums meet in LDS and each chunk's
+// partial goes to part[s][m][n].  A second kernel sums the chunks in a
+// fixed order and applies the epilogue.
+constexpr int kGvMaxM = 8;
+constexpr int kGvCols = 512;
+constexpr int kGvMaxSplit = 128;
+
+int gemv_splits(int K) {
+  const int s = (K + 15) / 16;   // at least 16 rows per chunk
+  return s < kGvMaxSplit ? s : kGvMaxSplit;
+}
+
+__global__ __launch_bounds__(256) void gemv_partial_kernel(GemmArgs g, int kchunk,
+                                                           float* part) {
+  __shared__ float red[4][kGvMaxM][kGvCols];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = blockIdx.x * kGvCols + 8 * lane;
+  const int k0 = blockIdx.y * kchunk;
+  const int k1 = k0 + kchunk < g.K ? k0 + kchunk : g.K;
+  const bool colok = n < g.N;                 // N % 8 == 0: all 8 or none
+  float acc[kGvMaxM][8];
+#pragma unroll
+  for (int m = 0; m < kGvMaxM; ++m)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[m][j] = 0.0f;
+  for (int k = k0 + w; k < k1; k += 4) {
+    const uint4 u = colok ? *reinterpret_cast<const uint4*>(
+                                g.B + static_cast<int64_t>(k) * g.ldb + n)
+                          : make_uint4(0, 0, 0, 0);
+    float bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = bf16_to_f32(half_of(u, j));
+#pragma unroll
+    for (int m = 0; m < kGvMaxM; ++m) {
+      if (m < g.M) {
+        const float av = bf16_to_f32(g.A[static_cast<int64_t>(m) * g.lda + k]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[m][j] += av * bv[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kGvMaxM; ++m)
+    if (m < g.M)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[w][m][8 * lane + j] = acc[m][j];
+  __syncthreads();
+  for (int l = threadIdx.x; l < g.M * kGvCols; l += 256) {
+    const int m = l / kGvCols, c = l % kGvCols;
+    const int nn = blockIdx.x * kGvCols + c;
+    if (nn < g.N)
+      part[(static_cast<int64_t>(blockIdx.y) * g.M + m) * g.N + nn] =
+          (red[0][m][c] + red[1][m][c]) + (red[2][m][c] + red[3][m][c]);
+  }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemv_finish_kernel(GemmArgs g, int splits,
+                                                          const float* part) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= g.M * g.N) return;
+  const int m = l / g.N, n = l % g.N;
+  float x = 0.0f;
+  for (int sp = 0; sp < splits; ++sp) x += part[(static_cast<int64_t>(sp) * g.M + m) * g.N + n];
+  epilogue<EPI>(g, m, n, x);
+}
+
+// C = A B (A rows m, B rows k): the split-K path for M <= kGvMaxM.
+template <int EPI>
+int gemv(const GemmArgs& g, float* part, hipStream_t s) {
+  const int splits = gemv_splits(g.K);
+  const int kchunk = (g.K + splits - 1) / splits;
+  const dim3 grid((g.N + kGvCols - 1) / kGvCols, splits);
+  hipLaunchKernelGGL(gemv_partial_kernel, grid, dim3(256), 0, s, g, kchunk, part);
+  RT_LAUNCH_CHECK("mlp gemv");
+  hipLaunchKernelGGL(gemv_finish_kernel<EPI>, dim3((g.M * g.N + 255) / 256), dim3(256), 0,
+                     s, g, splits, part);
+  RT_LAUNCH_CHECK("mlp gemv finish");
   return kOk;
 }
 
@@ -377,6 +465,7 @@ struct MlpPlan {
   float* norms;
   float *Z1, *Z2, *Yo, *dY, *dZ1, *dZ2, *loss;
   uint16_t *H1, *H2, *dYb, *dZ1b, *dZ2b;
+  float* part;    // split-K partial sums (few cores)
   float* gW[3];
   float* gb[3];
   size_t plan(const MlpDims& m, void* ws, bool grads) {
@@ -397,6 +486,15 @@ struct MlpPlan {
     dZ2b = ar.take<uint16_t>(B * m.d2);
     loss = ar.take<float>(B);
     const int dims[4] = {m.d0, m.d1, m.d2, m.d3};
+    part = nullptr;
+    if (m.B <= kGvMaxM) {
+      int64_t most = 0;
+      for (int l = 0; l < 3; ++l) {
+        const int64_t e = static_cast<int64_t>(gemv_splits(dims[l])) * m.B * dims[l + 1];
+        most = e > most ? e : most;
+      }
+      part = ar.take<float>(most);
+    }
     for (int l = 0; l < 3; ++l) {
       gW[l] = grads ? ar.take<float>(static_cast<int64_t>(dims[l]) * dims[l + 1]) : nullptr;
       gb[l] = grads ? ar.take<float>(dims[l + 1]) : nullptr;
@@ -425,17 +523,19 @@ int forward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& P
             hipStream_t s) {
   hipLaunchKernelGGL(mlp_prep_kernel, dim3(m.B), dim3(256), 0, s, G, m.d0, P.X, P.norms);
   RT_LAUNCH_CHECK("mlp prep");
+  // a handful of cores: the weights are streamed once, split over K
+  const bool few = P.part != nullptr;
   GemmArgs g{};
   g.M = m.B; g.N = m.d1; g.K = m.d0;
   g.A = P.X; g.lda = m.d0; g.B = p->Wb[0]; g.ldb = m.d1;
   g.C = P.Z1; g.ldc = m.d1; g.Cb = P.H1; g.bias = p->b[0];
-  RT_TRY((gemm<false, false, kEpiBiasGelu>(g, s)));
+  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s) : gemm<false, false, kEpiBiasGelu>(g, s)));
   g.N = m.d2; g.K = m.d1; g.A = P.H1; g.lda = m.d1; g.B = p->Wb[1]; g.ldb = m.d2;
   g.C = P.Z2; g.ldc = m.d2; g.Cb = P.H2; g.bias = p->b[1];
-  RT_TRY((gemm<false, false, kEpiBiasGelu>(g, s)));
+  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s) : gemm<false, false, kEpiBiasGelu>(g, s)));
   g.N = m.d3; g.K = m.d2; g.A = P.H2; g.lda = m.d2; g.B = p->Wb[2]; g.ldb = m.d3;
   g.C = P.Yo; g.ldc = m.d3; g.Cb = nullptr; g.bias = p->b[2];
-  RT_TRY((gemm<false, false, kEpiBias>(g, s)));
+  RT_TRY((few ? gemv<kEpiBias>(g, P.part, s) : gemm<false, false, kEpiBias>(g, s)));
   return kOk;
 }
 

@@ -21,14 +21,26 @@
 //
 // Data path (one workgroup of 8 wavefronts per slab).  Wave w owns the
 // 32-row blocks w, w+8, w+16, w+24 (I1 <= 1024) and walks the slab in
-// 64-column tiles.  Lane l loads, for each 16-column chunk q of the tile,
-// the 8 values Y[r0 + l%32][c0 + 16q + 8(l/32) .. +7] (16 bytes of BF16):
-// exactly the A operand of the 32x32x16 MFMA for TA = M B2 (K = columns).
-// For TB = B1^T M (K = rows) the B operand needs 8 consecutive rows of one
-// column, so the wave also writes its tile transposed into a private LDS
-// tile and reads it back with 16-byte loads.  TA accumulates in registers
-// across the column tiles; TB's partial sums over each wave's rows are
-// reduced across the 8 waves in LDS, in a fixed order, once per column tile.
+// 64-column tiles, column tile by column tile (RBW steps per column tile:
+// the number of row blocks a wave owns, rounded up to 1, 2 or 4).  Lane l
+// loads, for each 16-column chunk q of the tile, the 8 values
+// Y[r0 + l%32][c0 + 16q + 8(l/32) .. +7] (16 bytes of BF16): exactly the A
+// operand of the 32x32x16 MFMA for TA = M B2 (K = columns).  For TB = B1^T M
+// (K = rows) the B operand needs 8 consecutive rows of one column, so the
+// wave also writes its tile transposed into a private LDS tile and reads it
+// back with 16-byte loads.  TA accumulates in registers across the column
+// tiles; TB's partial sums over each wave's rows are reduced across the 8
+// waves in LDS, in a fixed order, once per column tile.
+//
+// Latency.  The vector-memory counter completes in issue order, so a wait
+// for any load also waits for every load issued before it.  Tiles are
+// loaded several steps ahead into a statically indexed ring of registers
+// (FP32 source: one tile ahead; BF16: three), B1^T sits in LDS for the whole
+// slab and B2^T of the next column tile is loaded one column tile ahead,
+// before that step's tile, so no wait inside the loop stalls on a tile
+// that is not yet needed.
+#include <utility>
+
 #include "stream.hpp"
 
 #include "kernels.hpp"
@@ -47,6 +59,11 @@ constexpr int kRBMax = 4;              // 32-row blocks per wave
 constexpr int kCT = 64;                // columns per tile
 constexpr int kYtStride = 40;          // halfwords per row of the transposed tile
 constexpr int kMaxI1 = 32 * kBW * kRBMax;
+constexpr int kWaveLds = 32 * kCT * 4; // per-wave LDS: transposed tile, then TB partial
+constexpr int kB1Pad = 8;              // halfwords of padding per B1^T row in LDS
+constexpr int kUnroll = 8;             // steps per loop trip: two column tiles at
+                                       // least, a multiple of the ring size
+static_assert(kCT * kYtStride * 2 <= kWaveLds, "transposed tile fits the wave's region");
 
 struct BfArgs {
   const void* Y;          // FP32 (first pass) or BF16 bit patterns
@@ -83,6 +100,9 @@ struct TileRaw<false> {
 };
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+constexpr int kOob = 0x7ffffff0;       // offset past every slab: loads return zero
 
 // Buffer descriptor over one slab (byte range); loads past it return zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64_t bytes) {
@@ -91,210 +111,248 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64
 }
 
 // Loads the lane's part of the 32 x 64 tile at rows rb*32.. and columns
-// c0..: buffer loads with a 32-bit offset into the slab; masked lanes get an
+// c0..: buffer loads with a 32-bit offset into the slab; masked lanes (rows
+// or columns past the slab, including whole tiles past the end) get an
 // offset past the slab, so the hardware returns zeros without branches.
-template <bool SRC_F32>
+// HALF (BF16 source, I2 % 8 == 4): rows start 8-byte aligned, two 8-byte
+// loads per chunk, the second absent in the half chunk at a row's end.
+template <bool SRC_F32, bool HALF>
 __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArgs& a,
                                           int rb, int lr, int c0, int g,
                                           TileRaw<SRC_F32>& t) {
   constexpr int kEl = SRC_F32 ? 4 : 2;
   const int r = rb * 32 + lr;
-  const bool tail4 = (a.I2 & 7) != 0;   // I2 % 8 == 4: the last chunk of a row is half
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = c0 + 16 * q + 8 * g;
     const bool ok = r < a.I1 && c < a.I2;   // I2 % 4 == 0
-    const bool half = ok && c + 8 > a.I2;   // only 4 of the 8 columns exist
-    const int off = ok ? (r * a.I2 + c) * kEl : 0x7ffffff0;
+    const bool full = ok && c + 8 <= a.I2;  // else only 4 of the 8 columns exist
+    // (r * I2 + c) * kEl < slab bytes < 2^31 whenever ok; clamped otherwise
+    const int off = ok ? ((ok ? r : 0) * a.I2 + (ok ? c : 0)) * kEl : kOob;
     if constexpr (SRC_F32) {
       // rows start 16-byte aligned (I2 % 4 == 0)
       const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, ok && !half ? off + 16
-                                                                            : 0x7ffffff0,
-                                                           0, 0);
+      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, full ? off + 16 : kOob, 0, 0);
       t.v[2 * q] = make_float4(__uint_as_float(lo.x), __uint_as_float(lo.y),
                                __uint_as_float(lo.z), __uint_as_float(lo.w));
       t.v[2 * q + 1] = make_float4(__uint_as_float(hi.x), __uint_as_float(hi.y),
                                    __uint_as_float(hi.z), __uint_as_float(hi.w));
-    } else if (!tail4) {
+    } else if constexpr (!HALF) {
       const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       t.v[q] = make_uint4(v.x, v.y, v.z, v.w);
     } else {
-      // rows start 8-byte aligned: two 8-byte loads, the second absent in
-      // a half chunk
-      typedef unsigned int v2u __attribute__((ext_vector_type(2)));
       const v2u lo = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-      const v2u hi = __builtin_amdgcn_raw_buffer_load_b64(rs, ok && !half ? off + 8
-                                                                          : 0x7ffffff0,
-                                                          0, 0);
+      const v2u hi = __builtin_amdgcn_raw_buffer_load_b64(rs, full ? off + 8 : kOob, 0, 0);
       t.v[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
     }
   }
 }
 
-template <bool SRC_F32, bool DOQ>
+// f(std::integral_constant<int, u>) for u = 0 .. N-1, unrolled at compile time.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// B2^T operand of column tile ct for this lane (row lr of B2^T).
+__device__ __forceinline__ void load_b2(const BfArgs& a, int ct, int lr, int g, v8bf* b2) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    b2[q] = as_v8bf(*reinterpret_cast<const uint4*>(
+        a.B2t + static_cast<int64_t>(lr) * a.ldb2 + ct * kCT + 16 * q + 8 * g));
+}
+
+// RBW: steps per column tile (the row blocks a wave owns, rounded up to 1, 2
+// or 4); with it every register array below is indexed statically.
+template <bool SRC_F32, bool DOQ, bool HALF, int RBW>
 __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   extern __shared__ __align__(16) char smem[];
+  constexpr int kSlots = SRC_F32 ? 2 : 4;   // tiles in registers: current + in flight
+  static_assert((RBW == 1 || RBW == 2 || RBW == 4) && RBW <= kRBMax, "row blocks");
+  static_assert(kUnroll % kSlots == 0 && kUnroll % (2 * RBW) == 0, "static indexing");
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int lr = lane & 31, g = lane >> 5;
-  uint16_t* yt = reinterpret_cast<uint16_t*>(smem) + w * (kCT * kYtStride);
-  float* red = reinterpret_cast<float*>(smem + kBW * kCT * kYtStride * 2);
+  uint16_t* yt = reinterpret_cast<uint16_t*>(smem + w * kWaveLds);
+  float* red = reinterpret_cast<float*>(smem);   // [kBW][32][kCT]: wave w's region
+  uint16_t* b1s = reinterpret_cast<uint16_t*>(smem + kBW * kWaveLds);
+  const int ldb1s = a.ldb1 + kB1Pad;
   const int nrb = (a.I1 + 31) / 32;
   const int nct = (a.I2 + kCT - 1) / kCT;
-  const int myrb = w < nrb ? (nrb - 1 - w) / kBW + 1 : 0;   // row blocks of this wave
+  // whole loop trips (kUnroll steps = 8 / RBW column tiles): the steps past
+  // the last column tile read masked (zero) tiles, so the loop body has no
+  // branches and every wait counts loads exactly
+  const int nsteps = (nct * RBW + kUnroll - 1) / kUnroll * kUnroll;
   const int64_t slab_elems = static_cast<int64_t>(a.I1) * a.I2;
 
   // one slab per workgroup: no outer loop, so nothing slab-invariant is kept
   // live across slabs
-  {
-    const int64_t slab = blockIdx.x;
-    const int e = a.exps[slab];
-    const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
-    const int64_t base = slab * slab_elems;
-    const __amdgpu_buffer_rsrc_t rs =
-        SRC_F32 ? slab_rsrc(static_cast<const float*>(a.Y) + base, slab_elems * 4)
-                : slab_rsrc(static_cast<const uint16_t*>(a.Y) + base, slab_elems * 2);
-    v16f accA[kRBMax];
-#pragma unroll
-    for (int i = 0; i < kRBMax; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) accA[i][v] = 0.0f;
+  const int64_t slab = blockIdx.x;
+  const int e = a.exps[slab];
+  const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
+  const int64_t base = slab * slab_elems;
+  const __amdgpu_buffer_rsrc_t rs =
+      SRC_F32 ? slab_rsrc(static_cast<const float*>(a.Y) + base, slab_elems * 4)
+              : slab_rsrc(static_cast<const uint16_t*>(a.Y) + base, slab_elems * 2);
 
-    // tiles are visited in the order (ct, i); each is loaded one step ahead
-    TileRaw<SRC_F32> buf[2];
-    if (!(SRC_F32 && DOQ) && myrb > 0) load_tile<SRC_F32>(rs, a, w, lr, 0, g, buf[0]);
+  // step s: column tile s / RBW, row block w + kBW (s % RBW)
+  TileRaw<SRC_F32> ring[kSlots];
+#pragma unroll
+  for (int k = 0; k + 1 < kSlots; ++k)
+    load_tile<SRC_F32, HALF>(rs, a, w + kBW * (k % RBW), lr, (k / RBW) * kCT, g, ring[k]);
+  // B2^T of column tile ct.  BF16 source: in b2[ct % 2], loaded one column
+  // tile ahead.  FP32 source (registers are short): one buffer, reloaded
+  // after the last product of the previous column tile
+  constexpr bool kB2Dbl = !SRC_F32;
+  v8bf b2[kB2Dbl ? 2 : 1][4];
+  load_b2(a, 0, lr, g, b2[0]);
+  if constexpr (DOQ) {
+    // B1^T for the whole slab, rows padded against bank conflicts
+    const int rowc = a.ldb1 / 8;
+    for (int l = threadIdx.x; l < 32 * rowc; l += kBThreads) {
+      const int k = l / rowc, cc = l - k * rowc;
+      *reinterpret_cast<uint4*>(b1s + k * ldb1s + 8 * cc) =
+          *reinterpret_cast<const uint4*>(a.B1t + static_cast<int64_t>(k) * a.ldb1 + 8 * cc);
+    }
+    __syncthreads();
+  }
 
-    for (int ct = 0; ct < nct; ++ct) {
-      const int c0 = ct * kCT;
-      v8bf b2[4];
+  v16f accA[RBW];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        b2[q] = as_v8bf(*reinterpret_cast<const uint4*>(
-            a.B2t + static_cast<int64_t>(lr) * a.ldb2 + c0 + 16 * q + 8 * g));
-      v16f accB[2];
+  for (int i = 0; i < RBW; ++i)
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) accB[s][v] = 0.0f;
+    for (int v = 0; v < 16; ++v) accA[i][v] = 0.0f;
+  v16f accB[2];
 
+  for (int s0 = 0; s0 < nsteps; s0 += kUnroll) {
+    static_for<kUnroll>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int s = s0 + u;
+      {
+        const int ct = s / RBW;
+        constexpr int i = u % RBW;           // s0 is a multiple of 2 RBW
+        constexpr int cb = kB2Dbl ? (u / RBW) % 2 : 0;   // ct % 2
+        const int rb = w + kBW * i;
+        const int c0 = ct * kCT;
+        if constexpr (i == 0) {
+          // the next column tile's B2^T, issued before this step's tile
+          if constexpr (kB2Dbl) load_b2(a, ct + 1 < nct ? ct + 1 : nct - 1, lr, g, b2[cb ^ 1]);
 #pragma unroll
-      for (int i = 0; i < kRBMax; ++i) {
-        if (i < myrb) {
-          const int rb = w + kBW * i;
-          // prefetch the next tile of this wave (the FP32-source sweep keeps
-          // one buffer: its raw tile is twice as large)
-          constexpr bool kPrefetch = !(SRC_F32 && DOQ);
-          if constexpr (kPrefetch) {
-            if (i + 1 < myrb)
-              load_tile<SRC_F32>(rs, a, rb + kBW, lr, c0, g, buf[(i + 1) & 1]);
-            else if (ct + 1 < nct)
-              load_tile<SRC_F32>(rs, a, w, lr, c0 + kCT, g, buf[(i + 1) & 1]);
-          } else {
-            load_tile<SRC_F32>(rs, a, rb, lr, c0, g, buf[i & 1]);
-          }
-          const TileRaw<SRC_F32>& cur = buf[i & 1];
-          uint4 yv[4];
+          for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if constexpr (SRC_F32) {
-              const float4 lo = cur.v[2 * q], hi = cur.v[2 * q + 1];
-              yv[q].x = pack2(lo.x * down, lo.y * down);
-              yv[q].y = pack2(lo.z * down, lo.w * down);
-              yv[q].z = pack2(hi.x * down, hi.y * down);
-              yv[q].w = pack2(hi.z * down, hi.w * down);
-              const int r = rb * 32 + lr, c = c0 + 16 * q + 8 * g;
-              if (r < a.I1 && c < a.I2) {
-                uint16_t* dst = a.Yb + base + static_cast<int64_t>(r) * a.I2 + c;
-                if (c + 8 <= a.I2 && (a.I2 & 7) == 0) {
-                  *reinterpret_cast<uint4*>(dst) = yv[q];
-                } else {   // 8-byte aligned rows; a half chunk stores 4 values
-                  *reinterpret_cast<uint2*>(dst) = make_uint2(yv[q].x, yv[q].y);
-                  if (c + 8 <= a.I2)
-                    *reinterpret_cast<uint2*>(dst + 4) = make_uint2(yv[q].z, yv[q].w);
-                }
+            for (int v = 0; v < 16; ++v) accB[h][v] = 0.0f;
+        }
+        {
+          const int sp = s + kSlots - 1;   // past the end: masked, no traffic
+          load_tile<SRC_F32, HALF>(rs, a, w + kBW * (sp % RBW), lr, (sp / RBW) * kCT, g,
+                                   ring[(u + kSlots - 1) % kSlots]);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // this step's loads are issued first
+        const TileRaw<SRC_F32>& cur = ring[u % kSlots];
+        // chunk by chunk, so that only one chunk's BF16 values are live:
+        // (first pass) round and store the copy; TA product; transposed copy
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint4 yv;
+          if constexpr (SRC_F32) {
+            const float4 lo = cur.v[2 * q], hi = cur.v[2 * q + 1];
+            yv.x = pack2(lo.x * down, lo.y * down);
+            yv.y = pack2(lo.z * down, lo.w * down);
+            yv.z = pack2(hi.x * down, hi.y * down);
+            yv.w = pack2(hi.z * down, hi.w * down);
+            const int r = rb * 32 + lr, c = c0 + 16 * q + 8 * g;
+            if (r < a.I1 && c < a.I2) {
+              uint16_t* dst = a.Yb + base + static_cast<int64_t>(r) * a.I2 + c;
+              if (c + 8 <= a.I2 && (a.I2 & 7) == 0) {
+                *reinterpret_cast<uint4*>(dst) = yv;
+              } else {   // 8-byte aligned rows; a half chunk stores 4 values
+                *reinterpret_cast<uint2*>(dst) = make_uint2(yv.x, yv.y);
+                if (c + 8 <= a.I2)
+                  *reinterpret_cast<uint2*>(dst + 4) = make_uint2(yv.z, yv.w);
               }
-            } else {
-              yv[q] = cur.v[q];
             }
+          } else {
+            yv = cur.v[q];
           }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            accA[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yv[q]), b2[q],
-                                                              accA[i], 0, 0, 0);
+          accA[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yv), b2[cb][q],
+                                                            accA[i], 0, 0, 0);
           if constexpr (DOQ) {
             // transposed copy: yt[col][row]
+            const uint32_t wds[4] = {yv.x, yv.y, yv.z, yv.w};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint32_t wds[4] = {yv[q].x, yv[q].y, yv[q].z, yv[q].w};
-#pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                const uint16_t h = static_cast<uint16_t>(wds[j >> 1] >> (16 * (j & 1)));
-                yt[(16 * q + 8 * g + j) * kYtStride + lr] = h;
-              }
+            for (int j = 0; j < 8; ++j) {
+              const uint16_t hv = static_cast<uint16_t>(wds[j >> 1] >> (16 * (j & 1)));
+              yt[(16 * q + 8 * g + j) * kYtStride + lr] = hv;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const v8bf b1 = as_v8bf(*reinterpret_cast<const uint4*>(
-                  a.B1t + static_cast<int64_t>(lr) * a.ldb1 + rb * 32 + 16 * h + 8 * g));
-#pragma unroll
-              for (int s = 0; s < 2; ++s) {
-                const v8bf yc = as_v8bf(*reinterpret_cast<const uint4*>(
-                    yt + (32 * s + lr) * kYtStride + 16 * h + 8 * g));
-                accB[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, yc, accB[s], 0, 0,
-                                                                  0);
-              }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           }
         }
-      }
-      // the step order is (ct, i) with i < myrb: when myrb is odd the
-      // buffer parity flips at the column-tile boundary
-      if (!(SRC_F32 && DOQ) && (myrb & 1)) {
-        const TileRaw<SRC_F32> t = buf[1];
-        buf[1] = buf[0];
-        buf[0] = t;
-      }
+        if constexpr (!kB2Dbl && i == RBW - 1)
+          load_b2(a, ct + 1 < nct ? ct + 1 : nct - 1, lr, g, b2[0]);
+        if constexpr (DOQ) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // rows past the slab hold zeros; their B1^T columns are read clamped
+          const int rbc = rb < nrb ? rb : nrb - 1;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const v8bf b1 = as_v8bf(*reinterpret_cast<const uint4*>(
+                b1s + lr * ldb1s + rbc * 32 + 16 * h + 8 * g));
+#pragma unroll
+            for (int sh = 0; sh < 2; ++sh) {
+              const v8bf yc = as_v8bf(*reinterpret_cast<const uint4*>(
+                  yt + (32 * sh + lr) * kYtStride + 16 * h + 8 * g));
+              accB[sh] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, yc, accB[sh], 0, 0,
+                                                                 0);
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-      if constexpr (DOQ) {
-        // TB partial of this wave (32 x 64) -> LDS; fixed-order sum over waves
+          if constexpr (i == RBW - 1) {
+            // TB partial of this wave (32 x 64) -> its own LDS region (the
+            // transposed tile is no longer needed); fixed-order sum over waves
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+            for (int sh = 0; sh < 2; ++sh)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int m = 8 * (v / 4) + 4 * g + (v % 4);
-            red[(w * 32 + m) * kCT + 32 * s + lr] = accB[s][v];
+              for (int v = 0; v < 16; ++v) {
+                const int m = 8 * (v / 4) + 4 * g + (v % 4);
+                red[(w * 32 + m) * kCT + 32 * sh + lr] = accB[sh][v];
+              }
+            __syncthreads();
+            for (int l = threadIdx.x; l < 32 * kCT; l += kBThreads) {
+              const int m = l / kCT, n = l % kCT;
+              float sum = 0.0f;
+#pragma unroll
+              for (int ww = 0; ww < kBW; ++ww) sum += red[(ww * 32 + m) * kCT + n];
+              if (m < a.K1 && c0 + n < a.I2)
+                a.TB[(slab * a.K1 + m) * a.I2 + c0 + n] = sum * up;
+            }
+            __syncthreads();
           }
-        __syncthreads();
-        for (int l = threadIdx.x; l < 32 * kCT; l += kBThreads) {
-          const int m = l / kCT, n = l % kCT;
-          float sum = 0.0f;
-#pragma unroll
-          for (int ww = 0; ww < kBW; ++ww) sum += red[(ww * 32 + m) * kCT + n];
-          if (m < a.K1 && c0 + n < a.I2)
-            a.TB[(slab * a.K1 + m) * a.I2 + c0 + n] = sum * up;
         }
-        __syncthreads();
       }
-    }
-    // TA rows of this wave's blocks
+      // keep the steps in program order: the scheduler must not move a
+      // step's loads ahead, where they would reuse registers still in flight
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  }
+  // TA rows of this wave's blocks
 #pragma unroll
-    for (int i = 0; i < kRBMax; ++i) {
-      const int rb = w + kBW * i;
-      if (rb < nrb) {
+  for (int i = 0; i < RBW; ++i) {
+    const int rb = w + kBW * i;
+    if (rb < nrb) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int m = 8 * (v / 4) + 4 * g + (v % 4);
-          const int r = rb * 32 + m;
-          if (r < a.I1 && lr < a.K2)
-            a.TA[(slab * a.I1 + r) * a.K2 + lr] = accA[i][v] * up;
-        }
+      for (int v = 0; v < 16; ++v) {
+        const int m = 8 * (v / 4) + 4 * g + (v % 4);
+        const int r = rb * 32 + m;
+        if (r < a.I1 && lr < a.K2)
+          a.TA[(slab * a.I1 + r) * a.K2 + lr] = accA[i][v] * up;
       }
     }
   }
@@ -368,11 +426,11 @@ __global__ void prep_bt_kernel(const float* B, int I, int K, uint16_t* Bt, int l
 
 int stats_grid(int64_t A) { return static_cast<int>(A < 1024 ? A : 1024); }
 
-template <bool SRC_F32, bool DOQ>
+template <bool SRC_F32, bool DOQ, bool HALF, int RBW>
 int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
-  auto k = bf16_stream_kernel<SRC_F32, DOQ>;
-  const size_t lds = DOQ ? static_cast<size_t>(kBW) * kCT * kYtStride * 2 +
-                               static_cast<size_t>(kBW) * 32 * kCT * 4
+  auto k = bf16_stream_kernel<SRC_F32, DOQ, HALF, RBW>;
+  const size_t lds = DOQ ? static_cast<size_t>(kBW) * kWaveLds +
+                               static_cast<size_t>(32) * (a.ldb1 + kB1Pad) * 2
                          : 0;
   if (lds > 0) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
@@ -385,6 +443,27 @@ int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
   return kOk;
 }
 
+template <bool SRC_F32, bool DOQ, bool HALF>
+int launch_bf_rbw(const BfArgs& a, int grid, hipStream_t s) {
+  // row-block steps per column tile: the blocks a wave owns, rounded up to 1, 2, 4
+  const int nrb = (a.I1 + 31) / 32;
+  const int per_wave = (nrb + kBW - 1) / kBW;
+  if (per_wave <= 1) return launch_bf<SRC_F32, DOQ, HALF, 1>(a, grid, s);
+  if (per_wave <= 2) return launch_bf<SRC_F32, DOQ, HALF, 2>(a, grid, s);
+  return launch_bf<SRC_F32, DOQ, HALF, 4>(a, grid, s);
+}
+
+template <bool SRC_F32, bool DOQ>
+int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
+  // only the BF16 source distinguishes rows that start 8-byte aligned
+  if constexpr (SRC_F32) {
+    return launch_bf_rbw<true, DOQ, false>(a, grid, s);
+  } else {
+    if ((a.I2 & 7) != 0) return launch_bf_rbw<false, DOQ, true>(a, grid, s);
+    return launch_bf_rbw<false, DOQ, false>(a, grid, s);
+  }
+}
+
 }  // namespace
 
 // Workspace of the BF16 passes (inside the streaming workspace): slab
@@ -395,9 +474,10 @@ size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
 }
 
 int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
-  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 || I2 > (1 << 30)) {
-    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0 and "
-              "sketch widths <= 32 (got %lld, %lld, %d, %d)",
+  // a slab's FP32 bytes must stay below the masked-load offset
+  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 || I1 * I2 * 4 > kOob - 64) {
+    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0, "
+              "I_{N-1} I_N < 2^29 and sketch widths <= 32 (got %lld, %lld, %d, %d)",
               kMaxI1, (long long)I1, (long long)I2, K1, K2);
     return kErrUnsupported;
   }
@@ -457,8 +537,11 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   }
   const int grid = static_cast<int>(c.A);   // one workgroup per slab
   ProfScope ps(stage, s);
-  if (B1) return from_f32 ? launch_bf<true, true>(a, grid, s) : launch_bf<false, true>(a, grid, s);
-  return from_f32 ? launch_bf<true, false>(a, grid, s) : launch_bf<false, false>(a, grid, s);
+  if (B1)
+    return from_f32 ? launch_bf_half<true, true>(a, grid, s)
+                    : launch_bf_half<false, true>(a, grid, s);
+  return from_f32 ? launch_bf_half<true, false>(a, grid, s)
+                  : launch_bf_half<false, false>(a, grid, s);
 }
 
 }  // namespace rt

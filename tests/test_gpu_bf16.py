@@ -97,7 +97,9 @@ SHAPES = [((12, 70, 104), (8, 9, 10)),     # ragged row block, partial column ti
           ((3, 33, 64), (3, 5, 32)),       # exactly one column tile, R~ = 32
           ((4, 5, 40, 48), (4, 5, 6, 7)),  # 4-way: slabs over two modes
           ((6, 50, 60), (6, 8, 9)),        # I_N % 8 == 4: half chunks at row ends
-          ((3, 40, 300), (3, 10, 30))]     # the learned-init workload's width
+          ((3, 40, 300), (3, 10, 30)),     # the learned-init workload's width
+          ((2, 800, 72), (2, 9, 10)),      # four row blocks per wave, the last masked
+          ((2, 1000, 36), (2, 7, 12))]     # four row blocks per wave, half chunks
 
 
 @pytest.mark.parametrize("dims,rt", SHAPES)

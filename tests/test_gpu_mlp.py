@@ -59,18 +59,21 @@ def normalized(G):
     return G / n.reshape((-1,) + (1,) * (G.ndim - 1)), n
 
 
-@pytest.mark.parametrize("hidden", [(128, 96), (1024, 1024)])
-def test_mlp_forward_matches_oracle(P, hidden):
-    G, net, params = setup(P, 501, 12, (20, 20, 20), 20, hidden)
+# batches of at most 8 cores take the split-K product path
+@pytest.mark.parametrize("hidden,B", [((128, 96), 12), ((1024, 1024), 12),
+                                      ((1024, 1024), 1), ((128, 96), 3)])
+def test_mlp_forward_matches_oracle(P, hidden, B):
+    G, net, params = setup(P, 501, B, (20, 20, 20), 20, hidden)
     V = net.forward(torch.from_numpy(G).cuda()).cpu().numpy().astype(np.float64)
     Gh, nrm = normalized(G)
-    Y, _ = M.forward(params, Gh.reshape(12, -1), bf16=bf16_round)
+    Y, _ = M.forward(params, Gh.reshape(B, -1), bf16=bf16_round)
     want = Y * (nrm ** (1.0 / 3.0))[:, None]
     assert rel(V, want) <= 2e-3
 
 
-def test_mlp_gradients_match_oracle(P):
-    B, cd, R = 16, (20, 20, 20), 20
+@pytest.mark.parametrize("B", [16, 4])
+def test_mlp_gradients_match_oracle(P, B):
+    cd, R = (20, 20, 20), 20
     G, net, params = setup(P, 502, B, cd, R, (128, 96))
     loss, gW, gb = net.grad(torch.from_numpy(G).cuda())
     Gh, _ = normalized(G)
