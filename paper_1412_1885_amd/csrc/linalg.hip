@@ -391,8 +391,9 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
     }
     double off = block_sum(p, red);
     if (off <= thresh) break;
+    const int hp = np / 2;
     for (int r = 0; r < np - 1; ++r) {
-      if (t < np / 2) {
+      if (t < hp) {
         int a = (t == 0) ? 0 : 1 + ((t - 1 + r) % (np - 1));
         int q = 1 + ((np - 2 - t + r) % (np - 1));
         int lo = a < q ? a : q, hi = a < q ? q : a;
@@ -413,28 +414,36 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
         cs[t][1] = s;
       }
       __syncthreads();
-      // rows: S <- J^T S (lane = column j, waves take pairs in turn)
-      const int jl = t & 63;
-      for (int pi = t >> 6; pi < np / 2; pi += kEigThreads / 64) {
-        const int p0 = pr[pi][0], q0 = pr[pi][1];
-        if (q0 >= n || jl >= n) continue;
-        const double c = cs[pi][0], s = cs[pi][1];
-        const double xp = S[p0][jl], xq = S[q0][jl];
-        S[p0][jl] = c * xp - s * xq;
-        S[q0][jl] = s * xp + c * xq;
+      // S <- J^T S J in place: the pairs partition the indices, so each
+      // thread owns a 2 x 2 block {lo_a, hi_a} x {lo_b, hi_b} (an index
+      // >= n is the dummy player: its row and column do not exist)
+      for (int blk = t; blk < hp * hp; blk += kEigThreads) {
+        const int pa = blk / hp, pb = blk - pa * hp;
+        const int i0 = pr[pa][0], i1 = pr[pa][1], j0 = pr[pb][0], j1 = pr[pb][1];
+        const double ca = cs[pa][0], sa = cs[pa][1], cb = cs[pb][0], sb = cs[pb][1];
+        const bool r1 = i1 < n, c1 = j1 < n;
+        const double b00 = S[i0][j0];
+        const double b01 = c1 ? S[i0][j1] : 0.0;
+        const double b10 = r1 ? S[i1][j0] : 0.0;
+        const double b11 = (r1 && c1) ? S[i1][j1] : 0.0;
+        // rows: J^T
+        const double x00 = ca * b00 - sa * b10, x01 = ca * b01 - sa * b11;
+        const double x10 = sa * b00 + ca * b10, x11 = sa * b01 + ca * b11;
+        // columns: J
+        S[i0][j0] = cb * x00 - sb * x01;
+        if (c1) S[i0][j1] = sb * x00 + cb * x01;
+        if (r1) S[i1][j0] = cb * x10 - sb * x11;
+        if (r1 && c1) S[i1][j1] = sb * x10 + cb * x11;
       }
-      __syncthreads();
-      // columns: S <- S J, V <- V J
-      for (int pi = t >> 6; pi < np / 2; pi += kEigThreads / 64) {
-        const int p0 = pr[pi][0], q0 = pr[pi][1];
-        if (q0 >= n || jl >= n) continue;
-        const double c = cs[pi][0], s = cs[pi][1];
-        const double xp = S[jl][p0], xq = S[jl][q0];
-        S[jl][p0] = c * xp - s * xq;
-        S[jl][q0] = s * xp + c * xq;
-        const double vp = V[jl][p0], vq = V[jl][q0];
-        V[jl][p0] = c * vp - s * vq;
-        V[jl][q0] = s * vp + c * vq;
+      // V <- V J: each thread owns one row's pair of columns
+      for (int l = t; l < n * hp; l += kEigThreads) {
+        const int i = l / hp, pb = l - i * hp;
+        const int j0 = pr[pb][0], j1 = pr[pb][1];
+        if (j1 >= n) continue;
+        const double cb = cs[pb][0], sb = cs[pb][1];
+        const double vp = V[i][j0], vq = V[i][j1];
+        V[i][j0] = cb * vp - sb * vq;
+        V[i][j1] = sb * vp + cb * vq;
       }
       __syncthreads();
     }

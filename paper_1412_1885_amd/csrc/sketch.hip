@@ -103,12 +103,101 @@ __global__ __launch_bounds__(kThreads) void sketch_gemm_kernel(
   }
 }
 
+// FP32 form of the split-K sketch product on the matrix cores
+// (v_mfma_f32_32x32x2_f32): a workgroup owns 128 rows i (32 per wavefront)
+// and all R <= 32 columns r over its range of k; k goes in chunks of 32 staged
+// through LDS with the same coalesced loads as above.  Exact FP32 products,
+// FP32 accumulation.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(kThreads) void sketch_mfma_kernel(
+    const float* __restrict__ Tm, const float* __restrict__ W, float* __restrict__ part,
+    int64_t A, int64_t I, int64_t C, int R, int64_t kper) {
+  constexpr int BI = 128, BK = 32;
+  static_assert(kThreads == 256, "staging maps");
+  __shared__ float ts[BK][BI + 1];
+  __shared__ float ws[BK][32];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lr = lane & 31, g = lane >> 5;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * BI;
+  const int64_t K = A * C;
+  const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kper;
+  const int64_t k1 = (k0 + kper < K) ? k0 + kper : K;
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  // stage kb is loaded into registers one stage ahead of its products
+  constexpr int kTv = BK * BI / kThreads, kWv = BK * 32 / kThreads;
+  float tv[kTv], wv[kWv];
+  auto load_stage = [&](int64_t kb) __attribute__((always_inline)) {
+    if (C == 1) {
+      // rows i contiguous: thread t takes row i0 + t % 128, k = kb + t / 128 + 2m
+      const int64_t i = i0 + (t & (BI - 1));
+#pragma unroll
+      for (int m = 0; m < kTv; ++m) {
+        const int64_t k = kb + (t >> 7) + 2 * m;
+        tv[m] = (k < k1 && i < I) ? Tm[k * I + i] : 0.0f;
+      }
+    } else {
+      // c contiguous: thread t takes k = kb + t % 32, rows t / 32 + 8m; one
+      // division per stage
+      const int64_t k = kb + (t & (BK - 1));
+      const bool kok = k < k1;
+      const int64_t a = kok ? k / C : 0;
+      const float* base = Tm + (a * I) * C + (kok ? k - a * C : 0);
+#pragma unroll
+      for (int m = 0; m < kTv; ++m) {
+        const int64_t i = i0 + (t >> 5) + 8 * m;
+        tv[m] = (kok && i < I) ? base[i * C] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kWv; ++m) {
+      const int l = t + kThreads * m;
+      const int64_t k = kb + (l >> 5);
+      const int r = l & 31;
+      wv[m] = (k < k1 && r < R) ? W[k * R + r] : 0.0f;
+    }
+  };
+  if (k0 < k1) load_stage(k0);
+  for (int64_t kb = k0; kb < k1; kb += BK) {
+    __syncthreads();   // the previous stage's products have read the tiles
+    if (C == 1) {
+#pragma unroll
+      for (int m = 0; m < kTv; ++m) ts[(t >> 7) + 2 * m][t & (BI - 1)] = tv[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < kTv; ++m) ts[t & (BK - 1)][(t >> 5) + 8 * m] = tv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kWv; ++m) {
+      const int l = t + kThreads * m;
+      ws[l >> 5][l & 31] = wv[m];
+    }
+    __syncthreads();
+    if (kb + BK < k1) load_stage(kb + BK);   // in flight during the products
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ts[kk + g][32 * w + lr], ws[kk + g][lr],
+                                                 acc, 0, 0, 0);
+  }
+  // acc[v]: row 8 (v / 4) + 4 g + v % 4 of this wave's 32, column lr
+  if (lr < R) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t i = i0 + 32 * w + 8 * (v / 4) + 4 * g + (v % 4);
+      if (i < I) part[(static_cast<int64_t>(blockIdx.y) * I + i) * R + lr] = acc[v];
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void sum_splits_kernel(
     const T* __restrict__ part, T* __restrict__ out, int64_t n, int S) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (idx >= n) return;
   T acc = T(0);
+#pragma unroll 8
   for (int s = 0; s < S; ++s) acc += part[s * n + idx];  // fixed order
   out[idx] = acc;
 }
@@ -159,6 +248,39 @@ __global__ __launch_bounds__(kThreads) void ttm_small_c_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (kb + i < K && cb + j < C) out[(a * K + kb + i) * C + cb + j] = acc[i][j];
+}
+
+// FP32 form of ttm_small_c for C, K <= 32 on the matrix cores: one
+// workgroup per a computes the 32 x 32 block out[a] = M^T X[a] with
+// v_mfma_f32_32x32x2_f32 (A operand M^T: lane l holds M[i][l % 32]; B
+// operand X[a]: lane l holds X[a][i][l % 32]; i = the pair of rows of the
+// step, by l / 32).  The four wavefronts take interleaved row pairs and
+// their sums meet in LDS in a fixed order.
+__global__ __launch_bounds__(kThreads) void ttm_small_mfma_kernel(
+    const float* __restrict__ X, const float* __restrict__ M, float* __restrict__ out,
+    int64_t A, int64_t I, int C, int K) {
+  __shared__ float red[4][32][33];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lr = lane & 31, g = lane >> 5;
+  const int64_t a = blockIdx.x;
+  const float* xa = X + a * I * C;
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll 8
+  for (int64_t i0 = 2 * w; i0 < I; i0 += 8) {
+    const int64_t i = i0 + g;
+    const float mv = (i < I && lr < K) ? M[i * K + lr] : 0.0f;
+    const float xv = (i < I && lr < C) ? xa[i * C + lr] : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(mv, xv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) red[w][8 * (v / 4) + 4 * g + (v % 4)][lr] = acc[v];
+  __syncthreads();
+  for (int l = t; l < K * C; l += kThreads) {
+    const int k = l / C, c = l % C;
+    out[(a * K + k) * C + c] = (red[0][k][c] + red[1][k][c]) + (red[2][k][c] + red[3][k][c]);
+  }
 }
 
 // out[c][r] = in[r][c] for an R x C matrix (tiled through LDS).
@@ -256,6 +378,46 @@ int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
   return kOk;
 }
 
+// FP32, R <= 32: the matrix-core form (same split-K partials and sum).
+template <>
+int launch_sketch_gemm<float>(const float* Tm, const float* W, float* Z, float* part,
+                              int64_t A, int64_t I, int64_t C, int R, hipStream_t s) {
+  if (R > 32) {
+    const int64_t K = A * C;
+    const int64_t S = sketch_gemm_splits(I, K);
+    int64_t kper = ceil_div(ceil_div(K, S), 32) * 32;
+    const int64_t Sused = ceil_div(K, kper);
+    dim3 grid(static_cast<unsigned>(ceil_div(I, 64)), static_cast<unsigned>(Sused));
+    if (R > 64) {
+      set_error("sketch width %d exceeds 64", R);
+      return kErrUnsupported;
+    }
+    hipLaunchKernelGGL((sketch_gemm_kernel<float, 64>), grid, dim3(kThreads), 0, s, Tm, W,
+                       part, A, I, C, R, kper);
+    RT_LAUNCH_CHECK("sketch_gemm");
+    const int64_t n = I * R;
+    hipLaunchKernelGGL(sum_splits_kernel<float>,
+                       dim3(static_cast<unsigned>(ceil_div(n, kThreads))), dim3(kThreads),
+                       0, s, part, Z, n, static_cast<int>(Sused));
+    RT_LAUNCH_CHECK("sketch_gemm sum");
+    return kOk;
+  }
+  const int64_t K = A * C;
+  const int64_t S = sketch_gemm_splits(I, K);   // the partial buffer holds S splits
+  int64_t kper = ceil_div(ceil_div(K, S), 32) * 32;
+  const int64_t Sused = ceil_div(K, kper);
+  dim3 grid(static_cast<unsigned>(ceil_div(I, 128)), static_cast<unsigned>(Sused));
+  hipLaunchKernelGGL(sketch_mfma_kernel, grid, dim3(kThreads), 0, s, Tm, W, part, A, I, C,
+                     R, kper);
+  RT_LAUNCH_CHECK("sketch_mfma");
+  const int64_t n = I * R;
+  hipLaunchKernelGGL(sum_splits_kernel<float>,
+                     dim3(static_cast<unsigned>(ceil_div(n, kThreads))), dim3(kThreads), 0,
+                     s, part, Z, n, static_cast<int>(Sused));
+  RT_LAUNCH_CHECK("sketch_mfma sum");
+  return kOk;
+}
+
 template <typename T>
 int launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t s) {
   dim3 grid(static_cast<unsigned>(ceil_div(C, 32)), static_cast<unsigned>(ceil_div(R, 32)));
@@ -281,6 +443,14 @@ int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
     set_error("ttm_small_c: C=%d K=%d unsupported", C, K);
     return kErrUnsupported;
   }
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (C <= 32 && K <= 32) {
+      hipLaunchKernelGGL(ttm_small_mfma_kernel, dim3(static_cast<unsigned>(A)),
+                         dim3(kThreads), 0, s, X, M, out, A, I, C, K);
+      RT_LAUNCH_CHECK("ttm_small_mfma");
+      return kOk;
+    }
+  }
   hipLaunchKernelGGL(ttm_small_c_kernel<T>, dim3(static_cast<unsigned>(A)),
                      dim3(kThreads), 0, s, X, M, out, A, I, C, K);
   RT_LAUNCH_CHECK("ttm_small_c");
@@ -290,8 +460,6 @@ int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
 #define RT_INST(T)                                                              \
   template int launch_expand<T>(const T*, const T*, T*, int64_t, int64_t, int,  \
                                 int64_t, hipStream_t);                          \
-  template int launch_sketch_gemm<T>(const T*, const T*, T*, T*, int64_t,       \
-                                     int64_t, int64_t, int, hipStream_t);       \
   template int launch_ttm_small_c<T>(const T*, const T*, T*, int64_t, int64_t,  \
                                      int, int, hipStream_t);                    \
   template int launch_transpose<T>(const T*, T*, int64_t, int64_t, hipStream_t); \
@@ -300,5 +468,7 @@ int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
 RT_INST(float)
 RT_INST(double)
 #undef RT_INST
+template int launch_sketch_gemm<double>(const double*, const double*, double*, double*,
+                                        int64_t, int64_t, int64_t, int, hipStream_t);
 
 }  // namespace rt
