@@ -310,13 +310,15 @@ int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
  * the recorded events and returns per-stage totals.  Host-side only; the
  * events are created by the library (no device memory).
  * Stages (each brackets the launches named): 0 = the streaming kernel of the
- * first sweep (the one that also converts to BF16 in the precision form),
+ * first sweep,
  * 1 = the streaming kernel of later sweeps, 2 = the core pass's streaming
  * kernel, 3 = intermediate contractions and sketch products, 4 = QR,
  * 5 = truncation (Gram, eig, rotation), 6 = FFCP, 7 = per-slab statistics
- * pass of the precision form (exponents, ||Y||^2).
+ * pass of the precision form (exponents, ||Y||^2), 8 = the precision form's
+ * FP32 -> BF16 conversion (the first sweep's streaming kernel then reads the
+ * BF16 copy).
  */
-#define RT_PROFILE_STAGES 8
+#define RT_PROFILE_STAGES 9
 typedef struct {
   double ms[RT_PROFILE_STAGES];   /* summed event time per stage          */
   int64_t count[RT_PROFILE_STAGES]; /* number of bracketed launches        */

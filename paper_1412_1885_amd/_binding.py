@@ -369,11 +369,11 @@ def stream_pass(Y3, B2, B1=None, stream=None):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9)]
 
 
 PROFILE_STAGES = ("first_pass", "sweep_pass", "core_pass", "contract", "qr",
-                  "truncate", "ffcp", "stats")
+                  "truncate", "ffcp", "stats", "convert")
 
 
 def profile_enable(on=True):
@@ -384,7 +384,7 @@ def profile_read():
     """Per-stage {name: (total_ms, launches)} of the bracketed stages."""
     p = Profile()
     _check(lib().rt_profile_read(ctypes.byref(p)))
-    return {PROFILE_STAGES[i]: (p.ms[i], int(p.count[i])) for i in range(8)}
+    return {PROFILE_STAGES[i]: (p.ms[i], int(p.count[i])) for i in range(len(PROFILE_STAGES))}
 
 
 def cp_fit_dense(Y, A, lam=None, stream=None):

@@ -13,7 +13,8 @@ enum ProfStage {
   kStageQr = 4,
   kStageTruncate = 5,
   kStageFfcp = 6,
-  kStageStats = 7
+  kStageStats = 7,
+  kStageConvert = 8
 };
 
 bool prof_enabled();

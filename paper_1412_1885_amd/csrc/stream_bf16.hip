@@ -13,11 +13,12 @@
 // The scale is exact (a power of two), keeps each slab's largest entries in
 // [1, 2) and its small entries out of the BF16 subnormal range.
 //
-// Passes.  The first pass of a call (FP32 input) reads FP32, rounds, writes
-// the BF16 copy and feeds the rounded values to the matrix cores in the same
-// kernel; ||Y||^2, the non-finite flag and the slab exponents come from a
-// statistics pass before it.  Later sweeps and the core pass read the BF16
-// copy.
+// Passes.  The first pass of a call (FP32 input) computes ||Y||^2, the
+// non-finite flag and the slab exponents in a statistics pass, then writes
+// the scaled BF16 copy with a conversion kernel of many small workgroups
+// (its HBM write stream overlaps its read stream only with that many
+// requests in flight); every contraction, of every sweep and of the core
+// pass, reads the BF16 copy.
 //
 // Data path (one workgroup of 8 wavefronts per slab).  Wave w owns the
 // 32-row blocks w, w+8, w+16, w+24 (I1 <= 1024) and walks the slab in
@@ -35,7 +36,7 @@
 // Latency.  The vector-memory counter completes in issue order, so a wait
 // for any load also waits for every load issued before it.  Tiles are
 // loaded several steps ahead into a statically indexed ring of registers
-// (FP32 source: one tile ahead; BF16: three), B1^T sits in LDS for the whole
+// (three tiles ahead), B1^T sits in LDS for the whole
 // slab and B2^T of the next column tile is loaded one column tile ahead,
 // before that step's tile, so no wait inside the loop stalls on a tile
 // that is not yet needed.
@@ -66,8 +67,7 @@ constexpr int kUnroll = 8;             // steps per loop trip: two column tiles 
 static_assert(kCT * kYtStride * 2 <= kWaveLds, "transposed tile fits the wave's region");
 
 struct BfArgs {
-  const void* Y;          // FP32 (first pass) or BF16 bit patterns
-  uint16_t* Yb;           // BF16 copy written by the first pass
+  const uint16_t* Y;      // BF16 bit patterns (the scaled copy or the caller's)
   const int32_t* exps;    // per-slab exponent
   int64_t A;
   int I1, I2;
@@ -86,16 +86,8 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
          (static_cast<uint32_t>(f32_to_bf16_rne(hi)) << 16);
 }
 
-// Raw operands of one 32 x 64 tile for one lane: 4 chunks of 8 values,
-// FP32 (first pass) or BF16.
-template <bool SRC_F32>
-struct TileRaw;
-template <>
-struct TileRaw<true> {
-  float4 v[8];
-};
-template <>
-struct TileRaw<false> {
+// Operands of one 32 x 64 tile for one lane: 4 chunks of 8 BF16 values.
+struct Tile {
   uint4 v[4];
 };
 
@@ -116,28 +108,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64
 // offset past the slab, so the hardware returns zeros without branches.
 // HALF (BF16 source, I2 % 8 == 4): rows start 8-byte aligned, two 8-byte
 // loads per chunk, the second absent in the half chunk at a row's end.
-template <bool SRC_F32, bool HALF>
+template <bool HALF>
 __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArgs& a,
-                                          int rb, int lr, int c0, int g,
-                                          TileRaw<SRC_F32>& t) {
-  constexpr int kEl = SRC_F32 ? 4 : 2;
+                                          int rb, int lr, int c0, int g, Tile& t) {
   const int r = rb * 32 + lr;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = c0 + 16 * q + 8 * g;
     const bool ok = r < a.I1 && c < a.I2;   // I2 % 4 == 0
     const bool full = ok && c + 8 <= a.I2;  // else only 4 of the 8 columns exist
-    // (r * I2 + c) * kEl < slab bytes < 2^31 whenever ok; clamped otherwise
-    const int off = ok ? ((ok ? r : 0) * a.I2 + (ok ? c : 0)) * kEl : kOob;
-    if constexpr (SRC_F32) {
-      // rows start 16-byte aligned (I2 % 4 == 0)
-      const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-      const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(rs, full ? off + 16 : kOob, 0, 0);
-      t.v[2 * q] = make_float4(__uint_as_float(lo.x), __uint_as_float(lo.y),
-                               __uint_as_float(lo.z), __uint_as_float(lo.w));
-      t.v[2 * q + 1] = make_float4(__uint_as_float(hi.x), __uint_as_float(hi.y),
-                                   __uint_as_float(hi.z), __uint_as_float(hi.w));
-    } else if constexpr (!HALF) {
+    // (r * I2 + c) * 2 < slab bytes < 2^31 whenever ok; clamped otherwise
+    const int off = ok ? ((ok ? r : 0) * a.I2 + (ok ? c : 0)) * 2 : kOob;
+    if constexpr (!HALF) {
       const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       t.v[q] = make_uint4(v.x, v.y, v.z, v.w);
     } else {
@@ -168,10 +150,10 @@ __device__ __forceinline__ void load_b2(const BfArgs& a, int ct, int lr, int g, 
 
 // RBW: steps per column tile (the row blocks a wave owns, rounded up to 1, 2
 // or 4); with it every register array below is indexed statically.
-template <bool SRC_F32, bool DOQ, bool HALF, int RBW>
+template <bool DOQ, bool HALF, int RBW>
 __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   extern __shared__ __align__(16) char smem[];
-  constexpr int kSlots = SRC_F32 ? 2 : 4;   // tiles in registers: current + in flight
+  constexpr int kSlots = 4;   // tiles in registers: the current one + three in flight
   static_assert((RBW == 1 || RBW == 2 || RBW == 4) && RBW <= kRBMax, "row blocks");
   static_assert(kUnroll % kSlots == 0 && kUnroll % (2 * RBW) == 0, "static indexing");
   const int lane = threadIdx.x & 63;
@@ -193,22 +175,17 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   // live across slabs
   const int64_t slab = blockIdx.x;
   const int e = a.exps[slab];
-  const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
+  const float up = ldexpf(1.0f, e);
   const int64_t base = slab * slab_elems;
-  const __amdgpu_buffer_rsrc_t rs =
-      SRC_F32 ? slab_rsrc(static_cast<const float*>(a.Y) + base, slab_elems * 4)
-              : slab_rsrc(static_cast<const uint16_t*>(a.Y) + base, slab_elems * 2);
+  const __amdgpu_buffer_rsrc_t rs = slab_rsrc(a.Y + base, slab_elems * 2);
 
   // step s: column tile s / RBW, row block w + kBW (s % RBW)
-  TileRaw<SRC_F32> ring[kSlots];
+  Tile ring[kSlots];
 #pragma unroll
   for (int k = 0; k + 1 < kSlots; ++k)
-    load_tile<SRC_F32, HALF>(rs, a, w + kBW * (k % RBW), lr, (k / RBW) * kCT, g, ring[k]);
-  // B2^T of column tile ct.  BF16 source: in b2[ct % 2], loaded one column
-  // tile ahead.  FP32 source (registers are short): one buffer, reloaded
-  // after the last product of the previous column tile
-  constexpr bool kB2Dbl = !SRC_F32;
-  v8bf b2[kB2Dbl ? 2 : 1][4];
+    load_tile<HALF>(rs, a, w + kBW * (k % RBW), lr, (k / RBW) * kCT, g, ring[k]);
+  // B2^T of column tile ct in b2[ct % 2], loaded one column tile ahead
+  v8bf b2[2][4];
   load_b2(a, 0, lr, g, b2[0]);
   if constexpr (DOQ) {
     // B1^T for the whole slab, rows padded against bank conflicts
@@ -235,12 +212,12 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
       {
         const int ct = s / RBW;
         constexpr int i = u % RBW;           // s0 is a multiple of 2 RBW
-        constexpr int cb = kB2Dbl ? (u / RBW) % 2 : 0;   // ct % 2
+        constexpr int cb = (u / RBW) % 2;   // ct % 2
         const int rb = w + kBW * i;
         const int c0 = ct * kCT;
         if constexpr (i == 0) {
           // the next column tile's B2^T, issued before this step's tile
-          if constexpr (kB2Dbl) load_b2(a, ct + 1 < nct ? ct + 1 : nct - 1, lr, g, b2[cb ^ 1]);
+          load_b2(a, ct + 1 < nct ? ct + 1 : nct - 1, lr, g, b2[cb ^ 1]);
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -248,36 +225,15 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
         }
         {
           const int sp = s + kSlots - 1;   // past the end: masked, no traffic
-          load_tile<SRC_F32, HALF>(rs, a, w + kBW * (sp % RBW), lr, (sp / RBW) * kCT, g,
-                                   ring[(u + kSlots - 1) % kSlots]);
+          load_tile<HALF>(rs, a, w + kBW * (sp % RBW), lr, (sp / RBW) * kCT, g,
+                          ring[(u + kSlots - 1) % kSlots]);
         }
         __builtin_amdgcn_sched_barrier(0);   // this step's loads are issued first
-        const TileRaw<SRC_F32>& cur = ring[u % kSlots];
-        // chunk by chunk, so that only one chunk's BF16 values are live:
-        // (first pass) round and store the copy; TA product; transposed copy
+        const Tile& cur = ring[u % kSlots];
+        // chunk by chunk: TA product, then the transposed copy
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          uint4 yv;
-          if constexpr (SRC_F32) {
-            const float4 lo = cur.v[2 * q], hi = cur.v[2 * q + 1];
-            yv.x = pack2(lo.x * down, lo.y * down);
-            yv.y = pack2(lo.z * down, lo.w * down);
-            yv.z = pack2(hi.x * down, hi.y * down);
-            yv.w = pack2(hi.z * down, hi.w * down);
-            const int r = rb * 32 + lr, c = c0 + 16 * q + 8 * g;
-            if (r < a.I1 && c < a.I2) {
-              uint16_t* dst = a.Yb + base + static_cast<int64_t>(r) * a.I2 + c;
-              if (c + 8 <= a.I2 && (a.I2 & 7) == 0) {
-                *reinterpret_cast<uint4*>(dst) = yv;
-              } else {   // 8-byte aligned rows; a half chunk stores 4 values
-                *reinterpret_cast<uint2*>(dst) = make_uint2(yv.x, yv.y);
-                if (c + 8 <= a.I2)
-                  *reinterpret_cast<uint2*>(dst + 4) = make_uint2(yv.z, yv.w);
-              }
-            }
-          } else {
-            yv = cur.v[q];
-          }
+          const uint4 yv = cur.v[q];
           accA[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yv), b2[cb][q],
                                                             accA[i], 0, 0, 0);
           if constexpr (DOQ) {
@@ -290,8 +246,6 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
             }
           }
         }
-        if constexpr (!kB2Dbl && i == RBW - 1)
-          load_b2(a, ct + 1 < nct ? ct + 1 : nct - 1, lr, g, b2[0]);
         if constexpr (DOQ) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -415,6 +369,39 @@ __global__ __launch_bounds__(256) void slab_stats_kernel(const void* Y, int64_t 
   if (t == 0) partial[blockIdx.x] = acc;
 }
 
+// The BF16 copy of an FP32 input: Yb = bf16_rne(Y * 2^-e_a) per slab a.
+// Slab a is row blockIdx.y of the grid; each thread converts four groups of
+// 4 consecutive values (16-byte loads, 8-byte stores), consecutive threads
+// on consecutive groups, so every wavefront instruction moves one
+// contiguous 1 KB (load) / 512 B (store) span.  Many small workgroups keep
+// enough loads and stores in flight to overlap the two streams.
+constexpr int kCvtThreads = 256, kCvtGroups = 4;
+
+__global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* Y,
+                                                                    uint16_t* Yb,
+                                                                    const int32_t* exps,
+                                                                    int64_t slab) {
+  const int64_t a = blockIdx.y;
+  const float down = ldexpf(1.0f, -exps[a]);
+  const int64_t n4 = slab / 4;   // slab % 4 == 0
+  const float4* src = reinterpret_cast<const float4*>(Y + a * slab);
+  uint2* dst = reinterpret_cast<uint2*>(Yb + a * slab);
+  const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kCvtThreads * kCvtGroups) + threadIdx.x;
+  float4 v[kCvtGroups];
+#pragma unroll
+  for (int u = 0; u < kCvtGroups; ++u) {
+    const int64_t gi = g0 + u * kCvtThreads;
+    v[u] = gi < n4 ? src[gi] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+#pragma unroll
+  for (int u = 0; u < kCvtGroups; ++u) {
+    const int64_t gi = g0 + u * kCvtThreads;
+    if (gi < n4)
+      dst[gi] = make_uint2(pack2(v[u].x * down, v[u].y * down),
+                           pack2(v[u].z * down, v[u].w * down));
+  }
+}
+
 // Bt[k][c] = bf16_rne(B[c][k]) for k < K, c < I; zero in the padding
 // (k < 32, c < ld).
 __global__ void prep_bt_kernel(const float* B, int I, int K, uint16_t* Bt, int ld) {
@@ -426,9 +413,9 @@ __global__ void prep_bt_kernel(const float* B, int I, int K, uint16_t* Bt, int l
 
 int stats_grid(int64_t A) { return static_cast<int>(A < 1024 ? A : 1024); }
 
-template <bool SRC_F32, bool DOQ, bool HALF, int RBW>
+template <bool DOQ, bool HALF, int RBW>
 int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
-  auto k = bf16_stream_kernel<SRC_F32, DOQ, HALF, RBW>;
+  auto k = bf16_stream_kernel<DOQ, HALF, RBW>;
   const size_t lds = DOQ ? static_cast<size_t>(kBW) * kWaveLds +
                                static_cast<size_t>(32) * (a.ldb1 + kB1Pad) * 2
                          : 0;
@@ -443,25 +430,21 @@ int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
   return kOk;
 }
 
-template <bool SRC_F32, bool DOQ, bool HALF>
+template <bool DOQ, bool HALF>
 int launch_bf_rbw(const BfArgs& a, int grid, hipStream_t s) {
   // row-block steps per column tile: the blocks a wave owns, rounded up to 1, 2, 4
   const int nrb = (a.I1 + 31) / 32;
   const int per_wave = (nrb + kBW - 1) / kBW;
-  if (per_wave <= 1) return launch_bf<SRC_F32, DOQ, HALF, 1>(a, grid, s);
-  if (per_wave <= 2) return launch_bf<SRC_F32, DOQ, HALF, 2>(a, grid, s);
-  return launch_bf<SRC_F32, DOQ, HALF, 4>(a, grid, s);
+  if (per_wave <= 1) return launch_bf<DOQ, HALF, 1>(a, grid, s);
+  if (per_wave <= 2) return launch_bf<DOQ, HALF, 2>(a, grid, s);
+  return launch_bf<DOQ, HALF, 4>(a, grid, s);
 }
 
-template <bool SRC_F32, bool DOQ>
+template <bool DOQ>
 int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
-  // only the BF16 source distinguishes rows that start 8-byte aligned
-  if constexpr (SRC_F32) {
-    return launch_bf_rbw<true, DOQ, false>(a, grid, s);
-  } else {
-    if ((a.I2 & 7) != 0) return launch_bf_rbw<false, DOQ, true>(a, grid, s);
-    return launch_bf_rbw<false, DOQ, false>(a, grid, s);
-  }
+  // rows that start 8-byte aligned (I2 % 8 == 4) take the half-chunk loads
+  if ((a.I2 & 7) != 0) return launch_bf_rbw<DOQ, true>(a, grid, s);
+  return launch_bf_rbw<DOQ, false>(a, grid, s);
 }
 
 }  // namespace
@@ -515,10 +498,24 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
                        B1, static_cast<int>(c.I1), K1, B1t, static_cast<int>(l1));
     RT_LAUNCH_CHECK("prep B1");
   }
+  if (first && !c.bf16_input) {
+    // the scaled BF16 copy, then every contraction reads it
+    const int64_t slab = c.I1 * c.I2;
+    const int64_t per_block = static_cast<int64_t>(kCvtThreads) * kCvtGroups * 4;
+    if (c.A > 65535) {
+      set_error("BF16 conversion: too many slabs (%lld)", (long long)c.A);
+      return kErrUnsupported;
+    }
+    ProfScope ps(kStageConvert, s);
+    hipLaunchKernelGGL(bf16_convert_kernel,
+                       dim3(static_cast<unsigned>((slab + per_block - 1) / per_block),
+                            static_cast<unsigned>(c.A)),
+                       dim3(kCvtThreads), 0, s, static_cast<const float*>(c.y), c.ybf16,
+                       exps, slab);
+    RT_LAUNCH_CHECK("bf16 convert");
+  }
   BfArgs a{};
-  const bool from_f32 = first && !c.bf16_input;
-  a.Y = from_f32 ? c.y : static_cast<const void*>(c.ybf16);
-  a.Yb = from_f32 ? c.ybf16 : nullptr;
+  a.Y = c.ybf16;
   a.exps = exps;
   a.A = c.A;
   a.I1 = static_cast<int>(c.I1);
@@ -537,11 +534,8 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   }
   const int grid = static_cast<int>(c.A);   // one workgroup per slab
   ProfScope ps(stage, s);
-  if (B1)
-    return from_f32 ? launch_bf_half<true, true>(a, grid, s)
-                    : launch_bf_half<false, true>(a, grid, s);
-  return from_f32 ? launch_bf_half<true, false>(a, grid, s)
-                  : launch_bf_half<false, false>(a, grid, s);
+  if (B1) return launch_bf_half<true>(a, grid, s);
+  return launch_bf_half<false>(a, grid, s);
 }
 
 }  // namespace rt
