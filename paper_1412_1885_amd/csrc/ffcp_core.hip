@@ -261,9 +261,17 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
   double* X1;
   double* W1;
   double* W2;
+  // The core in LDS keeps its last mode's rows at an odd stride GP (a row
+  // of R_{N-1} values padded by one when R_{N-1} is even), so lanes that
+  // read the same position of consecutive rows hit different banks.
+  const int RL = a.Rn[N - 1];
+  const int GP = GLDS ? (RL | 1) : RL;
+  auto gidx = [&](int64_t l) __attribute__((always_inline)) {
+    return (l / RL) * GP + l % RL;
+  };
   if constexpr (GLDS) {
     float* gs = reinterpret_cast<float*>(smem + c.oG);
-    for (int64_t l = t; l < core; l += NT) gs[l] = a.G[l];
+    for (int64_t l = t; l < core; l += NT) gs[gidx(l)] = a.G[l];
     G = gs;
     X1 = D(c.oX1);
     W1 = D(c.oW1);
@@ -332,7 +340,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
         double acc = 0.0;
         for (int j = 0; j < Rn; ++j) {
           const int64_t idx = (aa * Rn + j) * Cpost + cc;
-          const double x = src ? src[idx] : static_cast<double>(G[idx]);
+          const double x = src ? src[idx] : static_cast<double>(G[gidx(idx)]);
           acc += x * M[j * Rn + i];
         }
         dst[l] = acc;
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
       Apre *= Rn;
     }
     double p = 0.0;
-    for (int64_t l = t; l < core; l += NT) p += static_cast<double>(G[l]) * src[l];
+    for (int64_t l = t; l < core; l += NT) p += static_cast<double>(G[gidx(l)]) * src[l];
     nrm2 = block_sum(p, red);
     __syncthreads();
   }
@@ -371,9 +379,15 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
       double* dst = last ? Hlast : (st == 0 ? X1 : (((st - 1) & 1) ? W2 : W1));
       const bool reuse = st == 0 && !last && n > 0 && n < N - 1;
       if (!reuse && src == nullptr) {
-        // first step from the FP32 core: 4 consecutive (a, c) x 4 r per item
+        // first step from the FP32 core (it contracts mode N-1 or N-2, so
+        // Cpost is 1 or R_{N-1}): 4 positions (a, c) x 4 r per item, the
+        // positions nq apart so that consecutive items read consecutive
+        // rows of the core
         const int nac = Apre * Cpost;
-        const int total = ((nac + 3) / 4) * R4;
+        const int nq = (nac + 3) / 4;
+        const int total = nq * R4;
+        const int astride = Cpost == 1 ? GP : Rm * GP;   // padded strides
+        const int jstride = Cpost == 1 ? 1 : GP;
         for (int item = t; item < total; item += NT) {
           const int rq = item % R4;
           const int ab = item / R4;
@@ -381,11 +395,11 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
           bool val[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int ac = 4 * ab + u;
+            const int ac = ab + u * nq;
             val[u] = ac < nac;
             const int acc_ = val[u] ? ac : nac - 1;   // clamped, in bounds
             const int cc = acc_ % Cpost, aa = acc_ / Cpost;
-            off[u] = aa * Rm * Cpost + cc;
+            off[u] = aa * astride + cc;
           }
           double acc[4][4];
 #pragma unroll
@@ -394,21 +408,22 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
             for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
           const double* vp = Vm + 4 * rq;
           // operands of 4 consecutive j are loaded before any is used, so
-          // four LDS round trips overlap (tail j clamped, weight zero)
-          for (int j0 = 0; j0 < Rm; j0 += 4) {
+          // four LDS round trips overlap; the last group of a length that is
+          // not a multiple of 4 clamps j and weighs the extra terms zero
+          auto group = [&](int j0, bool tail) __attribute__((always_inline)) {
             double2 v01[4], v23[4];
             float g[4][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+              const int j = (!tail || j0 + q < Rm) ? j0 + q : Rm - 1;
               v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
               v23[q] = *reinterpret_cast<const double2*>(vp + j * RP + 2);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) g[q][u] = G[off[u] + j * Cpost];
+              for (int u = 0; u < 4; ++u) g[q][u] = G[off[u] + j * jstride];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const bool in = j0 + q < Rm;
+              const bool in = !tail || j0 + q < Rm;
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 const double gv = in ? static_cast<double>(g[q][u]) : 0.0;
@@ -418,11 +433,14 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
                 acc[u][3] += gv * v23[q].y;
               }
             }
-          }
+          };
+          int j0 = 0;
+          for (; j0 + 4 <= Rm; j0 += 4) group(j0, false);
+          if (j0 < Rm) group(j0, true);
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             if (val[u]) {
-              double* dp = dst + (4 * ab + u) * RP + 4 * rq;
+              double* dp = dst + (ab + u * nq) * RP + 4 * rq;
               *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
               *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
             }
@@ -439,11 +457,11 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
           const double* vp = Vm + 4 * rq;
           const double* sp = src + (aa * Rm * Cpost + cc) * RP + 4 * rq;
           const int sj = Cpost * RP;
-          for (int j0 = 0; j0 < Rm; j0 += 4) {
+          auto group = [&](int j0, bool tail) __attribute__((always_inline)) {
             double2 s01[4], s23[4], v01[4], v23[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const int j = (j0 + q < Rm) ? j0 + q : Rm - 1;
+              const int j = (!tail || j0 + q < Rm) ? j0 + q : Rm - 1;
               s01[q] = *reinterpret_cast<const double2*>(sp + j * sj);
               s23[q] = *reinterpret_cast<const double2*>(sp + j * sj + 2);
               v01[q] = *reinterpret_cast<const double2*>(vp + j * RP);
@@ -451,14 +469,17 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              if (j0 + q < Rm) {
+              if (!tail || j0 + q < Rm) {
                 acc0 += s01[q].x * v01[q].x;
                 acc1 += s01[q].y * v01[q].y;
                 acc2 += s23[q].x * v23[q].x;
                 acc3 += s23[q].y * v23[q].y;
               }
             }
-          }
+          };
+          int j0 = 0;
+          for (; j0 + 4 <= Rm; j0 += 4) group(j0, false);
+          if (j0 < Rm) group(j0, true);
           double* dp = dst + ac * RP + 4 * rq;
           *reinterpret_cast<double2*>(dp) = make_double2(acc0, acc1);
           *reinterpret_cast<double2*>(dp + 2) = make_double2(acc2, acc3);
@@ -576,6 +597,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
       for (int l = t; l < Rn * R4; l += NT) {
         const int j = l / R4, rq = l % R4;
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+#pragma unroll 4
         for (int q = 0; q < Rn; ++q) {
           const double mv = M[j * Rn + q];
           const double2 v01 = *reinterpret_cast<const double2*>(Vh + q * RP + 4 * rq);
@@ -592,9 +614,17 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
       __syncthreads();
       for (int l = t; l < R * R; l += NT) {
         const int i = l / R, j = l % R;
-        double acc = 0.0;
-        for (int q = 0; q < Rn; ++q) acc += Vh[q * RP + i] * Pm[q * RP + j];
-        G0[i * RP + j] = acc;
+        // four partial sums: independent LDS round trips and FMA chains
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int q = 0;
+        for (; q + 4 <= Rn; q += 4) {
+          a0 += Vh[q * RP + i] * Pm[q * RP + j];
+          a1 += Vh[(q + 1) * RP + i] * Pm[(q + 1) * RP + j];
+          a2 += Vh[(q + 2) * RP + i] * Pm[(q + 2) * RP + j];
+          a3 += Vh[(q + 3) * RP + i] * Pm[(q + 3) * RP + j];
+        }
+        for (; q < Rn; ++q) a0 += Vh[q * RP + i] * Pm[q * RP + j];
+        G0[i * RP + j] = (a0 + a1) + (a2 + a3);
       }
       __syncthreads();
       // columns normalized for n < N-1 (zero columns stay zero):
@@ -744,7 +774,10 @@ int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
     c.oG = c.oX1 = c.oW1 = c.oW2 = 0;
     return off;
   }
-  c.oG = take(4LL * core);
+  {
+    const int RL = a.Rn[a.N - 1];
+    c.oG = take(4LL * (core / RL) * (RL | 1));   // padded rows (see the kernel)
+  }
   c.oX1 = take(8LL * x1 > stage_bytes ? 8LL * x1 : stage_bytes);
   c.oStage = c.oX1;
   c.oW1 = take(8LL * (w[0] > 0 ? w[0] : 1));
