@@ -115,24 +115,30 @@ __device__ __forceinline__ bool gj_inverse_wave(const double* T, int RP, int R,
 // Wave-level Gauss-Jordan solve of X (T + delta I) = H for X (Rn x R), T
 // symmetric positive definite (R x R) and H (Rn x R), all with row stride
 // RP.  The wave holds the augmented matrix [T + delta I | H^T] (R rows),
-// lane c column c (R + Rn <= 64).  The T block is eliminated in the
-// symmetric (sweep) form: pivot k scales column k by 1/d and sets the pivot
-// to -1/d, so the block stays symmetric and the pivot column equals row k,
-// which lane i already holds as its entry k.  Each step therefore
-// publishes one value per lane in LDS (pcol), reads the column back as a
-// broadcast and applies R fused multiply-adds; the H^T columns see the
-// ordinary row operations.  After R steps lane R + i holds column i of
-// T^{-1} H^T, i.e. row i of X.  Without pivoting the pivots are the
-// Schur-complement diagonals: one <= 0 means T + delta I is not numerically
-// positive definite (returns false).
+// lane c column c (R + Rn <= 64), and eliminates two pivots per step (a
+// 2 x 2 pivot block; one at the end when R is odd), so the chain of
+// dependent steps is half as long: lanes k and k+1 publish their columns in
+// LDS, every lane reads both back as broadcasts, applies the block's
+// inverse to its rows k, k+1 and subtracts the corresponding combination of
+// the two pivot columns from its other rows.  The pivot lanes' columns
+// become e_k, e_{k+1} by the same arithmetic.  After the last step lane
+// R + i holds column i of T^{-1} H^T, i.e. row i of X.  Without pivoting the
+// pivot blocks are diagonal blocks of Schur complements of an SPD matrix: a
+// block whose leading entry or determinant is <= 0 means T + delta I is not
+// numerically positive definite (returns false).
 template <int RMAX>
 __device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, double delta,
                                               const double* H, int Rn, double* X,
                                               double* pcol) {
-  static_assert(RMAX % 2 == 0 && RMAX <= 32, "pivot column in double2 steps");
+  static_assert(RMAX % 2 == 0 && RMAX <= 32, "pivot columns in double2 steps");
+  // the widest form keeps one pivot per step (three columns of registers
+  // would not fit beside the rest of the kernel)
+  constexpr bool kBlocks = RMAX <= 24;
+  constexpr int kStep = kBlocks ? 2 : 1;
   const int c = threadIdx.x & 63;
   const bool isT = c < R, isH = c >= R && c < R + Rn;
   const int jt = isT ? c : 0, ih = isH ? c - R : 0;   // clamped: loads in bounds
+  double* pc1 = pcol + RMAX;
   double col[RMAX];
 #pragma unroll
   for (int i = 0; i < RMAX; ++i) {
@@ -144,35 +150,65 @@ __device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, do
       v = H[ih * RP + ic];
     col[i] = i < R ? v : 0.0;
   }
-  if (c < RMAX) pcol[c] = 0.0;   // slots R..RMAX-1 stay zero
   bool ok = true;
 #pragma unroll
-  for (int k = 0; k < RMAX; ++k) {
+  for (int k = 0; k < RMAX; k += kStep) {
     if (k < R) {
-      if (isT) pcol[c] = col[k];   // row k = column k of the symmetric block
+      const bool pair = kBlocks && k + 1 < R;
+      if (c == k || (pair && c == k + 1)) {
+        double* dst = c == k ? pcol : pc1;
+#pragma unroll
+        for (int i = 0; i < RMAX; i += 2)
+          *reinterpret_cast<double2*>(dst + i) = make_double2(col[i], col[i + 1]);
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double m[RMAX];
+      double m0[RMAX];   // pivot column k; zero below row R
 #pragma unroll
       for (int i = 0; i < RMAX; i += 2) {
         const double2 v = *reinterpret_cast<const double2*>(pcol + i);
-        m[i] = v.x;
-        m[i + 1] = v.y;
+        m0[i] = v.x;
+        m0[i + 1] = v.y;
       }
-      double p = m[k];
-      if (!(p > 0.0)) {
-        ok = false;
-        p = 1.0;
-      }
-      const double rp = recip(p);
-      const bool piv = c == k;
-      const double f = piv ? -rp : col[k] * rp;
+      if (pair) {
+        double m1[RMAX];   // pivot column k+1
 #pragma unroll
-      for (int i = 0; i < RMAX; ++i)
-        if (i != k) col[i] = (piv ? 0.0 : col[i]) - m[i] * f;
-      col[k] = f;
-      // every lane has read pcol before the next step rewrites it
+        for (int i = 0; i < RMAX; i += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(pc1 + i);
+          m1[i] = v.x;
+          m1[i + 1] = v.y;
+        }
+        // block [[a, b], [cc, d]] = rows/columns k, k+1
+        const int k1 = (k + 1) % RMAX;   // = k + 1 here
+        const double a = m0[k], cc = m0[k1], b = m1[k], d = m1[k1];
+        double det = a * d - b * cc;
+        if (!(a > 0.0 && det > 0.0)) {
+          ok = false;
+          det = 1.0;
+        }
+        const double rd = recip(det);
+        const double x0 = col[k], x1 = col[k1];
+        const double f0 = (d * x0 - b * x1) * rd;
+        const double f1 = (a * x1 - cc * x0) * rd;
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i)
+          if (i != k && i != k1) col[i] -= m0[i] * f0 + m1[i] * f1;
+        col[k] = f0;
+        col[k1] = f1;
+      } else {
+        double p = m0[k];
+        if (!(p > 0.0)) {
+          ok = false;
+          p = 1.0;
+        }
+        const double f = col[k] * recip(p);
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i)
+          if (i != k) col[i] -= m0[i] * f;
+        col[k] = f;
+      }
+      // every lane has read the pivot columns before the next step rewrites them
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
