@@ -246,7 +246,7 @@ def main():
     omt32 = [synth.f32(x) for x in d["omega_tildes"]]
     om_d = [torch.from_numpy(o).to(dev) for o in om32]
     omt_d = [[torch.from_numpy(o).to(dev) for o in lst] for lst in omt32]
-    ybf16 = torch.empty(dims, dtype=torch.int16, device=dev)
+    ybf16 = torch.empty(P.bf16_copy_shape(dims), dtype=torch.int16, device=dev)
     torch.cuda.synchronize()
 
     net, learned = None, None

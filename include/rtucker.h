@@ -104,8 +104,8 @@ typedef struct {
 
 /* Written by the device (caller-owned device memory). */
 typedef struct {
-  double normY2;    /* ||Y||_F^2 of the values the passes consumed (the
-                       BF16 copy in RT_BF16_MIXED), FP64 accumulation     */
+  double normY2;    /* ||Y||_F^2 of the input values (FP32, FP64, or the
+                       caller's BF16 values), FP64 accumulation           */
   double normG2;    /* ||G||_F^2 of the returned core                    */
   int32_t nonfinite; /* nonzero if a NaN/Inf was seen in Y               */
   int32_t rank_deficient; /* bit n set if Z_n had a zero Householder
@@ -128,6 +128,14 @@ typedef struct {
  * device work).  Returns RT_ERR_INVALID_ARG for an invalid description.
  */
 int rt_tucker_rand_workspace(const rt_tucker_desc* desc, size_t* bytes);
+
+/*
+ * Length, in uint16 values, of the Ybf16 buffer rt_tucker_rand needs (host
+ * only; no device work): I_1 ... I_{N-1} L with L = I_N rounded up to a
+ * multiple of 64, for RT_BF16_MIXED without RT_FLAG_BF16_INPUT; 0 otherwise.
+ * Returns RT_ERR_INVALID_ARG for an invalid description or NULL elems.
+ */
+int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems);
 
 /*
  * RandTucker2i (Algorithm 3, Section IV-A) on a dense tensor.
@@ -156,8 +164,13 @@ int rt_tucker_rand_workspace(const rt_tucker_desc* desc, size_t* bytes);
  *              RT_FLAG_NO_TRUNCATE), FP32 (FP64 for RT_F64).
  *   G          device output core, R_1 x ... x R_N, same type as U.
  *   Ybf16      RT_BF16_MIXED without RT_FLAG_BF16_INPUT: device buffer of
- *              prod I_n uint16 receiving the BF16 copy of Y (round to
- *              nearest even); NULL otherwise.
+ *              rt_tucker_bf16_copy_elems(desc) uint16 receiving the scaled
+ *              BF16 copy of Y, [I_1 ... I_{N-1}][L] row-major with row
+ *              stride L = I_N rounded up to a multiple of 64 (128 bytes):
+ *              entry (i_1..i_N) is bf16_rne(Y(i_1..i_N) 2^-e) with e the
+ *              binary exponent of the largest |Y| over the slab of fixed
+ *              (i_1..i_{N-2}); the L - I_N padding values are zero.
+ *              NULL otherwise.
  *   info       device rt_tucker_info (may be NULL).
  *   trace      host struct of optional device outputs (may be NULL).
  *   stream     hipStream_t.

@@ -87,6 +87,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.rt_tucker_rand_workspace.argtypes = [ctypes.POINTER(TuckerDesc), ctypes.POINTER(sz)]
+        L.rt_tucker_bf16_copy_elems.argtypes = [ctypes.POINTER(TuckerDesc),
+                                                ctypes.POINTER(i64)]
         L.rt_tucker_rand.argtypes = [ctypes.POINTER(TuckerDesc), vp, ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp), vp,
                                      vp, vp, ctypes.POINTER(TuckerTrace), vp]
@@ -112,7 +114,8 @@ def lib():
         L.rt_status_string.restype = ctypes.c_char_p
         L.rt_last_error.restype = ctypes.c_char_p
         L.rt_version.restype = ctypes.c_char_p
-        for f in ("rt_tucker_rand_workspace", "rt_tucker_rand", "rt_ffcp_workspace",
+        for f in ("rt_tucker_rand_workspace", "rt_tucker_bf16_copy_elems",
+                  "rt_tucker_rand", "rt_ffcp_workspace",
                   "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
                   "rt_stream_pass", "rt_profile_enable", "rt_profile_read",
                   "rt_mlp_workspace", "rt_mlp_sync_bf16", "rt_mlp_forward", "rt_mlp_grad",
@@ -201,6 +204,19 @@ def tucker_rand_workspace(desc):
     return n.value
 
 
+def bf16_copy_shape(dims, ranks_tilde=None):
+    """Shape of the Ybf16 buffer of the precision form for a tensor of these
+    dims (rt_tucker_bf16_copy_elems): dims[:-1] + (L,), L = dims[-1] rounded
+    up to a multiple of 64; the copy of Y is buf[..., :dims[-1]]."""
+    N = len(dims)
+    rt = ranks_tilde if ranks_tilde is not None else [1] * N
+    desc = tucker_desc(dims, rt, None, 1, "bf16")
+    n = ctypes.c_int64(0)
+    _check(lib().rt_tucker_bf16_copy_elems(ctypes.byref(desc), ctypes.byref(n)))
+    lead = int(np.prod([int(d) for d in dims[:-1]]))
+    return tuple(int(d) for d in dims[:-1]) + (n.value // lead,)
+
+
 def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
                 truncate=True, trace=False, ybf16=None, bf16_input=False,
                 dims=None, workspace=None, stream=None, sync=True):
@@ -224,8 +240,13 @@ def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
     out_r = [desc.ranks[n] if truncate else rt[n] for n in range(N)]
     U = [torch.empty((dims[n], out_r[n]), dtype=fdt, device=dev) for n in range(N)]
     G = torch.empty(out_r, dtype=fdt, device=dev)
-    if precision == "bf16" and not bf16_input and ybf16 is None:
-        ybf16 = torch.empty(dims, dtype=torch.int16, device=dev)
+    if precision == "bf16" and not bf16_input:
+        shape = bf16_copy_shape(dims, rt)
+        if ybf16 is None:
+            ybf16 = torch.empty(shape, dtype=torch.int16, device=dev)
+        _require_device(ybf16, "ybf16")
+        if ybf16.numel() < int(np.prod(shape)) or ybf16.element_size() != 2:
+            raise ValueError(f"ybf16 must hold {shape} 16-bit values")
     info = torch.zeros(TUCKER_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     ws_bytes = tucker_rand_workspace(desc)
     ws = workspace if workspace is not None and workspace.numel() >= ws_bytes \

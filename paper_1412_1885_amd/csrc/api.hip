@@ -578,6 +578,22 @@ int rt_tucker_rand_workspace(const rt_tucker_desc* desc, size_t* bytes) {
   return kOk;
 }
 
+int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems) {
+  RT_TRY(validate_tucker(desc));
+  if (!elems) {
+    set_error("elems is NULL");
+    return kErrInvalid;
+  }
+  if (desc->precision != RT_BF16_MIXED || (desc->flags & RT_FLAG_BF16_INPUT)) {
+    *elems = 0;
+    return kOk;
+  }
+  int64_t e = bf16_copy_ld(desc->dims[desc->N - 1]);
+  for (int p = 0; p < desc->N - 1; ++p) e *= desc->dims[p];
+  *elems = e;
+  return kOk;
+}
+
 int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
                    const void* const* Omega, const void* const* Omega_t,
                    void* ws, size_t ws_bytes, void* const* U, void* G,

@@ -360,6 +360,7 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
   for (int p = 0; p < N - 2; ++p) c.A *= d->dims[p];
   c.I1 = d->dims[N - 2];
   c.I2 = d->dims[N - 1];
+  c.ldy = c.bf16_input ? c.I2 : bf16_copy_ld(c.I2);
   c.ws = ws;
   c.ws_bytes = ws_bytes;
   c.norm_partial = static_cast<double*>(ws);

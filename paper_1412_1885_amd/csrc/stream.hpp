@@ -19,6 +19,8 @@ struct StreamCtx {
   int precision;
   bool bf16_input;
   int64_t A, I1, I2;    // [A, I_{N-1}, I_N]
+  int64_t ldy;          // row stride of ybf16 in values: bf16_copy_ld(I2),
+                        // or I2 for the caller's BF16 tensor
   void* ws;
   size_t ws_bytes;
   double* norm_partial;  // per-workgroup partial sums of ||Y||^2 (in ws)
@@ -34,6 +36,9 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
 // BF16 precision form (stream_bf16.hip)
 size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2);
 int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2);
+// row stride (values) of the BF16 copy of rows of I2 values: I2 rounded up
+// to a multiple of 64
+int64_t bf16_copy_ld(int64_t I2);
 // stage: profiling stage that brackets the streaming kernel itself
 int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
                      const float* B1, int K1, float* TA, float* TB, int stage,

@@ -20,6 +20,15 @@
 // requests in flight); every contraction, of every sweep and of the core
 // pass, reads the BF16 copy.
 //
+// Layout of the copy.  Rows of I2 values are stored at a stride rounded up
+// to 64 values (128 bytes, one L2 line), the padding written as zeros, so
+// every 64-column tile row is exactly one line.  With rows packed at 2*I2
+// bytes (I2 = 1000: 2000 B) a tile row straddles two lines, each line is
+// shared by two column tiles that a workgroup reads far apart in time, and
+// the second read of the line misses L2: the contractions then fetched
+// 1.3-1.9x the bytes of the copy.  A caller's own BF16 tensor
+// (RT_FLAG_BF16_INPUT) is read with its packed stride.
+//
 // Data path (one workgroup of 8 wavefronts per slab).  Wave w owns the
 // 32-row blocks w, w+8, w+16, w+24 (I1 <= 1024) and walks the slab in
 // 64-column tiles, column tile by column tile (RBW steps per column tile:
@@ -71,6 +80,7 @@ struct BfArgs {
   const int32_t* exps;    // per-slab exponent
   int64_t A;
   int I1, I2;
+  int ldy;                // row stride of Y in values (>= I2, multiple of 4)
   const uint16_t* B2t;    // [32][ldb2] BF16, zero beyond (K2, I2)
   int ldb2, K2;
   const uint16_t* B1t;    // [32][ldb1] BF16, zero beyond (K1, I1)
@@ -95,6 +105,7 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 constexpr int kOob = 0x7ffffff0;       // offset past every slab: loads return zero
+constexpr int kCopyAlign = 64;         // row stride multiple of the BF16 copy (128 B)
 
 // Buffer descriptor over one slab (byte range); loads past it return zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64_t bytes) {
@@ -106,7 +117,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64
 // c0..: buffer loads with a 32-bit offset into the slab; masked lanes (rows
 // or columns past the slab, including whole tiles past the end) get an
 // offset past the slab, so the hardware returns zeros without branches.
-// HALF (BF16 source, I2 % 8 == 4): rows start 8-byte aligned, two 8-byte
+// HALF (row stride ldy % 8 == 4): rows start 8-byte aligned, two 8-byte
 // loads per chunk, the second absent in the half chunk at a row's end.
 template <bool HALF>
 __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArgs& a,
@@ -117,8 +128,8 @@ __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const BfArg
     const int c = c0 + 16 * q + 8 * g;
     const bool ok = r < a.I1 && c < a.I2;   // I2 % 4 == 0
     const bool full = ok && c + 8 <= a.I2;  // else only 4 of the 8 columns exist
-    // (r * I2 + c) * 2 < slab bytes < 2^31 whenever ok; clamped otherwise
-    const int off = ok ? ((ok ? r : 0) * a.I2 + (ok ? c : 0)) * 2 : kOob;
+    // (r * ldy + c) * 2 < slab bytes < 2^31 whenever ok; clamped otherwise
+    const int off = ok ? ((ok ? r : 0) * a.ldy + (ok ? c : 0)) * 2 : kOob;
     if constexpr (!HALF) {
       const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       t.v[q] = make_uint4(v.x, v.y, v.z, v.w);
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   // the last column tile read masked (zero) tiles, so the loop body has no
   // branches and every wait counts loads exactly
   const int nsteps = (nct * RBW + kUnroll - 1) / kUnroll * kUnroll;
-  const int64_t slab_elems = static_cast<int64_t>(a.I1) * a.I2;
+  const int64_t slab_elems = static_cast<int64_t>(a.I1) * a.ldy;
 
   // one slab per workgroup: no outer loop, so nothing slab-invariant is kept
   // live across slabs
@@ -369,34 +380,41 @@ __global__ __launch_bounds__(256) void slab_stats_kernel(const void* Y, int64_t 
   if (t == 0) partial[blockIdx.x] = acc;
 }
 
-// The BF16 copy of an FP32 input: Yb = bf16_rne(Y * 2^-e_a) per slab a.
-// Slab a is row blockIdx.y of the grid; each thread converts four groups of
-// 4 consecutive values (16-byte loads, 8-byte stores), consecutive threads
-// on consecutive groups, so every wavefront instruction moves one
-// contiguous 1 KB (load) / 512 B (store) span.  Many small workgroups keep
-// enough loads and stores in flight to overlap the two streams.
+// The BF16 copy of an FP32 input: Yb[a][r][c] = bf16_rne(Y[a][r][c] 2^-e_a)
+// for c < I2 and zero for I2 <= c < ldy.  Slab a is row blockIdx.y of the
+// grid; each thread writes four groups of 4 consecutive copy values (8-byte
+// stores of 16-byte loads), consecutive threads on consecutive groups of the
+// padded slab, so every wavefront instruction moves one contiguous span
+// except where it crosses a row end.  Many small workgroups keep enough
+// loads and stores in flight to overlap the two streams.
 constexpr int kCvtThreads = 256, kCvtGroups = 4;
 
 __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* Y,
                                                                     uint16_t* Yb,
                                                                     const int32_t* exps,
-                                                                    int64_t slab) {
+                                                                    int I1, int I2,
+                                                                    int ldy) {
   const int64_t a = blockIdx.y;
   const float down = ldexpf(1.0f, -exps[a]);
-  const int64_t n4 = slab / 4;   // slab % 4 == 0
-  const float4* src = reinterpret_cast<const float4*>(Y + a * slab);
-  uint2* dst = reinterpret_cast<uint2*>(Yb + a * slab);
-  const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kCvtThreads * kCvtGroups) + threadIdx.x;
+  // I1 * ldy < 2^30 (shape check), so 32-bit group and value indexes
+  const uint32_t q = static_cast<uint32_t>(ldy) / 4;   // groups per copy row
+  const uint32_t ng = static_cast<uint32_t>(I1) * q;   // groups per copy slab
+  const float* src = Y + a * I1 * I2;
+  uint2* dst = reinterpret_cast<uint2*>(Yb + a * I1 * ldy);
+  const uint32_t g0 = blockIdx.x * (kCvtThreads * kCvtGroups) + threadIdx.x;
   float4 v[kCvtGroups];
 #pragma unroll
   for (int u = 0; u < kCvtGroups; ++u) {
-    const int64_t gi = g0 + u * kCvtThreads;
-    v[u] = gi < n4 ? src[gi] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const uint32_t gi = g0 + u * kCvtThreads;
+    const uint32_t r = gi / q, c = 4 * (gi - r * q);
+    v[u] = gi < ng && c < static_cast<uint32_t>(I2)
+               ? *reinterpret_cast<const float4*>(src + r * I2 + c)
+               : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 #pragma unroll
   for (int u = 0; u < kCvtGroups; ++u) {
-    const int64_t gi = g0 + u * kCvtThreads;
-    if (gi < n4)
+    const uint32_t gi = g0 + u * kCvtThreads;
+    if (gi < ng)
       dst[gi] = make_uint2(pack2(v[u].x * down, v[u].y * down),
                            pack2(v[u].z * down, v[u].w * down));
   }
@@ -442,8 +460,8 @@ int launch_bf_rbw(const BfArgs& a, int grid, hipStream_t s) {
 
 template <bool DOQ>
 int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
-  // rows that start 8-byte aligned (I2 % 8 == 4) take the half-chunk loads
-  if ((a.I2 & 7) != 0) return launch_bf_rbw<DOQ, true>(a, grid, s);
+  // rows that start 8-byte aligned (ldy % 8 == 4) take the half-chunk loads
+  if ((a.ldy & 7) != 0) return launch_bf_rbw<DOQ, true>(a, grid, s);
   return launch_bf_rbw<DOQ, false>(a, grid, s);
 }
 
@@ -456,11 +474,14 @@ size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
   return static_cast<size_t>(A) * 4 + 256 + 2 * 32 * (l1 + l2) + 512;
 }
 
+int64_t bf16_copy_ld(int64_t I2) { return (I2 + kCopyAlign - 1) / kCopyAlign * kCopyAlign; }
+
 int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
-  // a slab's FP32 bytes must stay below the masked-load offset
-  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 || I1 * I2 * 4 > kOob - 64) {
+  // a slab of the padded copy must stay below the masked-load offset
+  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 ||
+      I1 * bf16_copy_ld(I2) * 2 > kOob - 64) {
     set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0, "
-              "I_{N-1} I_N < 2^29 and sketch widths <= 32 (got %lld, %lld, %d, %d)",
+              "I_{N-1} I_N < 2^30 and sketch widths <= 32 (got %lld, %lld, %d, %d)",
               kMaxI1, (long long)I1, (long long)I2, K1, K2);
     return kErrUnsupported;
   }
@@ -499,8 +520,8 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
     RT_LAUNCH_CHECK("prep B1");
   }
   if (first && !c.bf16_input) {
-    // the scaled BF16 copy, then every contraction reads it
-    const int64_t slab = c.I1 * c.I2;
+    // the scaled BF16 copy (padded rows), then every contraction reads it
+    const int64_t slab = c.I1 * c.ldy;
     const int64_t per_block = static_cast<int64_t>(kCvtThreads) * kCvtGroups * 4;
     if (c.A > 65535) {
       set_error("BF16 conversion: too many slabs (%lld)", (long long)c.A);
@@ -511,7 +532,8 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
                        dim3(static_cast<unsigned>((slab + per_block - 1) / per_block),
                             static_cast<unsigned>(c.A)),
                        dim3(kCvtThreads), 0, s, static_cast<const float*>(c.y), c.ybf16,
-                       exps, slab);
+                       exps, static_cast<int>(c.I1), static_cast<int>(c.I2),
+                       static_cast<int>(c.ldy));
     RT_LAUNCH_CHECK("bf16 convert");
   }
   BfArgs a{};
@@ -520,6 +542,7 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   a.A = c.A;
   a.I1 = static_cast<int>(c.I1);
   a.I2 = static_cast<int>(c.I2);
+  a.ldy = static_cast<int>(c.ldy);
   a.B2t = B2t;
   a.ldb2 = static_cast<int>(l2);
   a.K2 = K2;

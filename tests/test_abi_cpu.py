@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1412_1885_amd as P
@@ -74,18 +75,40 @@ def test_tucker_workspace_validation():
 
 
 def test_bf16_shapes_checked_at_validation():
-    """The BF16 streaming pass needs I_N % 8 == 0, I_{N-1} <= 1024 and the
+    """The BF16 streaming pass needs I_N % 4 == 0, I_{N-1} <= 1024 and the
     two streamed sketch widths <= 32: rejected before anything is launched."""
     n = ctypes.c_size_t(0)
     ok = P.tucker_desc([4, 20, 32], [4, 5, 5], [3, 3, 3], precision="bf16")
     assert P.lib().rt_tucker_rand_workspace(ctypes.byref(ok), ctypes.byref(n)) == 0
-    for dims, rt in (([4, 20, 30], [4, 5, 5]),        # I_N % 8 != 0
+    for dims, rt in (([4, 20, 30], [4, 5, 5]),        # I_N % 4 != 0
                      ([4, 1100, 32], [4, 5, 5]),      # I_{N-1} > 1024
                      ([4, 40, 64], [4, 5, 33])):      # streamed width > 32
         d = P.tucker_desc(dims, rt, [3, 3, 3], precision="bf16")
         rc = P.lib().rt_tucker_rand_workspace(ctypes.byref(d), ctypes.byref(n))
         assert rc == -2, (dims, rt, rc)   # RT_ERR_UNSUPPORTED
         assert "BF16" in P.last_error()
+
+
+def test_bf16_copy_length():
+    """The BF16 copy's rows are padded to a multiple of 64 values; no copy in
+    the other forms or for a caller's BF16 tensor."""
+    n = ctypes.c_int64(-1)
+    L = P.lib()
+    for dims, want in (([1000, 1000, 1000], 1000 * 1000 * 1024),
+                       ([6, 40, 56], 6 * 40 * 64), ([3, 5, 7, 128], 3 * 5 * 7 * 128),
+                       ([2, 3, 68], 2 * 3 * 128)):
+        d = P.tucker_desc(dims, [2] * len(dims), precision="bf16")
+        assert L.rt_tucker_bf16_copy_elems(ctypes.byref(d), ctypes.byref(n)) == 0
+        assert n.value == want, dims
+        assert P.bf16_copy_shape(dims) == tuple(dims[:-1]) + (want // np.prod(dims[:-1]),)
+    for d in (P.tucker_desc([6, 40, 56], [2, 2, 2], precision="f32"),
+              P.tucker_desc([6, 40, 56], [2, 2, 2], precision="bf16", bf16_input=True)):
+        assert L.rt_tucker_bf16_copy_elems(ctypes.byref(d), ctypes.byref(n)) == 0
+        assert n.value == 0
+    d = P.tucker_desc([6, 40, 56], [2, 2, 2], precision="bf16")
+    assert L.rt_tucker_bf16_copy_elems(ctypes.byref(d), None) == -1
+    d.N = 1
+    assert L.rt_tucker_bf16_copy_elems(ctypes.byref(d), ctypes.byref(n)) == -1
 
 
 def test_gauss_seidel_flag_reports_unsupported():

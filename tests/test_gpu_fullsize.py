@@ -131,7 +131,8 @@ def test_fullsize_plain_fp32(P, work):
 
 
 def test_fullsize_precision_form(P, work):
-    ybf16 = torch.empty((I, I, I), dtype=torch.int16, device="cuda")
+    ybf16 = torch.empty(P.bf16_copy_shape((I, I, I)), dtype=torch.int16, device="cuda")
+    assert ybf16.shape == (I, I, 1024)
     out = run(P, work, "bf16", ybf16=ybf16)
     check_sketch_rows(out, work, bf16=True)
     check_properties(out, work)
@@ -142,7 +143,9 @@ def test_fullsize_precision_form(P, work):
         m = float(np.abs(Y32).max())
         e = int(np.frexp(m)[1] - 1) if m > 0 else 0
         want = bf16_bits(np.ldexp(Y32.astype(np.float64), -e).astype(np.float32))
-        assert np.array_equal(got[a].cpu().numpy().view(np.uint16), want), a
+        row = got[a].cpu().numpy().view(np.uint16)
+        assert np.array_equal(row[:, :I], want), a
+        assert not row[:, I:].any(), a
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
