@@ -199,7 +199,9 @@ __device__ bool chol_upper(double* S, int K, double* flag) {
 // factor Householder QR with a positive diagonal gives (up to rounding).
 // Falls back to Householder when a Gram matrix is not positive definite.
 //
-// The row work is spread over many workgroups (row chunks x matrices):
+// Sketches of at most kQfMaxI rows and K <= 32 take the fused one-workgroup
+// form below; for larger ones the row work is spread over many workgroups
+// (row chunks x matrices):
 //   rows(0): partial Gram of Z per chunk
 //   chol(0): sum of the partials (fixed order), R1, R1^{-1}
 //   rows(1): Q1 = Z R1^{-1} (FP64, kept in work) and its partial Gram
@@ -476,6 +478,341 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   }
 }
 
+// ------------------------------------------------- fused CholeskyQR2
+// The same CholeskyQR2 for sketches of at most kQfMaxI rows and K <= 32 in
+// ONE workgroup per matrix, so that no step waits on a global round trip or
+// a kernel boundary (the multi-kernel form spends most of its time there):
+//   G1 = Z^T Z  (FP64 MFMA over 4-row groups read straight from Z)
+//   R1 = chol(G1), R1^{-1}                     (one wavefront, registers)
+//   Q1 = Z R1^{-1} tile by tile, G2 = Q1^T Q1   (Q1 never leaves registers)
+//   R2 = chol(G2), M = R1^{-1} R2^{-1}
+//   Q  = Z M     (= Q1 R2^{-1} up to FP64 rounding; M is upper triangular)
+// v_mfma_f64_16x16x4_f64 lane layout (checked on the device): A (16 x 4)
+// lane l holds A[l%16][l/16], B (4 x 16) lane l holds B[l/16][l%16], D
+// (16 x 16) lane l element e holds D[4e + l/16][l%16].  A D tile of Q1 rows
+// therefore serves directly as both operands of the Gram product: its
+// element e is the 4-row slice 4e..4e+3 of the tile (k = l/16) in operand
+// layout.
+constexpr int kQfThreads = 512;
+constexpr int kQfWaves = kQfThreads / 64;
+constexpr int kQfMaxI = 4096;
+constexpr int kQfLd = 33;   // LDS row stride of the 32 x 32 FP64 matrices
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double wave_read(double v, int src) {   // src uniform
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// R^{-1} for the upper Cholesky factor R of the K x K matrix S (S = R^T R),
+// by one wavefront: lane c keeps column c of the trailing matrix in
+// registers (right-looking; row j of R is published in LDS each step),
+// then computes column c of R^{-1} by right-looking back substitution with
+// the columns of R read from LDS (Rt, row k = column k of R).  1/R[j][j]
+// comes from the hardware reciprocal square root refined by two Newton
+// steps, R[j][j] = S'[j][j] / sqrt(S'[j][j]).  Pivots at or below 1e-11 of
+// the mean diagonal of S fail (returns false, wave-uniform).  Writes R^{-1}
+// to Ri ([32][kQfLd], zero outside the upper K x K part).
+__device__ __forceinline__ bool chol_inv_wave(const double* S, int K, double* Ri,
+                                              double* Rt /*32 x 32*/, double* rowbuf /*2 x 32*/,
+                                              double* rdiag /*32*/) {
+  const int c = threadIdx.x & 63;
+  const int cc = c < 32 ? c : 31;
+  const double floor_ = 1e-11 * wave_sum(c < K ? S[cc * kQfLd + cc] : 0.0) / K;
+  double col[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) col[r] = (r <= c && c < K && r < K) ? S[r * kQfLd + cc] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    if (j < K) {
+      double d = wave_read(col[j], j);
+      if (!(d > floor_)) {
+        ok = false;
+        d = 1.0;
+      }
+      double y = __builtin_amdgcn_rsq(d);
+      const double h = 0.5 * d;
+      y = y * fma(-h * y, y, 1.5);
+      y = y * fma(-h * y, y, 1.5);
+      col[j] = (c == j) ? d * y : (c > j ? col[j] * y : 0.0);
+      if (c == j) rdiag[j] = y;
+      double* rb = rowbuf + 32 * (j & 1);
+      if (c < 32) rb[c] = col[j];          // row j of R (zero left of j)
+      wave_sync_lds();
+      // all of the row's loads first, one wait, then the updates
+      double rv[32];
+#pragma unroll
+      for (int r = j + 1; r < 32; ++r) rv[r] = rb[r];
+#pragma unroll
+      for (int r = j + 1; r < 32; ++r)
+        if (r <= c) col[r] -= rv[r] * col[j];
+    }
+  }
+  if (c < 32) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) Rt[c * 32 + r] = col[r];   // zero below the diagonal
+  }
+  wave_sync_lds();
+  // column c of R^{-1}: x_k = (delta_kc + s_k) / R[k][k], then s_i -= R[i][k] x_k
+  double x[32], sacc[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) sacc[i] = 0.0;
+#pragma unroll
+  for (int k = 31; k >= 0; --k) {
+    if (k < K) {
+      double rk[32];   // column k of R: loads issued together
+#pragma unroll
+      for (int i = 0; i < k; ++i) rk[i] = Rt[k * 32 + i];
+      x[k] = ((k == c) ? 1.0 : 0.0) + sacc[k];
+      x[k] *= rdiag[k];
+#pragma unroll
+      for (int i = 0; i < k; ++i) sacc[i] -= rk[i] * x[k];
+    } else {
+      x[k] = 0.0;
+    }
+  }
+  if (c < 32) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) Ri[i * kQfLd + c] = (c < K) ? x[i] : 0.0;
+  }
+  return ok;
+}
+
+// Fixed-order sum of the waves' Gram tiles (red: [waves][3][64][4]) into
+// the symmetric 32 x 32 matrix G (row stride kQfLd).
+__device__ void gram_reduce(const double* red, double* G) {
+  for (int o = threadIdx.x; o < 3 * 256; o += kQfThreads) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kQfWaves; ++w) v += red[w * 768 + o];
+    const int tile = o / 256, l = (o % 256) / 4, e = o % 4;
+    const int a = 4 * e + l / 16, bcol = l % 16;
+    if (tile == 0) {
+      G[a * kQfLd + bcol] = v;
+    } else if (tile == 1) {
+      G[a * kQfLd + 16 + bcol] = v;
+      G[(16 + bcol) * kQfLd + a] = v;
+    } else {
+      G[(16 + a) * kQfLd + 16 + bcol] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ void gram_store(double* red, const v4d& g00, const v4d& g01,
+                                           const v4d& g11) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    red[w * 768 + l * 4 + i] = g00[i];
+    red[w * 768 + 256 + l * 4 + i] = g01[i];
+    red[w * 768 + 512 + l * 4 + i] = g11[i];
+  }
+}
+
+// Tile (16 rows from r0, column tile ct) of Z X for the upper triangular X
+// whose operand values the lane holds in bx[ct][ks]; az[ks] = Z[r0 + l%16][4ks + l/16].
+template <typename T>
+__device__ __forceinline__ v4d tile_times(const T (&az)[8], const double (&bx)[2][8], int ct) {
+  // two accumulators: consecutive products do not wait on each other
+  v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  if (ct == 0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)   // X[k][c] = 0 for k > c
+      acc[ks & 1] = mfma_f64(static_cast<double>(az[ks]), bx[0][ks], acc[ks & 1]);
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+      acc[ks & 1] = mfma_f64(static_cast<double>(az[ks]), bx[1][ks], acc[ks & 1]);
+  }
+  return acc[0] + acc[1];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rows(const T* Z, int64_t I, int K, int64_t r0, T (&az)[8]) {
+  const int l = threadIdx.x & 63;
+  const int64_t r = r0 + (l & 15);
+  // unconditional loads from clamped (valid) addresses, zeroed afterwards:
+  // no branches, so a batch of loads is in flight together
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    const int k = 4 * ks + (l >> 4);
+    const bool ok = r < I && k < K;
+    const T v = Z[ok ? r * K + k : 0];
+    az[ks] = ok ? v : T(0);
+  }
+}
+
+// Register batches: the loads of a wave's next NG row groups (first Gram)
+// or NB row blocks (transforms) are all issued before any of them is used,
+// so a pass waits for global memory once per batch, not once per block.
+template <typename T> struct QfBatch { static constexpr int NG = 16, NB = 4; };
+template <> struct QfBatch<double> { static constexpr int NG = 16, NB = 4; };
+
+__device__ __forceinline__ void load_bx(const double* X, double (&bx)[2][8]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) bx[ct][ks] = X[(4 * ks + (l >> 4)) * kQfLd + 16 * ct + (l & 15)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kQfThreads) void qr_fused_kernel(QrBatch b) {
+  __shared__ double red[kQfWaves * 768];
+  __shared__ double S[32 * kQfLd];
+  __shared__ double Ri1[32 * kQfLd];
+  __shared__ double Ri2[32 * kQfLd];
+  __shared__ double rowbuf[64];
+  __shared__ double rdiag[32];
+  __shared__ double Rt[32 * 32];
+  __shared__ double scal[2];
+  const int m = blockIdx.x;
+  const int64_t I = b.I[m];
+  const int K = b.K[m];
+  const T* Z = static_cast<const T*>(b.Z[m]);
+  T* Qo = static_cast<T*>(b.Q[m]);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const bool wide = K > 16;   // second column tile
+  for (int e = t; e < 32 * kQfLd; e += kQfThreads) S[e] = 0.0;
+  __syncthreads();
+
+  // G1 = Z^T Z over 4-row groups: lane l holds Z[4g + l/16][l%16] (and +16)
+  constexpr int NG = QfBatch<T>::NG, NB = QfBatch<T>::NB;
+  {
+    v4d g00[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}, g01[2] = {g00[0], g00[0]},
+        g11[2] = {g00[0], g00[0]};
+    const int64_t ng = (I + 3) / 4;
+    const int k0 = l & 15, k1 = 16 + (l & 15);
+    for (int64_t gb = w; gb < ng; gb += NG * kQfWaves) {
+      T a0[NG], a1[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {   // clamped loads, zeroed: see load_rows
+        const int64_t r = 4 * (gb + j * kQfWaves) + (l >> 4);
+        const bool ok0 = r < I && k0 < K, ok1 = r < I && k1 < K;
+        const T v0 = Z[ok0 ? r * K + k0 : 0];
+        const T v1 = Z[ok1 ? r * K + k1 : 0];
+        a0[j] = ok0 ? v0 : T(0);
+        a1[j] = ok1 ? v1 : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
+        const double x0 = static_cast<double>(a0[j]), x1 = static_cast<double>(a1[j]);
+        g00[j & 1] = mfma_f64(x0, x0, g00[j & 1]);
+        if (wide) {
+          g01[j & 1] = mfma_f64(x0, x1, g01[j & 1]);
+          g11[j & 1] = mfma_f64(x1, x1, g11[j & 1]);
+        }
+      }
+    }
+    gram_store(red, g00[0] + g00[1], g01[0] + g01[1], g11[0] + g11[1]);
+  }
+  __syncthreads();
+  gram_reduce(red, S);
+  __syncthreads();
+  if (w == 0) {
+    const bool ok = chol_inv_wave(S, K, Ri1, Rt, rowbuf, rdiag);
+    if (l == 0) scal[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (scal[0] < 0.5) {
+    if (t == 0) b.need[m] = 1;   // Householder QR takes over
+    return;
+  }
+
+  // Q1 = Z R1^{-1} (registers only) and G2 = Q1^T Q1
+  const int64_t nrb = (I + 15) / 16;
+  {
+    double bx[2][8];
+    load_bx(Ri1, bx);
+    v4d g00[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}, g01[2] = {g00[0], g00[0]},
+        g11[2] = {g00[0], g00[0]};
+    for (int64_t b0 = w; b0 < nrb; b0 += NB * kQfWaves) {
+      T az[NB][8];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) load_rows(Z, I, K, 16 * (b0 + j * kQfWaves), az[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (b0 + j * kQfWaves >= nrb) break;   // zero rows: nothing to add
+        const v4d q0 = tile_times(az[j], bx, 0);
+        const v4d q1 = wide ? tile_times(az[j], bx, 1) : q0 * 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          g00[i & 1] = mfma_f64(q0[i], q0[i], g00[i & 1]);
+          if (wide) {
+            g01[i & 1] = mfma_f64(q0[i], q1[i], g01[i & 1]);
+            g11[i & 1] = mfma_f64(q1[i], q1[i], g11[i & 1]);
+          }
+        }
+      }
+    }
+    gram_store(red, g00[0] + g00[1], g01[0] + g01[1], g11[0] + g11[1]);
+  }
+  __syncthreads();
+  for (int e = t; e < 32 * kQfLd; e += kQfThreads) S[e] = 0.0;
+  __syncthreads();
+  gram_reduce(red, S);
+  __syncthreads();
+  if (w == 0) {
+    const bool ok = chol_inv_wave(S, K, Ri2, Rt, rowbuf, rdiag);
+    if (l == 0) scal[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (scal[0] < 0.5) {
+    if (t == 0) b.need[m] = 1;
+    return;
+  }
+  // M = R1^{-1} R2^{-1} (upper triangular) into S
+  for (int e = t; e < 32 * 32; e += kQfThreads) {
+    const int i = e / 32, c = e % 32;
+    double v = 0.0;
+    for (int k = i; k <= c; ++k) v += Ri1[i * kQfLd + k] * Ri2[k * kQfLd + c];
+    S[i * kQfLd + c] = v;
+  }
+  __syncthreads();
+  // Q = Z M
+  {
+    double bx[2][8];
+    load_bx(S, bx);
+    for (int64_t b0 = w; b0 < nrb; b0 += NB * kQfWaves) {
+      T az[NB][8];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) load_rows(Z, I, K, 16 * (b0 + j * kQfWaves), az[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int64_t rb = b0 + j * kQfWaves;
+        if (rb >= nrb) break;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          if (ct == 1 && !wide) break;
+          const v4d q = tile_times(az[j], bx, ct);
+          const int cidx = 16 * ct + (l & 15);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t r = 16 * rb + 4 * i + (l >> 4);
+            if (r < I && cidx < K) Qo[r * K + cidx] = static_cast<T>(q[i]);
+          }
+        }
+      }
+    }
+  }
+  if (t == 0) b.need[m] = 0;
+}
+
 template <typename T, int KMAX>
 int qr_dispatch(const QrBatch& b, int32_t* flag, hipStream_t s) {
   const dim3 rows_grid(kQrChunks, b.nb);
@@ -505,7 +842,20 @@ int64_t qr_work_doubles(int64_t I, int K) {
 template <typename T>
 int launch_qr(const QrBatch& b, int32_t* flag, hipStream_t s) {
   int kmax = 0;
-  for (int i = 0; i < b.nb; ++i) kmax = b.K[i] > kmax ? b.K[i] : kmax;
+  int64_t imax = 0;
+  for (int i = 0; i < b.nb; ++i) {
+    kmax = b.K[i] > kmax ? b.K[i] : kmax;
+    imax = b.I[i] > imax ? b.I[i] : imax;
+  }
+  if (kmax <= 32 && imax <= kQfMaxI) {
+    // one workgroup per sketch; Householder for any that CholeskyQR2 rejects
+    hipLaunchKernelGGL(qr_fused_kernel<T>, dim3(b.nb), dim3(kQfThreads), 0, s, b);
+    RT_LAUNCH_CHECK("qr fused");
+    hipLaunchKernelGGL((householder_kernel<T, 32>), dim3(b.nb), dim3(kQrThreads), 0, s, b,
+                       flag, static_cast<const int32_t*>(b.need));
+    RT_LAUNCH_CHECK("qr fallback");
+    return kOk;
+  }
   if (kmax <= 16) return qr_dispatch<T, 16>(b, flag, s);
   if (kmax <= 32) return qr_dispatch<T, 32>(b, flag, s);
   if (kmax <= 64) return qr_dispatch<T, 64>(b, flag, s);

@@ -132,6 +132,19 @@ def test_tucker_fp32_mfma_streaming_shapes(P, dims):
     check_tucker(out, ref, Y, 3, 2, 1e-5, 2e-4, 2e-4)
 
 
+@pytest.mark.parametrize("dims,rt", [((40, 45, 52), (20, 24, 17)),    # one workgroup, K > 16
+                                     ((4100, 6, 8), (10, 6, 8)),      # I_n > 4096: row chunks
+                                     ((50, 60, 64), (40, 12, 12))])   # K > 32: row chunks
+def test_tucker_fp32_qr_forms(P, dims, rt):
+    """The sketch bases come from the one-workgroup CholeskyQR2 for sketches
+    of at most 4096 rows and 32 columns and from the row-chunked form
+    otherwise; both match the oracle's Householder bases."""
+    ranks = tuple(min(4, r) for r in rt)
+    d = synth.case_tucker(307 + dims[0], dims, ranks, 30.0, rt, sweeps=2)
+    out, ref, Y = run_tucker(P, d, ranks, 2, "f32")
+    check_tucker(out, ref, Y, 3, 2, 1e-5, 2e-4, 2e-4)
+
+
 def test_tucker_fp32_4way(P):
     d = synth.case_tucker(302, (18, 20, 22, 24), (4, 5, 6, 7), 30.0, (6, 7, 8, 9),
                           sweeps=2)
