@@ -350,16 +350,60 @@ __global__ __launch_bounds__(kQrThreads) void qr_chol_kernel(QrBatch b, int pass
   }
 }
 
+__device__ __forceinline__ double wave_read(double v, int src) {   // src uniform
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// (the rotations need c^2 + s^2 = 1 to working precision)
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- Jacobi
+// One workgroup of four wavefronts per matrix.  A round (n/2 rotations, then
+// the 2 x 2 block updates of S and the column-pair updates of V) is a short
+// dependent chain; every lane owns at most kBlk blocks and kVp V entries,
+// whose indices are computed once, and issues all of its loads of a round
+// before its stores.  The round-robin pair schedule is arithmetic.
 constexpr int kEigThreads = 256;
 constexpr int kEigMax = 64;
+
+// Pair p of round r in the round-robin schedule over np players (np even;
+// every index >= n is the dummy).  With p < np/2 and r < np - 1 both
+// arguments of the reductions mod np - 1 lie in [0, 2(np - 1)), so one
+// conditional subtraction replaces them.
+__device__ __forceinline__ void jacobi_pair(int p, int r, int np, int& lo, int& hi) {
+  const int m = np - 1;
+  int x = p - 1 + r;
+  x = x >= m ? x - m : x;
+  int y = np - 2 - p + r;
+  y = y >= m ? y - m : y;
+  const int a = (p == 0) ? 0 : 1 + x;
+  const int q = 1 + y;
+  lo = a < q ? a : q;
+  hi = a < q ? q : a;
+}
 
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   __shared__ double S[kEigMax][kEigMax + 1];
   __shared__ double V[kEigMax][kEigMax + 1];
   __shared__ double cs[kEigMax / 2][2];
-  __shared__ int pr[kEigMax / 2][2];
   __shared__ double red[kEigThreads / 64];
+  __shared__ int flag[2];
   __shared__ int rankpos[kEigMax];
   const int m = blockIdx.x;
   const int n = b.n[m];
@@ -373,82 +417,118 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   }
   __syncthreads();
   const int np = (n + 1) & ~1;  // even number of players (dummy = n)
+  const int hp = np / 2;
   double fro = 0.0;
-  {
-    double p = 0.0;
-    for (int l = t; l < n * n; l += kEigThreads) {
-      double x = S[l / n][l % n];
-      p += x * x;
-    }
-    fro = block_sum(p, red);
+  for (int l = t; l < n * n; l += kEigThreads) {
+    const double x = S[l / n][l % n];
+    fro += x * x;
   }
-  // off-diagonal norm below 1e-13 of the matrix norm (above the rounding
-  // floor of the rotations, so the loop ends after a few sweeps)
-  const double thresh = 1e-26 * fro + 1e-300;
+  // A pair is rotated only while |a_pq| > 1e-14 ||S||_F (threshold Jacobi):
+  // a per-element test stays above the rounding floor of the 2 x 2 updates
+  // (a few ulps of ||S||), where a test on the whole off-diagonal norm can
+  // sit at that floor and never pass.  The sweeps end after one in which no
+  // pair was rotated.
+  const double thresh = 1e-14 * sqrt(block_sum(fro, red)) + 1e-300;
+  // the lane's blocks (pair indices pa, pb) and V entries (row i, pair pb)
+  // do not depend on the round: index arithmetic once, not per round
+  constexpr int kBlk = kEigMax * kEigMax / 4 / kEigThreads;   // 4
+  constexpr int kVp = kEigMax * kEigMax / 2 / kEigThreads;    // 8
+  int bpa[kBlk], bpb[kBlk], vi[kVp], vpb[kVp];
+#pragma unroll
+  for (int u = 0; u < kBlk; ++u) {
+    const int blk = u * kEigThreads + t;
+    bpa[u] = blk < hp * hp ? blk / hp : -1;
+    bpb[u] = blk < hp * hp ? blk - (blk / hp) * hp : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kVp; ++u) {
+    const int l = u * kEigThreads + t;
+    vi[u] = l < n * hp ? l / hp : -1;
+    vpb[u] = l < n * hp ? l - (l / hp) * hp : 0;
+  }
+  const int nblk = (hp * hp + kEigThreads - 1) / kEigThreads;   // slots in use
+  const int nvp = (n * hp + kEigThreads - 1) / kEigThreads;
+  int rc = 0;   // rounds so far (flag buffer parity)
   for (int sweep = 0; sweep < 40; ++sweep) {
-    double p = 0.0;
-    for (int l = t; l < n * n; l += kEigThreads) {
-      int i = l / n, j = l % n;
-      if (i != j) p += S[i][j] * S[i][j];
-    }
-    double off = block_sum(p, red);
-    if (off <= thresh) break;
-    const int hp = np / 2;
-    for (int r = 0; r < np - 1; ++r) {
-      if (t < hp) {
-        int a = (t == 0) ? 0 : 1 + ((t - 1 + r) % (np - 1));
-        int q = 1 + ((np - 2 - t + r) % (np - 1));
-        int lo = a < q ? a : q, hi = a < q ? q : a;
-        pr[t][0] = lo;
-        pr[t][1] = hi;
-        double c = 1.0, s = 0.0;
-        if (hi < n) {
-          double apq = S[lo][hi];
-          if (apq != 0.0) {
-            double tau = (S[hi][hi] - S[lo][lo]) / (2.0 * apq);
-            double tt = (tau >= 0.0 ? 1.0 : -1.0) /
-                        (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
+    bool swept = false;   // any rotation in this sweep (block-uniform)
+    for (int r = 0; r < np - 1; ++r, ++rc) {
+      if (t < 64) {   // hp <= 32: the rotations are wave 0's
+        bool rot = false;
+        if (t < hp) {
+          int lo, hi;
+          jacobi_pair(t, r, np, lo, hi);
+          double c = 1.0, s = 0.0;
+          if (hi < n) {
+            const double apq = S[lo][hi];
+            if (fabs(apq) > thresh) {
+              rot = true;
+              // tan of the smaller angle that annihilates apq:
+              // tt = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = a_qq - a_pp, e = 2 a_pq
+              const double d = S[hi][hi] - S[lo][lo], e = 2.0 * apq;
+              const double tt = (d >= 0.0 ? e : -e) / (fabs(d) + sqrt(d * d + e * e));
+              c = rsqrt_nr(1.0 + tt * tt);
+              s = tt * c;
+            }
           }
+          cs[t][0] = c;
+          cs[t][1] = s;
         }
-        cs[t][0] = c;
-        cs[t][1] = s;
+        const bool any = __ballot(rot) != 0;
+        if (t == 0) flag[rc & 1] = any ? 1 : 0;
       }
       __syncthreads();
-      // S <- J^T S J in place: the pairs partition the indices, so each
-      // thread owns a 2 x 2 block {lo_a, hi_a} x {lo_b, hi_b} (an index
-      // >= n is the dummy player: its row and column do not exist)
-      for (int blk = t; blk < hp * hp; blk += kEigThreads) {
-        const int pa = blk / hp, pb = blk - pa * hp;
-        const int i0 = pr[pa][0], i1 = pr[pa][1], j0 = pr[pb][0], j1 = pr[pb][1];
-        const double ca = cs[pa][0], sa = cs[pa][1], cb = cs[pb][0], sb = cs[pb][1];
+      if (flag[rc & 1] == 0) continue;   // nothing to apply this round
+      swept = true;
+      // S <- J^T S J in place: the pairs partition the indices, so the 2 x 2
+      // blocks {lo_a, hi_a} x {lo_b, hi_b} are disjoint (an index >= n is
+      // the dummy player: its row and column do not exist)
+#pragma unroll
+      for (int u = 0; u < kBlk; ++u) {
+        if (u >= nblk) break;
+        if (bpa[u] < 0) continue;
+        const int pa = bpa[u], pb = bpb[u];
+        int i0, i1, j0, j1;
+        jacobi_pair(pa, r, np, i0, i1);
+        jacobi_pair(pb, r, np, j0, j1);
         const bool r1 = i1 < n, c1 = j1 < n;
+        const int i1c = r1 ? i1 : i0, j1c = c1 ? j1 : j0;
+        const double ca = cs[pa][0], sa = cs[pa][1], cb = cs[pb][0], sb = cs[pb][1];
         const double b00 = S[i0][j0];
-        const double b01 = c1 ? S[i0][j1] : 0.0;
-        const double b10 = r1 ? S[i1][j0] : 0.0;
-        const double b11 = (r1 && c1) ? S[i1][j1] : 0.0;
-        // rows: J^T
+        const double b01 = c1 ? S[i0][j1c] : 0.0;
+        const double b10 = r1 ? S[i1c][j0] : 0.0;
+        const double b11 = (r1 && c1) ? S[i1c][j1c] : 0.0;
         const double x00 = ca * b00 - sa * b10, x01 = ca * b01 - sa * b11;
         const double x10 = sa * b00 + ca * b10, x11 = sa * b01 + ca * b11;
-        // columns: J
         S[i0][j0] = cb * x00 - sb * x01;
         if (c1) S[i0][j1] = sb * x00 + cb * x01;
         if (r1) S[i1][j0] = cb * x10 - sb * x11;
         if (r1 && c1) S[i1][j1] = sb * x10 + cb * x11;
       }
-      // V <- V J: each thread owns one row's pair of columns
-      for (int l = t; l < n * hp; l += kEigThreads) {
-        const int i = l / hp, pb = l - i * hp;
-        const int j0 = pr[pb][0], j1 = pr[pb][1];
+      // V <- V J: the lane's (row, column pair) entries; loads first
+      double vv[kVp][2];
+#pragma unroll
+      for (int u = 0; u < kVp; ++u) {
+        if (u >= nvp) break;
+        int j0, j1;
+        jacobi_pair(vpb[u], r, np, j0, j1);
+        const int i = vi[u] < 0 ? 0 : vi[u];
+        vv[u][0] = V[i][j0];
+        vv[u][1] = V[i][j1 < n ? j1 : j0];
+      }
+#pragma unroll
+      for (int u = 0; u < kVp; ++u) {
+        if (u >= nvp) break;
+        if (vi[u] < 0) continue;
+        int j0, j1;
+        jacobi_pair(vpb[u], r, np, j0, j1);
         if (j1 >= n) continue;
-        const double cb = cs[pb][0], sb = cs[pb][1];
-        const double vp = V[i][j0], vq = V[i][j1];
-        V[i][j0] = cb * vp - sb * vq;
-        V[i][j1] = sb * vp + cb * vq;
+        const double cb = cs[vpb[u]][0], sb = cs[vpb[u]][1];
+        V[vi[u]][j0] = cb * vv[u][0] - sb * vv[u][1];
+        V[vi[u]][j1] = sb * vv[u][0] + cb * vv[u][1];
       }
       __syncthreads();
     }
+    if (!swept) break;
   }
   // descending order, ties by ascending index
   if (t < n) {
@@ -504,20 +584,6 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ double wave_read(double v, int src) {   // src uniform
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), src);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<unsigned int>(lo));
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // R^{-1} for the upper Cholesky factor R of the K x K matrix S (S = R^T R),
 // by one wavefront: lane c keeps column c of the trailing matrix in
 // registers (right-looking; row j of R is published in LDS each step),
@@ -545,10 +611,7 @@ __device__ __forceinline__ bool chol_inv_wave(const double* S, int K, double* Ri
         ok = false;
         d = 1.0;
       }
-      double y = __builtin_amdgcn_rsq(d);
-      const double h = 0.5 * d;
-      y = y * fma(-h * y, y, 1.5);
-      y = y * fma(-h * y, y, 1.5);
+      const double y = rsqrt_nr(d);
       col[j] = (c == j) ? d * y : (c > j ? col[j] * y : 0.0);
       if (c == j) rdiag[j] = y;
       double* rb = rowbuf + 32 * (j & 1);
