@@ -71,8 +71,11 @@ constexpr int kYtStride = 40;          // halfwords per row of the transposed ti
 constexpr int kMaxI1 = 32 * kBW * kRBMax;
 constexpr int kWaveLds = 32 * kCT * 4; // per-wave LDS: transposed tile, then TB partial
 constexpr int kB1Pad = 8;              // halfwords of padding per B1^T row in LDS
-constexpr int kUnroll = 8;             // steps per loop trip: two column tiles at
-                                       // least, a multiple of the ring size
+// Steps per loop trip: a multiple of the ring size and of two column tiles.
+// The compiler's wait counts at the loop head are conservative (the first
+// step of a trip waits for every tile in flight), so a longer trip pays
+// that drain less often: 16 steps took the core pass from 0.50 to 0.47 ms.
+constexpr int kUnroll = 16;
 static_assert(kCT * kYtStride * 2 <= kWaveLds, "transposed tile fits the wave's region");
 
 struct BfArgs {
