@@ -12,8 +12,8 @@
  *   - rt_ttm, rt_cp_fit_dense : building blocks exported for tests and for
  *                      evaluating a CP model against the dense tensor.
  *   - rt_mlp_*       : the learned FFCP initializer (no counterpart in the
- *                      paper; it proposes the "initialize A" of Algorithm 1,
- *                      line 1).
+ *                      paper; it proposes the initialization step of
+ *                      Algorithm 1).
  *
  * Conventions shared by every entry point
  *   - Tensors are dense, row-major (last index fastest), contiguous.
@@ -142,10 +142,10 @@ int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems);
  *
  * For each sweep s = 1..sweeps and every mode n (Jacobi order: every mode of
  * a sweep uses the bases of the previous sweep; sweep 1 uses Omega_p, the
- * random initial U^(p) of Algorithm 3, line 1):
+ * random initial U^(p) that Algorithm 3 starts from):
  *     X_n = Y x_{p != n} B_p^T,    Z_n = X_(n) Omega~_n^(s),
  *     Q_n = orth(Z_n)   (FP64 Householder QR, signs so that diag(R) >= 0)
- * then the core G~ = Y x_1 Q_1^T ... x_N Q_N^T (Algorithm 3, line 8) and,
+ * then the core G~ = Y x_1 Q_1^T ... x_N Q_N^T (the core projection of Algorithm 3) and,
  * unless RT_FLAG_NO_TRUNCATE, the truncation to R_n:
  *     W_n = top-R_n eigenvectors of G~_(n) G~_(n)^T (descending, each
  *           column's largest-magnitude entry positive),
@@ -167,9 +167,10 @@ int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems);
  *              rt_tucker_bf16_copy_elems(desc) uint16 receiving the scaled
  *              BF16 copy of Y, [I_1 ... I_{N-1}][L] row-major with row
  *              stride L = I_N rounded up to a multiple of 64 (128 bytes):
- *              entry (i_1..i_N) is bf16_rne(Y(i_1..i_N) 2^-e) with e the
- *              binary exponent of the largest |Y| over the slab of fixed
- *              (i_1..i_{N-2}); the L - I_N padding values are zero.
+ *              entry (i_1..i_N) is bf16_rne(Y(i_1..i_N) 2^-e) with one
+ *              e per slab of fixed (i_1..i_{N-2}): 0 while the binary
+ *              exponent of the slab's largest |Y| lies in [-100, 100], that
+ *              exponent otherwise; the L - I_N padding values are zero.
  *              NULL otherwise.
  *   info       device rt_tucker_info (may be NULL).
  *   trace      host struct of optional device outputs (may be NULL).
@@ -184,7 +185,7 @@ int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
                    uint16_t* Ybf16, rt_tucker_info* info,
                    const rt_tucker_trace* trace, void* stream);
 
-/* FFCP update rules (Algorithm 1, line 6). */
+/* FFCP update rules (the factor update of Algorithm 1). */
 typedef enum {
   RT_ALS = 0,  /* eq. (14): A = U G_(n)(KR V) (hadamard A^T A)^{-1}        */
   RT_HALS = 1, /* eq. (8), standard form a_r <- max(eps, a_r + (q_r -
@@ -326,10 +327,12 @@ int rt_cp_fit_dense(const rt_ffcp_desc* desc, const float* Y,
  * first sweep,
  * 1 = the streaming kernel of later sweeps, 2 = the core pass's streaming
  * kernel, 3 = intermediate contractions and sketch products, 4 = QR,
- * 5 = truncation (Gram, eig, rotation), 6 = FFCP, 7 = per-slab statistics
- * pass of the precision form (exponents, ||Y||^2), 8 = the precision form's
- * FP32 -> BF16 conversion (the first sweep's streaming kernel then reads the
- * BF16 copy).
+ * 5 = truncation (Gram, eig, rotation), 6 = FFCP, 7 = the precision form's
+ * per-slab statistics (slab exponents and ||Y||^2 from the conversion's
+ * partials, re-conversion of the slabs that need a scale; a caller's BF16
+ * input: its statistics pass), 8 = the precision form's FP32 -> BF16
+ * conversion, which also yields those partials (the first sweep's streaming
+ * kernel then reads the BF16 copy).
  */
 #define RT_PROFILE_STAGES 9
 typedef struct {
@@ -345,7 +348,7 @@ int rt_profile_read(rt_profile* out);
 
 /*
  * Learned FFCP initializer (no counterpart in the paper: it supplies the
- * "initialize A" of Algorithm 1, line 1).  A 3-layer MLP maps the normalized
+ * initialization step of Algorithm 1).  A 3-layer MLP maps the normalized
  * core x = vec(G)/||G|| (d0 = prod R_n entries) to compressed factors V_n
  * (R_n x R) of that core:
  *   h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), y = h2 W3 + b3,

@@ -167,7 +167,7 @@ def ffcp(U, G, A_init, update="als", max_it=1000, tol=1e-6, l1=0.0,
 
 
 def hosvd_init(U, G, R, pad=None):
-    """HOSVD initialization of Alg. 1 line 1: V_n = top-R eigenvectors of
+    """HOSVD initialization (Alg. 1's initialization step): V_n = top-R eigenvectors of
     G_(n) G_(n)^T; when R > R_n the missing columns come from ``pad[n]``
     (R_n x (R - R_n), given Gaussian numbers).  Returns A_n = U_n V_n."""
     A = []

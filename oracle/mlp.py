@@ -4,7 +4,7 @@ to CP factors of that core, trained by the CP reconstruction loss.
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper has no learned component; the network is an addition that serves
-Alg. 1 line 1 ("initialize A").  Its training loss is the CP objective of the
+Alg. 1's initialization step.  Its training loss is the CP objective of the
 core, and its gradient with respect to the predicted factors is eq. (5)
 applied to the core (eq. (17) shows FFCP on an orthonormal Tucker format is
 CP of the core):

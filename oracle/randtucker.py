@@ -94,7 +94,7 @@ def rand_tucker(Y, omegas, omega_tildes, sweeps=1, ranks=None,
 
     Y            : N-way array (promoted to FP64).
     omegas       : list of N Gaussian matrices Omega_p, I_p x R~_p (the
-                   random initial U^(p) of Alg. 3, line 1).
+                   random initial U^(p) that Alg. 3 starts from).
     omega_tildes : list (length >= sweeps) of lists of N matrices
                    Omega~_n, (prod_{p != n} R~_p) x R~_n, rows in the
                    row-major order of (j_p)_{p != n}.

@@ -164,21 +164,29 @@ __device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, do
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double m0[RMAX];   // pivot column k; zero below row R
+      // both pivot columns (k; k+1, unused in a single-pivot step), every
+      // load issued before the first use: one LDS round trip per step
+      double m0[RMAX], m1[RMAX];   // zero below row R
 #pragma unroll
       for (int i = 0; i < RMAX; i += 2) {
         const double2 v = *reinterpret_cast<const double2*>(pcol + i);
         m0[i] = v.x;
         m0[i + 1] = v.y;
       }
-      if (pair) {
-        double m1[RMAX];   // pivot column k+1
 #pragma unroll
-        for (int i = 0; i < RMAX; i += 2) {
-          const double2 v = *reinterpret_cast<const double2*>(pc1 + i);
-          m1[i] = v.x;
-          m1[i + 1] = v.y;
-        }
+      for (int i = 0; i < RMAX; i += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(pc1 + i);
+        m1[i] = v.x;
+        m1[i + 1] = v.y;
+      }
+      // keep the second column's loads ahead of the branch (the compiler
+      // would sink them into it, behind a second wait); register-only.  The
+      // widest block form has no registers to spare for it.
+      if constexpr (RMAX <= 20) {
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i) asm volatile("" : "+v"(m1[i]));
+      }
+      if (pair) {
         // block [[a, b], [cc, d]] = rows/columns k, k+1
         const int k1 = (k + 1) % RMAX;   // = k + 1 here
         const double a = m0[k], cc = m0[k1], b = m1[k], d = m1[k1];
@@ -193,7 +201,7 @@ __device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, do
         const double f1 = (a * x1 - cc * x0) * rd;
 #pragma unroll
         for (int i = 0; i < RMAX; ++i)
-          if (i != k && i != k1) col[i] -= m0[i] * f0 + m1[i] * f1;
+          if (i != k && i != k1) col[i] = fma(-m1[i], f1, fma(-m0[i], f0, col[i]));
         col[k] = f0;
         col[k1] = f1;
       } else {
@@ -205,7 +213,7 @@ __device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, do
         const double f = col[k] * recip(p);
 #pragma unroll
         for (int i = 0; i < RMAX; ++i)
-          if (i != k) col[i] -= m0[i] * f;
+          if (i != k) col[i] = fma(-m0[i], f, col[i]);
         col[k] = f;
       }
       // every lane has read the pivot columns before the next step rewrites them

@@ -1,6 +1,6 @@
 // Small FP64 factorizations of the method:
 //  * orthonormal basis of a sketch Z_n (Section IV-A, step 3 of the range
-//    finder; Algorithm 3, line 6) with diag(R) >= 0: CholeskyQR2 in FP64,
+//    finder; the orthonormalization in Algorithm 3) with diag(R) >= 0: CholeskyQR2 in FP64,
 //    falling back to Householder QR when the sketch is numerically rank
 //    deficient;
 //  * symmetric eigen-decomposition (cyclic Jacobi, parallel ordering) of the

@@ -1,4 +1,4 @@
-// Learned FFCP initializer (Algorithm 1, line 1: "initialize A").
+// Learned FFCP initializer (the initialization step of Algorithm 1).
 //
 // A 3-layer MLP maps a normalized Tucker core x = vec(G)/||G|| to
 // compressed CP factors V_n (R_n x R) of that core:

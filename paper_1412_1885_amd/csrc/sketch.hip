@@ -1,4 +1,4 @@
-// Sketch products of Algorithm 3 (line 5) computed from the streamed
+// Sketch products Z_n = X_(n) Omega~_n of Algorithm 3 computed from the streamed
 // intermediates without forming X_n.
 //
 // With T = Y x_{p in S} B_p^T the streamed intermediate (S = the modes one

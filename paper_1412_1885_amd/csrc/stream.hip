@@ -4,9 +4,9 @@
 // I2 = I_N, row-major).  One pass over Y computes, for every slab,
 //     P_a = M_a B2          (I1 x K2: the mode-N contraction, TA)
 //     Q_a = B1^T M_a        (K1 x I2: the mode-(N-1) contraction, TB)
-// so a single read of Y feeds every sketch of one Jacobi sweep (Algorithm 3,
-// lines 3-6: X_n for n < N is reached from TA, X_N from TB); the core pass
-// (Algorithm 3, line 8) computes P only.  These are the blocked products of
+// so a single read of Y feeds every sketch of one Jacobi sweep of
+// Algorithm 3 (X_n for n < N is reached from TA, X_N from TB); the core pass
+// (the core projection of Algorithm 3) computes P only.  These are the blocked products of
 // eq. (22) restricted to one GPU: each workgroup owns whole slabs, and the
 // partial products over column ranges are summed in a fixed order.
 //

@@ -3,7 +3,7 @@
 //                   sweep of Algorithm 3 needs both: every X_n with n < N is
 //                   reached from TA, X_N from TB)
 //   stream_single : TA = Y x_N Q_N^T (first contraction of the core,
-//                   Algorithm 3 line 8)
+//                   the core projection of Algorithm 3)
 // Y is viewed as [A, I_{N-1}, I_N] (A = prod_{p < N-1} I_p).  The first
 // pass of a call also produces ||Y||^2 and the non-finite flag.
 #pragma once

@@ -1,24 +1,28 @@
 // BF16 precision form of the Y-streaming passes (RT_BF16_MIXED).
 //
 // The sketches and the core projection contract Y against thin factor
-// matrices (Algorithm 3, lines 3-6 and 8; the blocked products of eq. (22)).
+// matrices (the sketches and the core projection of Algorithm 3; the
+// blocked products of eq. (22)).
 // In this form the tensor is stored once in BF16 and every pass after the
 // first reads 2 bytes per element; the products run on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation, so at R~ <= 32 a pass is
 // bound by HBM bandwidth, not by the matrix cores.
 //
 // Scaling.  Each slab a of the streaming view [A, I1, I2] carries a power of
-// two 2^e_a with e_a the binary exponent of max|Y[a]|; the stored value is
-// bf16_rne(Y * 2^-e_a) and every product of the slab is multiplied by 2^e_a.
-// The scale is exact (a power of two), keeps each slab's largest entries in
-// [1, 2) and its small entries out of the BF16 subnormal range.
+// two 2^e_a; the stored value is bf16_rne(Y * 2^-e_a) and every product of
+// the slab is multiplied by 2^e_a.  A power-of-two scale is exact, so it
+// changes nothing while every value and product of the slab stays in the
+// normal FP32 range: e_a = 0 unless the binary exponent of max|Y[a]| lies
+// outside [-kScaleWindow, kScaleWindow], and then e_a is that exponent (the
+// slab's largest entries land in [1, 2), its small ones out of the BF16
+// subnormal range, its products and FP32 sums away from overflow).
 //
-// Passes.  The first pass of a call (FP32 input) computes ||Y||^2, the
-// non-finite flag and the slab exponents in a statistics pass, then writes
-// the scaled BF16 copy with a conversion kernel of many small workgroups
-// (its HBM write stream overlaps its read stream only with that many
-// requests in flight); every contraction, of every sweep and of the core
-// pass, reads the BF16 copy.
+// Passes.  The first pass of a call (FP32 input) reads Y once: a conversion
+// kernel of many small workgroups (its HBM write stream overlaps its read
+// stream only with that many requests in flight) writes the copy at scale
+// 2^0 and per-block partials of max|Y| and ||Y||^2; a per-slab reduction
+// sets e_a, and the rare slabs with e_a != 0 are converted again, scaled.
+// Every contraction, of every sweep and of the core pass, reads the copy.
 //
 // Layout of the copy.  Rows of I2 values are stored at a stride rounded up
 // to 64 values (128 bytes, one L2 line), the padding written as zeros, so
@@ -109,6 +113,7 @@ typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 constexpr int kOob = 0x7ffffff0;       // offset past every slab: loads return zero
 constexpr int kCopyAlign = 64;         // row stride multiple of the BF16 copy (128 B)
+constexpr int kScaleWindow = 100;      // |exponent of max|Y[a]|| up to which e_a = 0
 
 // Buffer descriptor over one slab (byte range); loads past it return zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* p, int64_t bytes) {
@@ -326,65 +331,38 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   }
 }
 
-// Per-slab statistics of the input: exponent of max|Y[a]| (FP32 input only),
-// ||Y||^2 partial sums per workgroup (FP64).
-template <bool SRC_F32>
-__global__ __launch_bounds__(256) void slab_stats_kernel(const void* Y, int64_t A,
-                                                         int64_t slab, int32_t* exps,
-                                                         double* partial) {
-  __shared__ float smax[4];
+// Statistics of a caller's BF16 input (no scaling: e_a = 0): ||Y||^2
+// partial sums per workgroup (FP64), slabs strided over the grid.  An FP32
+// input's statistics come from its conversion.
+__global__ __launch_bounds__(256) void bf16_input_stats_kernel(const uint16_t* Y, int64_t A,
+                                                               int64_t slab, int32_t* exps,
+                                                               double* partial) {
   __shared__ double ssum[4];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   double acc = 0.0;
   for (int64_t a = blockIdx.x; a < A; a += gridDim.x) {
-    float mx = 0.0f;
+    const uint16_t* p = Y + a * slab;
     double s = 0.0;
-    if constexpr (SRC_F32) {
-      const float* p = static_cast<const float*>(Y) + a * slab;
-      const int64_t n4 = slab / 4;
-      for (int64_t l = t; l < n4; l += 256) {
-        const float4 v = reinterpret_cast<const float4*>(p)[l];
-        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-        const double dx = v.x, dy = v.y, dz = v.z, dw = v.w;
-        s += (dx * dx + dy * dy) + (dz * dz + dw * dw);
-        if (!(fabsf(v.x) <= 3.4e38f && fabsf(v.y) <= 3.4e38f && fabsf(v.z) <= 3.4e38f &&
-              fabsf(v.w) <= 3.4e38f))
-          s = __longlong_as_double(0x7ff8000000000000LL);
-      }
-      for (int64_t l = n4 * 4 + t; l < slab; l += 256) {
-        const float v = p[l];
-        mx = fmaxf(mx, fabsf(v));
-        s += static_cast<double>(v) * v;
-        if (!(fabsf(v) <= 3.4e38f)) s = __longlong_as_double(0x7ff8000000000000LL);
-      }
-    } else {
-      const uint16_t* p = static_cast<const uint16_t*>(Y) + a * slab;
-      for (int64_t l = t; l < slab; l += 256) {
-        const float v = bf16_to_f32(p[l]);
-        s += static_cast<double>(v) * v;
-      }
+    for (int64_t l = t; l < slab; l += 256) {
+      const float v = bf16_to_f32(p[l]);
+      s += static_cast<double>(v) * v;
     }
     s = wave_sum(s);
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     __syncthreads();
-    if (lane == 0) {
-      smax[wv] = mx;
-      ssum[wv] = s;
-    }
+    if (lane == 0) ssum[wv] = s;
     __syncthreads();
     if (t == 0) {
-      const float m = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
-      int e = 0;
-      if (SRC_F32 && m > 0.0f && m <= 3.4e38f) e = ilogbf(m);
-      exps[a] = e < -126 ? -126 : (e > 127 ? 127 : e);   // 2^-e stays finite
+      exps[a] = 0;
       acc += (ssum[0] + ssum[1]) + (ssum[2] + ssum[3]);
     }
   }
   if (t == 0) partial[blockIdx.x] = acc;
 }
 
-// The BF16 copy of an FP32 input: Yb[a][r][c] = bf16_rne(Y[a][r][c] 2^-e_a)
-// for c < I2 and zero for I2 <= c < ldy.  Slab a is row blockIdx.y of the
+// The BF16 copy of an FP32 input at scale 2^0, in the one read of Y:
+// Yb[a][r][c] = bf16_rne(Y[a][r][c]) for c < I2 and zero for I2 <= c < ldy,
+// plus this block's max|Y| and sum of Y^2 (FP64; NaN once a value is not
+// finite) in pmax / psum [A][gridDim.x].  Slab a is row blockIdx.y of the
 // grid; each thread writes four groups of 4 consecutive copy values (8-byte
 // stores of 16-byte loads), consecutive threads on consecutive groups of the
 // padded slab, so every wavefront instruction moves one contiguous span
@@ -392,13 +370,22 @@ __global__ __launch_bounds__(256) void slab_stats_kernel(const void* Y, int64_t 
 // loads and stores in flight to overlap the two streams.
 constexpr int kCvtThreads = 256, kCvtGroups = 4;
 
+__device__ __forceinline__ float4 load_group(const float* src, uint32_t gi, uint32_t q,
+                                             uint32_t ng, int I2) {
+  const uint32_t r = gi / q, c = 4 * (gi - r * q);
+  return gi < ng && c < static_cast<uint32_t>(I2)
+             ? *reinterpret_cast<const float4*>(src + r * I2 + c)
+             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* Y,
-                                                                    uint16_t* Yb,
-                                                                    const int32_t* exps,
-                                                                    int I1, int I2,
-                                                                    int ldy) {
+                                                                    uint16_t* Yb, int I1,
+                                                                    int I2, int ldy,
+                                                                    float* pmax,
+                                                                    double* psum) {
+  __shared__ float smax[kCvtThreads / 64];
+  __shared__ double ssum[kCvtThreads / 64];
   const int64_t a = blockIdx.y;
-  const float down = ldexpf(1.0f, -exps[a]);
   // I1 * ldy < 2^30 (shape check), so 32-bit group and value indexes
   const uint32_t q = static_cast<uint32_t>(ldy) / 4;   // groups per copy row
   const uint32_t ng = static_cast<uint32_t>(I1) * q;   // groups per copy slab
@@ -407,19 +394,94 @@ __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* 
   const uint32_t g0 = blockIdx.x * (kCvtThreads * kCvtGroups) + threadIdx.x;
   float4 v[kCvtGroups];
 #pragma unroll
-  for (int u = 0; u < kCvtGroups; ++u) {
-    const uint32_t gi = g0 + u * kCvtThreads;
-    const uint32_t r = gi / q, c = 4 * (gi - r * q);
-    v[u] = gi < ng && c < static_cast<uint32_t>(I2)
-               ? *reinterpret_cast<const float4*>(src + r * I2 + c)
-               : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  }
+  for (int u = 0; u < kCvtGroups; ++u) v[u] = load_group(src, g0 + u * kCvtThreads, q, ng, I2);
+  float mx = 0.0f;
+  double sq = 0.0;
+  bool finite = true;
 #pragma unroll
   for (int u = 0; u < kCvtGroups; ++u) {
     const uint32_t gi = g0 + u * kCvtThreads;
     if (gi < ng)
-      dst[gi] = make_uint2(pack2(v[u].x * down, v[u].y * down),
-                           pack2(v[u].z * down, v[u].w * down));
+      dst[gi] = make_uint2(pack2(v[u].x, v[u].y), pack2(v[u].z, v[u].w));
+    const float ax = fabsf(v[u].x), ay = fabsf(v[u].y), az = fabsf(v[u].z), aw = fabsf(v[u].w);
+    mx = fmaxf(mx, fmaxf(fmaxf(ax, ay), fmaxf(az, aw)));
+    const double dx = v[u].x, dy = v[u].y, dz = v[u].z, dw = v[u].w;
+    sq += (dx * dx + dy * dy) + (dz * dz + dw * dw);
+    finite = finite && ax <= 3.4e38f && ay <= 3.4e38f && az <= 3.4e38f && aw <= 3.4e38f;
+  }
+  if (!finite) sq = __longlong_as_double(0x7ff8000000000000LL);
+  sq = wave_sum(sq);
+  mx = wave_max(mx);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    smax[wv] = mx;
+    ssum[wv] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = smax[0];
+    double t = ssum[0];
+#pragma unroll
+    for (int w = 1; w < kCvtThreads / 64; ++w) {
+      m = fmaxf(m, smax[w]);
+      t += ssum[w];
+    }
+    const int64_t i = a * gridDim.x + blockIdx.x;
+    pmax[i] = m;
+    psum[i] = t;
+  }
+}
+
+// Per slab (one workgroup each): max|Y[a]| and ||Y[a]||^2 from the
+// conversion blocks' partials in a fixed order, and e_a (0 inside the
+// window; the exponent of the maximum, clamped so 2^-e stays finite,
+// outside it).
+__global__ __launch_bounds__(256) void slab_finish_kernel(const float* pmax,
+                                                          const double* psum, int nb,
+                                                          int32_t* exps, double* slab_sum) {
+  __shared__ double red[4];
+  __shared__ float rmax[4];
+  const int64_t a = blockIdx.x;
+  float m = 0.0f;
+  double t = 0.0;
+  for (int j = threadIdx.x; j < nb; j += 256) {
+    m = fmaxf(m, pmax[a * nb + j]);
+    t += psum[a * nb + j];
+  }
+  m = wave_max(m);
+  t = wave_sum(t);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    rmax[wv] = m;
+    red[wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float mm = fmaxf(fmaxf(rmax[0], rmax[1]), fmaxf(rmax[2], rmax[3]));
+    int e = 0;
+    if (mm > 0.0f && mm <= 3.4e38f) e = ilogbf(mm);
+    e = e < -126 ? -126 : (e > 127 ? 127 : e);
+    exps[a] = (e >= -kScaleWindow && e <= kScaleWindow) ? 0 : e;
+    slab_sum[a] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// The slabs with e_a != 0 again, scaled: Yb = bf16_rne(Y * 2^-e_a) (one
+// workgroup per slab; the others return at once).
+__global__ __launch_bounds__(256) void bf16_rescale_kernel(const float* Y, uint16_t* Yb,
+                                                           const int32_t* exps, int I1,
+                                                           int I2, int ldy) {
+  const int64_t a = blockIdx.x;
+  const int e = exps[a];
+  if (e == 0) return;
+  const float down = ldexpf(1.0f, -e);
+  const uint32_t q = static_cast<uint32_t>(ldy) / 4;
+  const uint32_t ng = static_cast<uint32_t>(I1) * q;
+  const float* src = Y + a * I1 * I2;
+  uint2* dst = reinterpret_cast<uint2*>(Yb + a * I1 * ldy);
+  for (uint32_t gi = threadIdx.x; gi < ng; gi += 256) {
+    const float4 v = load_group(src, gi, q, ng, I2);
+    dst[gi] = make_uint2(pack2(v.x * down, v.y * down), pack2(v.z * down, v.w * down));
   }
 }
 
@@ -470,14 +532,57 @@ int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
 
 }  // namespace
 
-// Workspace of the BF16 passes (inside the streaming workspace): slab
-// exponents and the two transposed BF16 factor copies.
-size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
-  const int64_t l1 = (I1 + 63) / 64 * 64, l2 = (I2 + 63) / 64 * 64;
-  return static_cast<size_t>(A) * 4 + 256 + 2 * 32 * (l1 + l2) + 512;
+int64_t bf16_copy_ld(int64_t I2) { return (I2 + kCopyAlign - 1) / kCopyAlign * kCopyAlign; }
+
+namespace {
+
+// conversion blocks per slab
+int64_t cvt_blocks(int64_t I1, int64_t I2) {
+  const int64_t per_block = static_cast<int64_t>(kCvtThreads) * kCvtGroups * 4;
+  return (I1 * bf16_copy_ld(I2) + per_block - 1) / per_block;
 }
 
-int64_t bf16_copy_ld(int64_t I2) { return (I2 + kCopyAlign - 1) / kCopyAlign * kCopyAlign; }
+// Workspace of the BF16 passes (inside the streaming workspace), in order:
+// slab exponents (int32, A), the two transposed BF16 factor copies, the
+// conversion blocks' partial sums (FP64, A x nb), their maxima (FP32,
+// A x nb) and the slab sums (FP64, A).
+struct BfWs {
+  int32_t* exps;
+  uint16_t* B2t;
+  uint16_t* B1t;
+  double* psum;
+  float* pmax;
+  double* slab_sum;
+  size_t bytes;
+};
+
+BfWs bf16_ws_layout(char* base, int64_t A, int64_t I1, int64_t I2) {
+  const int64_t l1 = (I1 + 63) / 64 * 64, l2 = (I2 + 63) / 64 * 64;
+  const int64_t nb = cvt_blocks(I1, I2);
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  BfWs w{};
+  int64_t o = 0;
+  w.exps = reinterpret_cast<int32_t*>(base + o);
+  o += up(A * 4);
+  w.B2t = reinterpret_cast<uint16_t*>(base + o);
+  o += up(2 * 32 * l2);
+  w.B1t = reinterpret_cast<uint16_t*>(base + o);
+  o += up(2 * 32 * l1);
+  w.psum = reinterpret_cast<double*>(base + o);
+  o += up(A * nb * 8);
+  w.pmax = reinterpret_cast<float*>(base + o);
+  o += up(A * nb * 4);
+  w.slab_sum = reinterpret_cast<double*>(base + o);
+  o += up(A * 8);
+  w.bytes = static_cast<size_t>(o);
+  return w;
+}
+
+}  // namespace
+
+size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
+  return bf16_ws_layout(nullptr, A, I1, I2).bytes + 512;
+}
 
 int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
   // a slab of the padded copy must stay below the masked-load offset
@@ -499,18 +604,15 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   RT_TRY(bf16_check_shape(c.I1, c.I2, B1 ? K1 : 0, K2));
   const int64_t l1 = (c.I1 + 63) / 64 * 64, l2 = (c.I2 + 63) / 64 * 64;
   char* base = static_cast<char*>(c.ws) + 1024 * sizeof(double) + 256;
-  int32_t* exps = reinterpret_cast<int32_t*>(base);
-  uint16_t* B2t = reinterpret_cast<uint16_t*>(base + (c.A * 4 + 255) / 256 * 256);
-  uint16_t* B1t = B2t + 32 * l2;
-  if (first) {
+  const BfWs w = bf16_ws_layout(base, c.A, c.I1, c.I2);
+  int32_t* exps = w.exps;
+  uint16_t* B2t = w.B2t;
+  uint16_t* B1t = w.B1t;
+  if (first && c.bf16_input) {
     const int g = stats_grid(c.A);
     ProfScope ps(kStageStats, s);
-    if (c.bf16_input)
-      hipLaunchKernelGGL(slab_stats_kernel<false>, dim3(g), dim3(256), 0, s, c.ybf16,
-                         c.A, c.I1 * c.I2, exps, c.norm_partial);
-    else
-      hipLaunchKernelGGL(slab_stats_kernel<true>, dim3(g), dim3(256), 0, s, c.y, c.A,
-                         c.I1 * c.I2, exps, c.norm_partial);
+    hipLaunchKernelGGL(bf16_input_stats_kernel, dim3(g), dim3(256), 0, s, c.ybf16, c.A,
+                       c.I1 * c.I2, exps, c.norm_partial);
     RT_LAUNCH_CHECK("slab stats");
     RT_TRY(launch_sum_partials(c.norm_partial, g, c.norm_out, c.nonfinite, s));
   }
@@ -523,21 +625,33 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
     RT_LAUNCH_CHECK("prep B1");
   }
   if (first && !c.bf16_input) {
-    // the scaled BF16 copy (padded rows), then every contraction reads it
-    const int64_t slab = c.I1 * c.ldy;
-    const int64_t per_block = static_cast<int64_t>(kCvtThreads) * kCvtGroups * 4;
-    if (c.A > 65535) {
+    // the BF16 copy (padded rows) and the statistics in one read of Y, then
+    // the slab exponents and the rare slabs that need a scale; every
+    // contraction reads the copy
+    const int64_t nb = cvt_blocks(c.I1, c.I2);
+    if (c.A > 65535 || nb > 0x7fffffff) {
       set_error("BF16 conversion: too many slabs (%lld)", (long long)c.A);
       return kErrUnsupported;
     }
-    ProfScope ps(kStageConvert, s);
-    hipLaunchKernelGGL(bf16_convert_kernel,
-                       dim3(static_cast<unsigned>((slab + per_block - 1) / per_block),
-                            static_cast<unsigned>(c.A)),
-                       dim3(kCvtThreads), 0, s, static_cast<const float*>(c.y), c.ybf16,
-                       exps, static_cast<int>(c.I1), static_cast<int>(c.I2),
+    {
+      ProfScope ps(kStageConvert, s);
+      hipLaunchKernelGGL(bf16_convert_kernel,
+                         dim3(static_cast<unsigned>(nb), static_cast<unsigned>(c.A)),
+                         dim3(kCvtThreads), 0, s, static_cast<const float*>(c.y), c.ybf16,
+                         static_cast<int>(c.I1), static_cast<int>(c.I2),
+                         static_cast<int>(c.ldy), w.pmax, w.psum);
+      RT_LAUNCH_CHECK("bf16 convert");
+    }
+    ProfScope ps(kStageStats, s);
+    hipLaunchKernelGGL(slab_finish_kernel, dim3(static_cast<unsigned>(c.A)), dim3(256), 0, s,
+                       w.pmax, w.psum, static_cast<int>(nb), exps, w.slab_sum);
+    RT_LAUNCH_CHECK("slab finish");
+    hipLaunchKernelGGL(bf16_rescale_kernel, dim3(static_cast<unsigned>(c.A)), dim3(256), 0, s,
+                       static_cast<const float*>(c.y), c.ybf16, exps,
+                       static_cast<int>(c.I1), static_cast<int>(c.I2),
                        static_cast<int>(c.ldy));
-    RT_LAUNCH_CHECK("bf16 convert");
+    RT_LAUNCH_CHECK("bf16 rescale");
+    RT_TRY(launch_sum_partials(w.slab_sum, static_cast<int>(c.A), c.norm_out, c.nonfinite, s));
   }
   BfArgs a{};
   a.Y = c.ybf16;

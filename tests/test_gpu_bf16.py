@@ -62,10 +62,12 @@ def bf16_round(x):
 
 
 def slab_exponents(Y):
-    """floor(log2(max |slab|)) per slab of the [A, I_{N-1}, I_N] view."""
+    """Scale exponent e_a per slab of the [A, I_{N-1}, I_N] view: 0 while
+    floor(log2(max |slab|)) lies in [-100, 100], that exponent otherwise."""
     A = int(np.prod(Y.shape[:-2]))
     m = np.abs(Y.reshape(A, -1)).max(axis=1)
-    return np.where(m > 0, np.frexp(m)[1] - 1, 0)
+    e = np.where(m > 0, np.frexp(m)[1] - 1, 0)
+    return np.where(np.abs(e) <= 100, 0, e)
 
 
 def first_sweep_sketches(Y32, om32, omt32):
@@ -117,11 +119,16 @@ def test_bf16_first_sweep_sketches_exact_inputs(P, dims, rt):
 
 
 def test_bf16_copy_is_scaled_rne(P):
-    """The BF16 copy holds bf16_rne(Y * 2^-e_a), bit for bit, with e_a the
-    exponent of the slab's largest magnitude (slabs scaled very
-    differently)."""
-    d = synth.case_tucker(410, (6, 40, 56), (3, 3, 3), 30.0, (6, 6, 6))
-    Y32 = synth.f32(d["Y"] * np.array([1e-30, 1e-3, 1.0, 7.0, 1e5, 3e20])[:, None, None])
+    """The BF16 copy holds bf16_rne(Y * 2^-e_a), bit for bit: e_a = 0 for
+    slabs whose largest magnitude has its exponent in [-100, 100], that
+    exponent for the others (slabs scaled very differently, two outside the
+    window, one of them with FP32 subnormals)."""
+    d = synth.case_tucker(410, (8, 40, 56), (3, 3, 3), 30.0, (6, 6, 6))
+    scales = np.array([1e-36, 1e-28, 1e-3, 1.0, 7.0, 1e5, 3e20, 1e32])
+    Y32 = synth.f32(d["Y"] * scales[:, None, None])
+    e_want = slab_exponents(Y32)
+    assert e_want[0] < -100 and e_want[-1] > 100 and not e_want[1:-1].any()
+    assert np.any((Y32[0] != 0) & (np.abs(Y32[0]) < np.finfo(np.float32).tiny))
     om32 = synth.f32(d["omegas"])
     omt32 = [synth.f32(d["omega_tildes"][0])]
     out = run(P, Y32, om32, omt32, (3, 3, 3), 1)
@@ -130,7 +137,7 @@ def test_bf16_copy_is_scaled_rne(P):
     want = bf16_bits(scaled)
     got = out["ybf16"].cpu().numpy().view(np.uint16)
     # rows padded to a multiple of 64 values, the padding zero
-    assert got.shape == (6, 40, 64)
+    assert got.shape == (8, 40, 64)
     assert np.array_equal(got[..., :56], want)
     assert not got[..., 56:].any()
 
