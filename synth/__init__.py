@@ -229,6 +229,41 @@ def cp_congruent_device(case, dims, R, c_lo, c_hi, snr_db, ranks_tilde,
             "init_rng": g["init"]}
 
 
+def nonneg_cp_device(case, dims, R, ranks_tilde, zero_frac=0.2, noise_sigma=0.01,
+                     sweeps=2, device="cuda"):
+    """The nonnegative CP workload of ``case_nonneg`` (U[0,1] factors with
+    exactly ``zero_frac`` zeros, |N(0, sigma)| noise) built in device memory:
+    factors and the method's randoms from the same seeded numpy streams;
+    Y* = [[A_1, ..., A_N]] formed in FP64 by torch (mode-1 unfolding times the
+    transposed Khatri-Rao product of the other factors); the noise from
+    torch's generator seeded with the case's noise stream; the sum rounded
+    once to FP32."""
+    import torch
+    g = rngs(case)
+    A = nonneg_factors(g["factors"], dims, R, "uniform", 1.0, zero_frac)
+    om = omegas(g["omega"], dims, ranks_tilde)
+    omt = [omega_tildes(g["omega_t1"], ranks_tilde)]
+    if sweeps >= 2:
+        omt.append(omega_tildes(g["omega_t2"], ranks_tilde))
+    noise_seed = int(g["noise"].integers(0, 2**62))
+    At = [torch.from_numpy(a).to(device) for a in A]
+    kr = At[-1]
+    for a in reversed(At[1:-1]):   # rows: (i_2, ..., i_N) row-major
+        kr = (a[:, None, :] * kr[None, :, :]).reshape(-1, R)
+    Y = At[0] @ kr.T               # I_1 x prod_{n>1} I_n, FP64
+    del kr
+    gen = torch.Generator(device=device)
+    gen.manual_seed(noise_seed)
+    for r0 in range(0, Y.shape[0], 16):   # |N(0, sigma)| added in row blocks
+        blk = Y[r0:r0 + 16]
+        blk.add_(torch.randn(blk.shape, dtype=torch.float64, device=device,
+                             generator=gen).abs_().mul_(noise_sigma))
+    Y32 = Y.to(torch.float32).reshape(tuple(dims))
+    del Y
+    return {"Y": Y32, "A_true": A, "omegas": om, "omega_tildes": omt,
+            "init_rng": g["init"]}
+
+
 def mlp_weights(case, dims):
     """He-initialized weights of the learned initializer: W_l ~ N(0, 2/fan_in)
     (d_l x d_{l+1}), zero biases; FP32 values (returned as float32 arrays)."""
