@@ -749,7 +749,7 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
 
 // LDS layout; returns the byte size or -1 when the small matrices alone do
 // not fit.  glds selects the core and MTTKRP buffers in LDS as well.
-int64_t layout(CoreAlsArgs& c, bool glds, int nt) {
+int64_t layout(CoreAlsArgs& c, bool glds) {
   const FfcpArgs& a = c.a;
   const int N = a.N, R = a.R;
   c.RP = (R + 3) / 4 * 4;
@@ -843,9 +843,9 @@ int launch_one(const CoreAlsArgs& c, int64_t lds, hipStream_t s) {
 
 template <int RMAX, int NT>
 int launch_r(CoreAlsArgs& c, hipStream_t s) {
-  int64_t lds = layout(c, true, NT);
+  int64_t lds = layout(c, true);
   if (lds + 64 <= kLdsMax) return launch_one<RMAX, NT, true>(c, lds, s);
-  lds = layout(c, false, NT);
+  lds = layout(c, false);
   if (lds + 64 <= kLdsMax) return launch_one<RMAX, NT, false>(c, lds, s);
   return kErrUnsupported;
 }

