@@ -19,21 +19,47 @@ namespace {
 constexpr int kThreads = 256;
 
 // out[a, i, c] = sum_j B[i, j] X[a, j, c]; one thread per output (J <= 64).
+// out[a, i, c] = sum_j B[i, j] X[a, j, c] (the expansion of a test matrix by
+// a factor).  Each thread produces kExpRows rows i of one column c, so every
+// X value it loads serves kExpRows products (X is read once per block of
+// rows, not once per row); the block's B rows sit in LDS.  The sum runs over
+// j in order, as a plain loop would.
+constexpr int kExpRows = 8;
+constexpr int kExpMaxJ = 64;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void expand_kernel(
     const T* __restrict__ X, const T* __restrict__ B, T* __restrict__ out,
     int64_t A, int64_t I, int J, int64_t C) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (idx >= A * I * C) return;
-  const int64_t c = idx % C;
-  const int64_t t = idx / C;
-  const int64_t i = t % I;
-  const int64_t a = t / I;
-  const T* xp = X + a * J * C + c;
-  const T* bp = B + i * J;
-  T acc = T(0);
-  for (int j = 0; j < J; ++j) acc += bp[j] * xp[j * C];
-  out[idx] = acc;
+  __shared__ T bs[kExpRows][kExpMaxJ];
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t nib = (I + kExpRows - 1) / kExpRows;
+  // row blocks and a strided over the grid (block-uniform trip counts, so
+  // every thread reaches the barriers)
+  for (int64_t ib = blockIdx.y; ib < nib; ib += gridDim.y) {
+    const int64_t i0 = ib * kExpRows;
+    __syncthreads();   // the previous block's rows are no longer read
+    for (int l = threadIdx.x; l < kExpRows * J; l += kThreads) {
+      const int u = l / J, j = l - u * J;
+      bs[u][j] = (i0 + u < I) ? B[(i0 + u) * J + j] : T(0);
+    }
+    __syncthreads();
+    if (c >= C) continue;
+    for (int64_t a = blockIdx.z; a < A; a += gridDim.z) {
+      const T* xp = X + a * J * C + c;
+      T acc[kExpRows];
+#pragma unroll
+      for (int u = 0; u < kExpRows; ++u) acc[u] = T(0);
+      for (int j = 0; j < J; ++j) {
+        const T x = xp[static_cast<int64_t>(j) * C];
+#pragma unroll
+        for (int u = 0; u < kExpRows; ++u) acc[u] += bs[u][j] * x;
+      }
+#pragma unroll
+      for (int u = 0; u < kExpRows; ++u)
+        if (i0 + u < I) out[(a * I + i0 + u) * C + c] = acc[u];
+    }
+  }
 }
 
 // Split-K product part[s][i][r] = sum over the s-th range of k = a*C + c of
@@ -334,9 +360,16 @@ __global__ __launch_bounds__(kThreads) void gram_waves_kernel(
 template <typename T>
 int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
                   int64_t C, hipStream_t s) {
-  const int64_t n = A * I * C;
-  if (n <= 0) return kOk;
-  hipLaunchKernelGGL(expand_kernel<T>, dim3(static_cast<unsigned>(ceil_div(n, kThreads))),
+  if (A <= 0 || I <= 0 || C <= 0) return kOk;
+  const int64_t gx = ceil_div(C, kThreads), nib = ceil_div(I, kExpRows);
+  if (J > kExpMaxJ || gx > 0x7fffffff) {
+    set_error("expand: J %d or C %lld out of range", J, (long long)C);
+    return kErrUnsupported;
+  }
+  hipLaunchKernelGGL(expand_kernel<T>,
+                     dim3(static_cast<unsigned>(gx),
+                          static_cast<unsigned>(nib < 65535 ? nib : 65535),
+                          static_cast<unsigned>(A < 65535 ? A : 65535)),
                      dim3(kThreads), 0, s, X, B, out, A, I, J, C);
   RT_LAUNCH_CHECK("expand");
   return kOk;
