@@ -138,6 +138,7 @@ struct TuckerPlan {
   T* W0;
   T* W1;
   T* zpart;
+  int64_t zpart_cap;
   double* gram[RT_MAX_MODES];
   double* W[RT_MAX_MODES];
   T* WT[RT_MAX_MODES];
@@ -196,7 +197,8 @@ struct TuckerPlan {
     // the last core contraction also runs through the split-K product with
     // prod_{p>1} R~_p rows
     const int64_t rows_max = imax > core / K[0] ? imax : core / K[0];
-    zpart = ar.take<T>((65536 + rows_max) * static_cast<int64_t>(kmax));
+    zpart_cap = sketch_part_elems(rows_max, kmax);
+    zpart = ar.take<T>(zpart_cap);
     stream_bytes = stream_workspace_bytes(d);
     stream_ws = ar.take<char>(stream_bytes);
     return ar.need;
@@ -270,7 +272,7 @@ int sketch_from_intermediate(Plan& P, int n, const T* const* B, const T* Omt,
   int64_t Apre = 1, Cpost = 1;
   for (int p = 0; p < n; ++p) Apre *= D[p];
   for (int p = n + 1; p < N; ++p) Cpost *= D[p];
-  return launch_sketch_gemm<T>(base, src, P.Z[n], P.zpart, Apre, P.I[n], Cpost,
+  return launch_sketch_gemm<T>(base, src, P.Z[n], P.zpart, P.zpart_cap, Apre, P.I[n], Cpost,
                                P.K[n], s);
 }
 
@@ -361,7 +363,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     // mode 1 last, as one split-K product over I_1 (rows = the other core
     // indices), then transposed into G~ = [R~_1, ...].
     const int64_t rest = P.core / P.K[0];
-    RT_TRY(launch_sketch_gemm<T>(src, B[0], bufs[cur], P.zpart, P.I[0], rest, 1,
+    RT_TRY(launch_sketch_gemm<T>(src, B[0], bufs[cur], P.zpart, P.zpart_cap, P.I[0], rest, 1,
                                  P.K[0], s));
     RT_TRY(launch_transpose<T>(bufs[cur], P.Gt, rest, P.K[0], s));
   }

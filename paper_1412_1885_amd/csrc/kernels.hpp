@@ -24,10 +24,15 @@ template <typename T>
 int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
                   int64_t C, hipStream_t s);
 // Z[i, r] = sum_{a, c} Tm[a, i, c] W[a*C + c, r]; part: split-K scratch of
-// (65536 + I) * R elements.
+// part_cap elements, at least sketch_part_elems(I, R). The split count aims
+// at kSketchTargetBlocks workgroups of 64 rows, so S * I <= 64 * target + I.
+constexpr int64_t kSketchTargetBlocks = 1024;
+inline int64_t sketch_part_elems(int64_t I, int64_t R) {
+  return (64 * kSketchTargetBlocks + I) * R;
+}
 template <typename T>
-int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
-                       int64_t I, int64_t C, int R, hipStream_t s);
+int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t part_cap,
+                       int64_t A, int64_t I, int64_t C, int R, hipStream_t s);
 // out[c][r] = in[r][c] (R x C matrix).
 template <typename T>
 int launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t s);

@@ -42,14 +42,23 @@ ProfScope::ProfScope(int stage, hipStream_t s) : stage_(stage), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
   a_ = take_event();
   b_ = take_event();
-  if (a_ && b_) hipEventRecord(a_, s_);
+  if (a_ && b_ && hipEventRecord(a_, s_) == hipSuccess) return;
+  // no timing for this scope: hand the events back
+  if (a_) g_pool.push_back(a_);
+  if (b_) g_pool.push_back(b_);
+  a_ = b_ = nullptr;
 }
 
 ProfScope::~ProfScope() {
   if (!a_ || !b_) return;
-  hipEventRecord(b_, s_);
+  const bool ok = hipEventRecord(b_, s_) == hipSuccess;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_live.push_back({a_, b_, stage_});
+  if (ok) {
+    g_live.push_back({a_, b_, stage_});
+  } else {
+    g_pool.push_back(a_);
+    g_pool.push_back(b_);
+  }
 }
 
 }  // namespace rt

@@ -377,21 +377,32 @@ int launch_expand(const T* X, const T* B, T* out, int64_t A, int64_t I, int J,
 
 int64_t sketch_gemm_splits(int64_t I, int64_t K) {
   const int64_t iblocks = ceil_div(I, 64);
-  int64_t S = ceil_div(1024, iblocks);
+  int64_t S = ceil_div(kSketchTargetBlocks, iblocks);
   const int64_t maxS = ceil_div(K, 32);
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   return S;
 }
 
+// The split-K partials take Sused * I * R elements of part.
+static int check_part(int64_t Sused, int64_t I, int R, int64_t part_cap) {
+  if (Sused * I * R > part_cap) {
+    set_error("sketch partials need %lld elements, scratch holds %lld",
+              static_cast<long long>(Sused * I * R), static_cast<long long>(part_cap));
+    return kErrWorkspace;
+  }
+  return kOk;
+}
+
 template <typename T>
-int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
-                       int64_t I, int64_t C, int R, hipStream_t s) {
+int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t part_cap,
+                       int64_t A, int64_t I, int64_t C, int R, hipStream_t s) {
   const int64_t K = A * C;
   const int64_t S = sketch_gemm_splits(I, K);
   int64_t kper = ceil_div(K, S);
   kper = ceil_div(kper, 32) * 32;
   const int64_t Sused = ceil_div(K, kper);
+  RT_TRY(check_part(Sused, I, R, part_cap));
   dim3 grid(static_cast<unsigned>(ceil_div(I, 64)), static_cast<unsigned>(Sused));
   if (R <= 32) {
     hipLaunchKernelGGL((sketch_gemm_kernel<T, 32>), grid, dim3(kThreads), 0, s, Tm,
@@ -414,12 +425,14 @@ int launch_sketch_gemm(const T* Tm, const T* W, T* Z, T* part, int64_t A,
 // FP32, R <= 32: the matrix-core form (same split-K partials and sum).
 template <>
 int launch_sketch_gemm<float>(const float* Tm, const float* W, float* Z, float* part,
-                              int64_t A, int64_t I, int64_t C, int R, hipStream_t s) {
+                              int64_t part_cap, int64_t A, int64_t I, int64_t C, int R,
+                              hipStream_t s) {
   if (R > 32) {
     const int64_t K = A * C;
     const int64_t S = sketch_gemm_splits(I, K);
     int64_t kper = ceil_div(ceil_div(K, S), 32) * 32;
     const int64_t Sused = ceil_div(K, kper);
+    RT_TRY(check_part(Sused, I, R, part_cap));
     dim3 grid(static_cast<unsigned>(ceil_div(I, 64)), static_cast<unsigned>(Sused));
     if (R > 64) {
       set_error("sketch width %d exceeds 64", R);
@@ -439,6 +452,7 @@ int launch_sketch_gemm<float>(const float* Tm, const float* W, float* Z, float* 
   const int64_t S = sketch_gemm_splits(I, K);   // the partial buffer holds S splits
   int64_t kper = ceil_div(ceil_div(K, S), 32) * 32;
   const int64_t Sused = ceil_div(K, kper);
+  RT_TRY(check_part(Sused, I, R, part_cap));
   dim3 grid(static_cast<unsigned>(ceil_div(I, 128)), static_cast<unsigned>(Sused));
   hipLaunchKernelGGL(sketch_mfma_kernel, grid, dim3(kThreads), 0, s, Tm, W, part, A, I, C,
                      R, kper);
@@ -502,6 +516,7 @@ RT_INST(float)
 RT_INST(double)
 #undef RT_INST
 template int launch_sketch_gemm<double>(const double*, const double*, double*, double*,
-                                        int64_t, int64_t, int64_t, int, hipStream_t);
+                                        int64_t, int64_t, int64_t, int64_t, int,
+                                        hipStream_t);
 
 }  // namespace rt
