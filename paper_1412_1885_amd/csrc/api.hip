@@ -543,20 +543,6 @@ __global__ void hosvd_pad_kernel(const double* W, const float* pad, double* V,
   V[l] = (r < k) ? W[j * k + r] : static_cast<double>(pad[j * (R - k) + (r - k)]);
 }
 
-template <typename T>
-__global__ void gram_of_core_kernel(const T* G, double* S, int64_t Apre, int Rn,
-                                    int64_t Cpost) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= Rn * Rn) return;
-  const int i = l / Rn, j = l % Rn;
-  double acc = 0.0;
-  for (int64_t a = 0; a < Apre; ++a)
-    for (int64_t c = 0; c < Cpost; ++c)
-      acc += static_cast<double>(G[(a * Rn + i) * Cpost + c]) *
-             static_cast<double>(G[(a * Rn + j) * Cpost + c]);
-  S[l] = acc;
-}
-
 }  // namespace
 }  // namespace rt
 
@@ -733,26 +719,29 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
     double* const* dstV = desc->init == RT_INIT_COEFF_GUARDED ? P.Valt : P.Vinit;
     int64_t core = 1;
     for (int n = 0; n < N; ++n) core *= desc->ranks[n];
+    // The Grams are formed one wavefront per entry, and the N eigenproblems
+    // run as one batch. Each writes its R_n x k eigenvectors over its own
+    // Gram: the eigensolver reads its whole input before writing.
     int64_t Apre = 1;
+    EigBatch eb{};
+    eb.nb = N;
     for (int n = 0; n < N; ++n) {
       const int Rn = desc->ranks[n];
-      const int k = R < Rn ? R : Rn;
       const int64_t Cpost = core / (Apre * Rn);
-      hipLaunchKernelGGL(gram_of_core_kernel<float>,
-                         dim3((Rn * Rn + 255) / 256), dim3(256), 0, s, G,
-                         P.hgram[n], Apre, Rn, Cpost);
-      RT_LAUNCH_CHECK("hosvd gram");
+      RT_TRY(launch_gram_waves<float>(G, P.hgram[n], Apre, Rn, Cpost, s));
       Apre *= Rn;
-      EigBatch one{};
-      one.nb = 1;
-      one.S[0] = P.hgram[n];
-      one.n[0] = Rn;
-      one.k[0] = k;
-      one.W[0] = P.H;  // Rn x k scratch
-      one.evals[0] = nullptr;
-      RT_TRY(launch_eig(one, s));
+      eb.S[n] = P.hgram[n];
+      eb.W[n] = P.hgram[n];
+      eb.evals[n] = nullptr;
+      eb.n[n] = Rn;
+      eb.k[n] = R < Rn ? R : Rn;
+    }
+    RT_TRY(launch_eig(eb, s));
+    for (int n = 0; n < N; ++n) {
+      const int Rn = desc->ranks[n];
+      const int k = eb.k[n];
       hipLaunchKernelGGL(hosvd_pad_kernel, dim3((Rn * R + 255) / 256), dim3(256),
-                         0, s, P.H, (k < R) ? pad[n] : nullptr, dstV[n], Rn,
+                         0, s, P.hgram[n], (k < R) ? pad[n] : nullptr, dstV[n], Rn,
                          k, R);
       RT_LAUNCH_CHECK("hosvd pad");
     }

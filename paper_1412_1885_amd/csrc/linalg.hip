@@ -374,11 +374,15 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // ---------------------------------------------------------------- Jacobi
-// One workgroup of four wavefronts per matrix.  A round (n/2 rotations, then
-// the 2 x 2 block updates of S and the column-pair updates of V) is a short
-// dependent chain; every lane owns at most kBlk blocks and kVp V entries,
-// whose indices are computed once, and issues all of its loads of a round
-// before its stores.  The round-robin pair schedule is arithmetic.
+// One workgroup of four wavefronts per matrix.  The pairs of a round
+// partition the indices, so S and V split into disjoint 2 x 2 blocks
+// (pair a) x (pair b); a thread owns such blocks (at most kBlk, indices
+// computed once).  S is double-buffered: a round reads every value it needs
+// from the previous copy, each thread derives the rotations of its own two
+// pairs from that copy (the same arithmetic on the same values gives every
+// thread the same rotation), writes its block of S J^T..J into the other
+// copy and rotates its block of V in place.  One barrier per round.  The
+// round-robin pair schedule is arithmetic.
 constexpr int kEigThreads = 256;
 constexpr int kEigMax = 64;
 
@@ -398,12 +402,27 @@ __device__ __forceinline__ void jacobi_pair(int p, int r, int np, int& lo, int& 
   hi = a < q ? q : a;
 }
 
+// Rotation (c, s) of the pair (lo, hi) from a_pp = Spp, a_qq = Sqq,
+// a_pq = Spq: the smaller angle that annihilates a_pq,
+// tan = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = a_qq - a_pp, e = 2 a_pq.
+// A pair is rotated only while |a_pq| > thresh; returns whether it is.
+__device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq,
+                                                bool real, double thresh, double& c,
+                                                double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (!real || !(fabs(apq) > thresh)) return false;
+  const double d = aqq - app, e = 2.0 * apq;
+  const double tt = (d >= 0.0 ? e : -e) / (fabs(d) + sqrt(d * d + e * e));
+  c = rsqrt_nr(1.0 + tt * tt);
+  s = tt * c;
+  return true;
+}
+
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
-  __shared__ double S[kEigMax][kEigMax + 1];
+  __shared__ double S2[2][kEigMax][kEigMax + 1];
   __shared__ double V[kEigMax][kEigMax + 1];
-  __shared__ double cs[kEigMax / 2][2];
   __shared__ double red[kEigThreads / 64];
-  __shared__ int flag[2];
   __shared__ int rankpos[kEigMax];
   const int m = blockIdx.x;
   const int n = b.n[m];
@@ -412,7 +431,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   const double* Sin = b.S[m];
   for (int l = t; l < n * n; l += kEigThreads) {
     int i = l / n, j = l % n;
-    S[i][j] = 0.5 * (Sin[i * n + j] + Sin[j * n + i]);
+    S2[0][i][j] = 0.5 * (Sin[i * n + j] + Sin[j * n + i]);
     V[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -420,116 +439,74 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   const int hp = np / 2;
   double fro = 0.0;
   for (int l = t; l < n * n; l += kEigThreads) {
-    const double x = S[l / n][l % n];
+    const double x = S2[0][l / n][l % n];
     fro += x * x;
   }
-  // A pair is rotated only while |a_pq| > 1e-14 ||S||_F (threshold Jacobi):
-  // a per-element test stays above the rounding floor of the 2 x 2 updates
-  // (a few ulps of ||S||), where a test on the whole off-diagonal norm can
-  // sit at that floor and never pass.  The sweeps end after one in which no
-  // pair was rotated.
+  // Threshold Jacobi: |a_pq| > 1e-14 ||S||_F.  A per-element test stays
+  // above the rounding floor of the 2 x 2 updates (a few ulps of ||S||),
+  // where a test on the whole off-diagonal norm can sit at that floor and
+  // never pass.  The sweeps end after one in which no pair was rotated.
   const double thresh = 1e-14 * sqrt(block_sum(fro, red)) + 1e-300;
-  // the lane's blocks (pair indices pa, pb) and V entries (row i, pair pb)
-  // do not depend on the round: index arithmetic once, not per round
   constexpr int kBlk = kEigMax * kEigMax / 4 / kEigThreads;   // 4
-  constexpr int kVp = kEigMax * kEigMax / 2 / kEigThreads;    // 8
-  int bpa[kBlk], bpb[kBlk], vi[kVp], vpb[kVp];
+  int bpa[kBlk], bpb[kBlk];
 #pragma unroll
   for (int u = 0; u < kBlk; ++u) {
     const int blk = u * kEigThreads + t;
     bpa[u] = blk < hp * hp ? blk / hp : -1;
     bpb[u] = blk < hp * hp ? blk - (blk / hp) * hp : 0;
   }
-#pragma unroll
-  for (int u = 0; u < kVp; ++u) {
-    const int l = u * kEigThreads + t;
-    vi[u] = l < n * hp ? l / hp : -1;
-    vpb[u] = l < n * hp ? l - (l / hp) * hp : 0;
-  }
   const int nblk = (hp * hp + kEigThreads - 1) / kEigThreads;   // slots in use
-  const int nvp = (n * hp + kEigThreads - 1) / kEigThreads;
-  int rc = 0;   // rounds so far (flag buffer parity)
+  int cur = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    bool swept = false;   // any rotation in this sweep (block-uniform)
-    for (int r = 0; r < np - 1; ++r, ++rc) {
-      if (t < 64) {   // hp <= 32: the rotations are wave 0's
-        bool rot = false;
-        if (t < hp) {
-          int lo, hi;
-          jacobi_pair(t, r, np, lo, hi);
-          double c = 1.0, s = 0.0;
-          if (hi < n) {
-            const double apq = S[lo][hi];
-            if (fabs(apq) > thresh) {
-              rot = true;
-              // tan of the smaller angle that annihilates apq:
-              // tt = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = a_qq - a_pp, e = 2 a_pq
-              const double d = S[hi][hi] - S[lo][lo], e = 2.0 * apq;
-              const double tt = (d >= 0.0 ? e : -e) / (fabs(d) + sqrt(d * d + e * e));
-              c = rsqrt_nr(1.0 + tt * tt);
-              s = tt * c;
-            }
-          }
-          cs[t][0] = c;
-          cs[t][1] = s;
-        }
-        const bool any = __ballot(rot) != 0;
-        if (t == 0) flag[rc & 1] = any ? 1 : 0;
-      }
-      __syncthreads();
-      if (flag[rc & 1] == 0) continue;   // nothing to apply this round
-      swept = true;
-      // S <- J^T S J in place: the pairs partition the indices, so the 2 x 2
-      // blocks {lo_a, hi_a} x {lo_b, hi_b} are disjoint (an index >= n is
-      // the dummy player: its row and column do not exist)
+    int rotated = 0;   // this thread saw a rotation in this sweep
+    for (int r = 0; r < np - 1; ++r) {
+      const double(*Sc)[kEigMax + 1] = S2[cur];
+      double(*Sn)[kEigMax + 1] = S2[cur ^ 1];
 #pragma unroll
       for (int u = 0; u < kBlk; ++u) {
         if (u >= nblk) break;
         if (bpa[u] < 0) continue;
-        const int pa = bpa[u], pb = bpb[u];
         int i0, i1, j0, j1;
-        jacobi_pair(pa, r, np, i0, i1);
-        jacobi_pair(pb, r, np, j0, j1);
+        jacobi_pair(bpa[u], r, np, i0, i1);
+        jacobi_pair(bpb[u], r, np, j0, j1);
         const bool r1 = i1 < n, c1 = j1 < n;
         const int i1c = r1 ? i1 : i0, j1c = c1 ? j1 : j0;
-        const double ca = cs[pa][0], sa = cs[pa][1], cb = cs[pb][0], sb = cs[pb][1];
-        const double b00 = S[i0][j0];
-        const double b01 = c1 ? S[i0][j1c] : 0.0;
-        const double b10 = r1 ? S[i1c][j0] : 0.0;
-        const double b11 = (r1 && c1) ? S[i1c][j1c] : 0.0;
-        const double x00 = ca * b00 - sa * b10, x01 = ca * b01 - sa * b11;
-        const double x10 = sa * b00 + ca * b10, x11 = sa * b01 + ca * b11;
-        S[i0][j0] = cb * x00 - sb * x01;
-        if (c1) S[i0][j1] = sb * x00 + cb * x01;
-        if (r1) S[i1][j0] = cb * x10 - sb * x11;
-        if (r1 && c1) S[i1][j1] = sb * x10 + cb * x11;
+        // every load of the block first: its four entries, the three
+        // entries of each pair's 2 x 2 diagonal block, its V entries
+        const double b00 = Sc[i0][j0], b01 = Sc[i0][j1c];
+        const double b10 = Sc[i1c][j0], b11 = Sc[i1c][j1c];
+        const double ap0 = Sc[i0][i0], ap1 = Sc[i1c][i1c], apx = Sc[i0][i1c];
+        const double bp0 = Sc[j0][j0], bp1 = Sc[j1c][j1c], bpx = Sc[j0][j1c];
+        const double v00 = V[i0][j0], v01 = V[i0][j1c];
+        const double v10 = V[i1c][j0], v11 = V[i1c][j1c];
+        double ca, sa, cb, sb;
+        rotated |= jacobi_rotation(ap0, ap1, apx, r1, thresh, ca, sa);
+        rotated |= jacobi_rotation(bp0, bp1, bpx, c1, thresh, cb, sb);
+        // a dummy row or column holds zeros
+        const double e01 = c1 ? b01 : 0.0, e10 = r1 ? b10 : 0.0;
+        const double e11 = (r1 && c1) ? b11 : 0.0;
+        const double x00 = ca * b00 - sa * e10, x01 = ca * e01 - sa * e11;
+        const double x10 = sa * b00 + ca * e10, x11 = sa * e01 + ca * e11;
+        Sn[i0][j0] = cb * x00 - sb * x01;
+        if (c1) Sn[i0][j1] = sb * x00 + cb * x01;
+        if (r1) Sn[i1][j0] = cb * x10 - sb * x11;
+        if (r1 && c1) Sn[i1][j1] = sb * x10 + cb * x11;
+        // V <- V J on rows {i0, i1}, columns {j0, j1}
+        if (c1) {
+          V[i0][j0] = cb * v00 - sb * v01;
+          V[i0][j1] = sb * v00 + cb * v01;
+          if (r1) {
+            V[i1][j0] = cb * v10 - sb * v11;
+            V[i1][j1] = sb * v10 + cb * v11;
+          }
+        }
       }
-      // V <- V J: the lane's (row, column pair) entries; loads first
-      double vv[kVp][2];
-#pragma unroll
-      for (int u = 0; u < kVp; ++u) {
-        if (u >= nvp) break;
-        int j0, j1;
-        jacobi_pair(vpb[u], r, np, j0, j1);
-        const int i = vi[u] < 0 ? 0 : vi[u];
-        vv[u][0] = V[i][j0];
-        vv[u][1] = V[i][j1 < n ? j1 : j0];
-      }
-#pragma unroll
-      for (int u = 0; u < kVp; ++u) {
-        if (u >= nvp) break;
-        if (vi[u] < 0) continue;
-        int j0, j1;
-        jacobi_pair(vpb[u], r, np, j0, j1);
-        if (j1 >= n) continue;
-        const double cb = cs[vpb[u]][0], sb = cs[vpb[u]][1];
-        V[vi[u]][j0] = cb * vv[u][0] - sb * vv[u][1];
-        V[vi[u]][j1] = sb * vv[u][0] + cb * vv[u][1];
-      }
+      cur ^= 1;
       __syncthreads();
     }
-    if (!swept) break;
+    if (!__syncthreads_or(rotated)) break;
   }
+  const double(*S)[kEigMax + 1] = S2[cur];
   // descending order, ties by ascending index
   if (t < n) {
     double lt = S[t][t];
