@@ -188,6 +188,25 @@ def init_factors(rng, dims, R, nonneg=False):
     return [rng.standard_normal((I, R)) for I in dims]
 
 
+def nonneg_tucker_format(case, dims, R, dist="exp", scale=10.0, zero_frac=0.2):
+    """An exact Tucker format of a noise-free nonnegative CP model, for FFCP
+    on tensors too large to form (Section V-A's 10^4 x 10^4 x 10^4 x 10^4
+    example): true factors A_n (``nonneg_factors``), U_n R_n = A_n their
+    reduced QR, core G = sum_r R_1[:, r] o ... o R_N[:, r] (R^N entries), and
+    U[0,1] initial factors from the case's init stream."""
+    g = rngs(case)
+    A = nonneg_factors(g["factors"], dims, R, dist, scale, zero_frac)
+    U, Rs = [], []
+    for a in A:
+        q, r = np.linalg.qr(a)
+        U.append(q)
+        Rs.append(r)
+    letters = "abcdefghijklmnopq"[:len(dims)]
+    G = np.einsum(",".join(c + "z" for c in letters) + "->" + letters, *Rs)
+    A0 = init_factors(g["init"], dims, R, nonneg=True)
+    return {"A": A, "U": U, "G": G, "A0": A0}
+
+
 # ------------------------------------------------ device-resident workloads
 
 def cp_congruent_device(case, dims, R, c_lo, c_hi, snr_db, ranks_tilde,

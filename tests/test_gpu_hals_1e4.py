@@ -1,0 +1,93 @@
+"""FFCP-HALS on the noise-free nonnegative example of Section V-A at its own
+size: four modes of 10^4, exponential (mean 10) factors with exactly 20 %
+zeros, R = 10, handed over as an exact Tucker format U_n = orth(A_n)
+(10^4 x 10, the Q of a reduced QR) and G = sum_r R_1[:, r] o ... o R_4[:, r]
+(10^4 entries), so the 10^16-entry tensor is never formed.  The device gets
+U_n and G in FP32; the oracle runs in FP64 on the same FP32 values.
+
+* Iterates: twelve HALS iterations from the same U[0,1] start; fits equal
+  to 1e-9 (both FP64), factors and weights to 1e-6 (the device returns
+  FP32).
+* Convergence (|dFit| < 1e-12): iteration counts within 2 of the oracle's
+  and the final fits equal to 1e-9.
+* Recovery, pinned to the generating model rather than to the oracle: every
+  component's SIR (footnote of Section V-A) at least 130 dB.  The paper's
+  FP64 run reaches > 200 dB; here the FP32 rounding of U_n and G (relative
+  6e-8) caps it near 150 dB (the FP64 oracle on these inputs: 149 dB), and
+  the FP32 output adds its own rounding.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ffcp as F
+from oracle.metrics import sir_factors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DIMS, R = (10000,) * 4, 10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1412_1885_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def work():
+    d = synth.nonneg_tucker_format(27, DIMS, R, "exp", 10.0, 0.2)
+    U = [synth.f32(u).astype(np.float64) for u in d["U"]]
+    G = synth.f32(d["G"]).astype(np.float64)
+    A0 = [synth.f32(a).astype(np.float64) for a in d["A0"]]
+    return {"A": d["A"], "U": U, "G": G, "A0": A0}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.float32).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run(P, w, max_it, tol):
+    return P.ffcp([dev(u) for u in w["U"]], dev(w["G"]), R, update="hals",
+                  A_init=[dev(a) for a in w["A0"]], max_it=max_it, tol=tol,
+                  fit_trace=True)
+
+
+def test_hals_1e4_iterates(P, work):
+    w = work
+    iters = 12
+    out = run(P, w, iters, 0.0)
+    ref = F.ffcp(w["U"], w["G"], w["A0"], update="hals", max_it=iters, tol=0.0)
+    assert int(out["info"]["iterations"]) == iters
+    np.testing.assert_allclose(out["fits"], ref["fits"], rtol=0, atol=1e-9)
+    for n in range(4):
+        assert rel(host(out["A"][n]), ref["A"][n]) <= 1e-6, n
+    assert rel(host(out["lam"]), ref["lam"]) <= 1e-6
+
+
+def test_hals_1e4_convergence_and_recovery(P, work):
+    w = work
+    out = run(P, w, 1000, 1e-12)
+    ref = F.ffcp(w["U"], w["G"], w["A0"], update="hals", max_it=1000, tol=1e-12)
+    it = int(out["info"]["iterations"])
+    assert out["info"]["converged"] == 1 and ref["converged"]
+    assert abs(it - ref["iterations"]) <= 2
+    assert abs(out["info"]["fit"] - ref["fits"][-1]) <= 1e-9
+    for n in range(4):
+        A = host(out["A"][n])
+        assert A.min() >= 0.0, n
+        sirs = sir_factors(w["A"][n], A)
+        assert sirs.min() >= 130.0, (n, sirs.min())

@@ -290,6 +290,21 @@ def test_hosvd_init_eigenvectors():
 
 # ------------------------------------------- the paper's noise-free example
 
+def test_nonneg_tucker_format_is_the_cp_model():
+    """The seeded Tucker format of the 10^4-per-mode HALS workload (here at
+    small sizes): [[G; U]] equals the dense nonnegative CP tensor, U_n is
+    orthonormal, each factor has exactly 20 % zeros."""
+    dims, R = (12, 13, 14, 15), 3
+    d = synth.nonneg_tucker_format(28, dims, R, "exp", 10.0, 0.2)
+    Y = np.einsum("ir,jr,kr,lr->ijkl", *d["A"])
+    Yt = T.multi_ttm_t(d["G"], [u.T for u in d["U"]])
+    assert np.linalg.norm(Yt - Y) <= 1e-13 * np.linalg.norm(Y)
+    for I, u, a in zip(dims, d["U"], d["A"]):
+        assert np.linalg.norm(u.T @ u - np.eye(R)) <= 1e-13
+        assert int(np.sum(a == 0.0)) == round(0.2 * I * R)
+        assert a.min() >= 0.0
+
+
 @pytest.mark.slow
 def test_paper_noise_free_nonneg_recovery_sir():
     """Section V-A (the 10^4 x 10^4 x 10^4 x 10^4 example, scaled to
