@@ -182,9 +182,11 @@ def run_hals_1e4(P, torch, synth, reps):
     """FFCP-HALS on Section V-A's noise-free nonnegative example at its own
     size: four modes of 10^4, R = 10, exponential (mean 10) factors with
     20 % zeros, handed over as its exact Tucker format (U_n 10^4 x 10, G
-    10^4 entries; the tensor itself is never formed).  Times whole fits
-    (|dFit| < 1e-12 from a U[0,1] start) and reports the recovered
-    components' SIR against the generating factors."""
+    10^4 entries; the tensor itself is never formed).  Times fits of a
+    fixed 30 iterations from a U[0,1] start (the fit reaches the rounding
+    floor of its closed form by about 17, after which a tolerance test is
+    decided by rounding) and reports the recovered components' SIR against
+    the generating factors."""
     from scipy.optimize import linear_sum_assignment
     dims, R = (10000,) * 4, 10
     d = synth.nonneg_tucker_format(27, dims, R, "exp", 10.0, 0.2)
@@ -194,7 +196,7 @@ def run_hals_1e4(P, torch, synth, reps):
     stream = torch.cuda.current_stream()
 
     def fit(ws):
-        return P.ffcp(U, G, R, update="hals", A_init=A0, max_it=1000, tol=1e-12,
+        return P.ffcp(U, G, R, update="hals", A_init=A0, max_it=30, tol=0.0,
                       workspace=ws, sync=False)
 
     f = fit(None)                      # sizes the workspace
@@ -225,7 +227,7 @@ def run_hals_1e4(P, torch, synth, reps):
             sirs.append(20.0 * np.log10(np.linalg.norm(za[:, r]) / err))
     return {"workload": "nonneg CP rank 10, 10^4 x 10^4 x 10^4 x 10^4 as its exact "
                         "Tucker format (FP32 U_n, G)",
-            "update": "hals", "tol": 1e-12, "fits_timed": reps,
+            "update": "hals", "fits_timed": reps,
             "ms": round(ms, 4), "iterations": it,
             "us_per_iteration": round(ms * 1e3 / max(it, 1), 2),
             "converged": int(info["converged"]), "fit": float(info["fit"]),

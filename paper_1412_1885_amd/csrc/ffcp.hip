@@ -36,19 +36,77 @@ struct InfoDev {
 
 __device__ __forceinline__ void bsync() { __syncthreads(); }
 
-// out[o] = sum_i X[i*ldx + ox(o)] * Y[i*ldy + oy(o)], o < nout, i < rows;
-// one wave per output (lanes stride the rows), deterministic order.
-template <typename FX, typename FY>
-__device__ void wave_dots(const double* X, int64_t ldx, const double* Y,
-                          int64_t ldy, int64_t rows, int nout, FX ox, FY oy,
-                          double* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int o = wave; o < nout; o += kFWaves) {
-    const int cx = ox(o), cy = oy(o);
-    double acc = 0.0;
-    for (int64_t i = lane; i < rows; i += 64) acc += X[i * ldx + cx] * Y[i * ldy + cy];
-    acc = wave_sum(acc);
-    if (lane == 0) out[o] = acc;
+// Cross products of row-major FP64 matrices with packed rows:
+//   out[a * q + b] = sum_i X[i * p + a] Y[i * q + b]   (a < p, b < q),
+// or only the diagonal out[a] (diag; X = Y, p = q), over `rows` rows.
+// One workgroup does it, so the cost is the number of dependent memory
+// round trips: the rows go through LDS in blocks as large as the staging
+// buffer holds (st: kXtyStage doubles; B rows of X and Y, one copy when
+// X = Y), which the threads load with consecutive addresses (B p and B q
+// contiguous doubles), about 16 loads in flight per thread.  When there are
+// fewer outputs than threads, the threads form G = threads / outputs groups
+// that take every G-th row of a block; the G partial sums of an output are
+// added in group order at the end.  Every output is a sum in a fixed order:
+// deterministic.
+constexpr int kXtyStage = 2 * 64 * kRMax;            // doubles (64 KB)
+constexpr int kXtyOut = kRMax * kRMax / kFThreads;   // outputs per thread
+
+__device__ void block_xty(const double* X, const double* Y, int64_t rows, int p,
+                          int q, bool diag, double* out, double* st) {
+  const int t = threadIdx.x;
+  const bool same = X == Y;
+  const int w = same ? p : p + q;              // staged doubles per row
+  const int B = kXtyStage / w;                 // rows per block (>= 64)
+  const int nout = diag ? p : p * q;
+  const int G = nout < kFThreads ? kFThreads / nout : 1;
+  const int g = t / (nout < kFThreads ? nout : kFThreads);   // this thread's group
+  double acc[kXtyOut];
+#pragma unroll
+  for (int u = 0; u < kXtyOut; ++u) acc[u] = 0.0;
+  for (int64_t i0 = 0; i0 < rows; i0 += B) {
+    const int nb = static_cast<int>(rows - i0 < B ? rows - i0 : B);
+    const int nx = nb * p, ny = same ? 0 : nb * q;
+    double* sY = same ? st : st + nx;
+    const int64_t xb = i0 * p, yb = i0 * q;
+    for (int e = t; e < nx + ny; e += kFThreads) {
+      st[e] = e < nx ? X[xb + e] : Y[yb + (e - nx)];
+    }
+    bsync();
+    if (g < G) {
+#pragma unroll
+      for (int u = 0; u < kXtyOut; ++u) {
+        const int o = (G > 1 ? t - g * nout : t) + u * kFThreads;
+        if (o < nout && (G > 1 ? u == 0 : true)) {
+          const int ia = diag ? o : o / q, ib = diag ? o : o % q;
+          double s0 = 0.0, s1 = 0.0;
+          int i = g;
+          for (; i + G < nb; i += 2 * G) {
+            s0 += st[i * p + ia] * sY[i * q + ib];
+            s1 += st[(i + G) * p + ia] * sY[(i + G) * q + ib];
+          }
+          if (i < nb) s0 += st[i * p + ia] * sY[i * q + ib];
+          acc[u] += s0 + s1;
+        }
+      }
+    }
+    bsync();
+  }
+  if (G > 1) {
+    // partial sums of the groups, added in group order
+    if (g < G) st[g * nout + (t - g * nout)] = acc[0];
+    bsync();
+    for (int o = t; o < nout; o += kFThreads) {
+      double v = 0.0;
+      for (int k = 0; k < G; ++k) v += st[k * nout + o];
+      out[o] = v;
+    }
+    bsync();
+  } else {
+#pragma unroll
+    for (int u = 0; u < kXtyOut; ++u) {
+      const int o = t + u * kFThreads;
+      if (o < nout) out[o] = acc[u];
+    }
   }
 }
 
@@ -71,6 +129,7 @@ __device__ void core_ttm_sq(const double* X, double* out, const double* M,
 template <int RMAX>
 __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
   __shared__ double Ts[kRMax * kRMax];   // T, then its Cholesky factor
+  __shared__ double st[kXtyStage];   // block_xty staging
   __shared__ double red[kFWaves];
   __shared__ double sh[8];
   __shared__ int shi[4];
@@ -107,10 +166,8 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
     const int Rn = a.Rn[n];
     const double* Un = a.U64[n];
     const double* An = a.A[n];
-    wave_dots(Un, Rn, An, R, a.I[n], Rn * R, [&](int o) { return o / R; },
-              [&](int o) { return o % R; }, a.V[n]);
-    wave_dots(An, R, An, R, a.I[n], R * R, [&](int o) { return o / R; },
-              [&](int o) { return o % R; }, a.Gram[n]);
+    block_xty(Un, An, a.I[n], Rn, R, false, a.V[n], st);
+    block_xty(An, An, a.I[n], R, R, false, a.Gram[n], st);
   }
   bsync();
 
@@ -126,9 +183,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
       const int Rn = a.Rn[n];
       int64_t Cpost = coreSize / (Apre * Rn);
       // UtU in Ts (Rn <= 64)
-      wave_dots(a.U64[n], Rn, a.U64[n], Rn, a.I[n], Rn * Rn,
-                [&](int o) { return o / Rn; }, [&](int o) { return o % Rn; },
-                a.H);
+      block_xty(a.U64[n], a.U64[n], a.I[n], Rn, Rn, false, a.H, st);
       bsync();
       core_ttm_sq(src, bufs[cur], a.H, Apre, Rn, Cpost);
       bsync();
@@ -190,14 +245,33 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
         first = false;
       }
       const double* H = src;  // Rn x R
-      // Q = U_n H
+      // Q = U_n H: H staged in LDS, one thread per row of Q; the row of U_n
+      // is loaded 16 values at a time, so a row costs ceil(R_n / 16) memory
+      // round trips
       double* Qm = a.Qm;
-      for (int64_t l = t; l < In * R; l += kFThreads) {
-        const int64_t i = l / R;
-        const int r = static_cast<int>(l % R);
-        double acc = 0.0;
-        for (int j = 0; j < Rn; ++j) acc += a.U64[n][i * Rn + j] * H[j * R + r];
-        Qm[l] = acc;
+      for (int l = t; l < Rn * R; l += kFThreads) st[l] = H[l];
+      bsync();
+      for (int64_t i = t; i < In; i += kFThreads) {
+        double acc[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) acc[r] = 0.0;
+        const double* urow = a.U64[n] + i * Rn;
+        for (int j0 = 0; j0 < Rn; j0 += 16) {
+          double uv[16];
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) uv[jj] = j0 + jj < Rn ? urow[j0 + jj] : 0.0;
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) {
+            if (j0 + jj < Rn) {
+#pragma unroll
+              for (int r = 0; r < RMAX; ++r)
+                if (r < R) acc[r] += uv[jj] * st[(j0 + jj) * R + r];
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+          if (r < R) Qm[i * R + r] = acc[r];
       }
       // T = hadamard of the other Grams
       for (int l = t; l < R * R; l += kFThreads) {
@@ -288,9 +362,12 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
       } else if (a.update == 1) {
         // ---- HALS: columns in order, in place per row --------------------
         for (int64_t i = t; i < In; i += kFThreads) {
-          double row[RMAX];
+          double row[RMAX], qrow[RMAX];   // both rows loaded before any use
 #pragma unroll
-          for (int r = 0; r < RMAX; ++r) row[r] = (r < R) ? An[i * R + r] : 0.0;
+          for (int r = 0; r < RMAX; ++r) {
+            row[r] = (r < R) ? An[i * R + r] : 0.0;
+            qrow[r] = (r < R) ? Qm[i * R + r] : 0.0;
+          }
 #pragma unroll
           for (int r = 0; r < RMAX; ++r) {
             if (r < R) {
@@ -298,7 +375,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
 #pragma unroll
               for (int q = 0; q < RMAX; ++q)
                 if (q < R) s += row[q] * Ts[q * R + r];
-              double v = row[r] + (Qm[i * R + r] - s) / Ts[r * R + r];
+              double v = row[r] + (qrow[r] - s) / Ts[r * R + r];
               row[r] = v > 1e-16 ? v : 1e-16;
             }
           }
@@ -335,19 +412,30 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
         bsync();
       }
       if (n < N - 1) {
-        wave_dots(An, R, An, R, In, R, [&](int o) { return o; },
-                  [&](int o) { return o; }, a.scal + 8);
+        block_xty(An, An, In, R, R, true, a.scal + 8, st);
         bsync();
-        for (int64_t l = t; l < In * R; l += kFThreads) {
-          const double nr = sqrt(a.scal[8 + l % R]);
-          if (nr > 0.0) An[l] /= nr;
+        // column norms in LDS; 8 elements per thread and step, loads first
+        for (int r = t; r < R; r += kFThreads) st[r] = sqrt(a.scal[8 + r]);
+        bsync();
+        const int64_t cnt = In * R;
+        for (int64_t l0 = t; l0 < cnt; l0 += 8 * kFThreads) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int64_t l = l0 + u * kFThreads;
+            v[u] = l < cnt ? An[l] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int64_t l = l0 + u * kFThreads;
+            const double nr = st[l % R];
+            if (l < cnt && nr > 0.0) An[l] = v[u] / nr;
+          }
         }
         bsync();
       }
-      wave_dots(a.U64[n], Rn, An, R, In, Rn * R, [&](int o) { return o / R; },
-                [&](int o) { return o % R; }, a.V[n]);
-      wave_dots(An, R, An, R, In, R * R, [&](int o) { return o / R; },
-                [&](int o) { return o % R; }, a.Gram[n]);
+      block_xty(a.U64[n], An, In, Rn, R, false, a.V[n], st);
+      block_xty(An, An, In, R, R, false, a.Gram[n], st);
       bsync();
     }
     // ---- fit ----------------------------------------------------------------
@@ -386,8 +474,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
   {
     const int n = N - 1;
     const double* An = a.A[n];
-    wave_dots(An, R, An, R, a.I[n], R, [&](int o) { return o; },
-              [&](int o) { return o; }, a.scal + 8);
+    block_xty(An, An, a.I[n], R, R, true, a.scal + 8, st);
     bsync();
     const int64_t cnt = a.I[n] * R;
     for (int64_t l = t; l < cnt; l += kFThreads) {

@@ -8,10 +8,16 @@ U_n and G in FP32; the oracle runs in FP64 on the same FP32 values.
 * Iterates: twelve HALS iterations from the same U[0,1] start; fits equal
   to 1e-9 (both FP64), factors and weights to 1e-6 (the device returns
   FP32).
-* Convergence (|dFit| < 1e-12): iteration counts within 2 of the oracle's
-  and the final fits equal to 1e-9.
-* Recovery, pinned to the generating model rather than to the oracle: every
-  component's SIR (footnote of Section V-A) at least 130 dB.  The paper's
+* Convergence (|dFit| < 1e-5): iteration counts within 1 of the oracle's
+  (it stops at 14, with dFit 5.9e-6 there and 2.7e-5 one step earlier) and
+  the final fits equal to 2e-8.  The stop is tested far above the rounding
+  floor of the closed-form fit 1 - sqrt(||Yt||^2 - 2<Yt, Yhat> +
+  ||Yhat||^2) / ||Yt||: near a perfect fit the root of that cancelling
+  difference is known only to ~1e-7, and from iteration ~17 on the fits of
+  both sides wander at that level, so a tighter stop is decided by rounding.
+* Recovery after 30 iterations, pinned to the generating model rather than
+  to the oracle: every component's SIR (footnote of Section V-A) at least
+  130 dB.  The paper's
   FP64 run reaches > 200 dB; here the FP32 rounding of U_n and G (relative
   6e-8) caps it near 150 dB (the FP64 oracle on these inputs: 149 dB), and
   the FP32 output adds its own rounding.
@@ -78,14 +84,19 @@ def test_hals_1e4_iterates(P, work):
     assert rel(host(out["lam"]), ref["lam"]) <= 1e-6
 
 
-def test_hals_1e4_convergence_and_recovery(P, work):
+def test_hals_1e4_convergence(P, work):
     w = work
-    out = run(P, w, 1000, 1e-12)
-    ref = F.ffcp(w["U"], w["G"], w["A0"], update="hals", max_it=1000, tol=1e-12)
-    it = int(out["info"]["iterations"])
+    out = run(P, w, 1000, 1e-5)
+    ref = F.ffcp(w["U"], w["G"], w["A0"], update="hals", max_it=1000, tol=1e-5)
     assert out["info"]["converged"] == 1 and ref["converged"]
-    assert abs(it - ref["iterations"]) <= 2
-    assert abs(out["info"]["fit"] - ref["fits"][-1]) <= 1e-9
+    assert abs(int(out["info"]["iterations"]) - ref["iterations"]) <= 1
+    assert abs(out["info"]["fit"] - ref["fits"][-1]) <= 2e-8
+
+
+def test_hals_1e4_recovery(P, work):
+    w = work
+    out = run(P, w, 30, 0.0)
+    assert int(out["info"]["iterations"]) == 30
     for n in range(4):
         A = host(out["A"][n])
         assert A.min() >= 0.0, n
