@@ -38,7 +38,9 @@ __device__ __forceinline__ void bsync() { __syncthreads(); }
 
 // Cross products of row-major FP64 matrices with packed rows:
 //   out[a * q + b] = sum_i X[i * p + a] Y[i * q + b]   (a < p, b < q),
-// or only the diagonal out[a] (diag; X = Y, p = q), over `rows` rows.
+// or only the diagonal out[a] (diag; X = Y, p = q), over `rows` rows; with
+// out2, also out2[a * q + b] = sum_i Y[i * q + a] Y[i * q + b] from the same
+// staged rows (one pass over Y for U^T A and A^T A).
 // One workgroup does it, so the cost is the number of dependent memory
 // round trips: the rows go through LDS in blocks as large as the staging
 // buffer holds (st: kXtyStage doubles; B rows of X and Y, one copy when
@@ -48,21 +50,24 @@ __device__ __forceinline__ void bsync() { __syncthreads(); }
 // that take every G-th row of a block; the G partial sums of an output are
 // added in group order at the end.  Every output is a sum in a fixed order:
 // deterministic.
+// KOUT bounds the outputs per thread: nout <= KOUT * threads.
 constexpr int kXtyStage = 2 * 64 * kRMax;            // doubles (64 KB)
-constexpr int kXtyOut = kRMax * kRMax / kFThreads;   // outputs per thread
 
+template <int KOUT>
 __device__ void block_xty(const double* X, const double* Y, int64_t rows, int p,
-                          int q, bool diag, double* out, double* st) {
+                          int q, bool diag, double* out, double* st,
+                          double* out2 = nullptr) {
   const int t = threadIdx.x;
   const bool same = X == Y;
   const int w = same ? p : p + q;              // staged doubles per row
   const int B = kXtyStage / w;                 // rows per block (>= 64)
-  const int nout = diag ? p : p * q;
+  const int nout1 = diag ? p : p * q;
+  const int nout = nout1 + (out2 ? q * q : 0);
   const int G = nout < kFThreads ? kFThreads / nout : 1;
   const int g = t / (nout < kFThreads ? nout : kFThreads);   // this thread's group
-  double acc[kXtyOut];
+  double acc[KOUT];
 #pragma unroll
-  for (int u = 0; u < kXtyOut; ++u) acc[u] = 0.0;
+  for (int u = 0; u < KOUT; ++u) acc[u] = 0.0;
   for (int64_t i0 = 0; i0 < rows; i0 += B) {
     const int nb = static_cast<int>(rows - i0 < B ? rows - i0 : B);
     const int nx = nb * p, ny = same ? 0 : nb * q;
@@ -72,20 +77,40 @@ __device__ void block_xty(const double* X, const double* Y, int64_t rows, int p,
       st[e] = e < nx ? X[xb + e] : Y[yb + (e - nx)];
     }
     bsync();
-    if (g < G) {
+    // sum over rows g, g + G, ... of the block for output o (X or Y first)
+    auto dot = [&](int o, bool batched) __attribute__((always_inline)) -> double {
+      const bool two = o >= nout1;
+      const int oo = two ? o - nout1 : o;
+      const double* sA = two ? sY : st;
+      const int pa = two ? q : p;
+      const int ia = diag ? oo : oo / q, ib = diag ? oo : oo % q;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int i = g;
+      if (batched) {
+        // 8 rows' operands read from LDS before their products, so the
+        // reads overlap instead of each waiting on the previous sum
+        for (; i + 7 * G < nb; i += 8 * G) {
+          double xa[8], yb[8];
 #pragma unroll
-      for (int u = 0; u < kXtyOut; ++u) {
-        const int o = (G > 1 ? t - g * nout : t) + u * kFThreads;
-        if (o < nout && (G > 1 ? u == 0 : true)) {
-          const int ia = diag ? o : o / q, ib = diag ? o : o % q;
-          double s0 = 0.0, s1 = 0.0;
-          int i = g;
-          for (; i + G < nb; i += 2 * G) {
-            s0 += st[i * p + ia] * sY[i * q + ib];
-            s1 += st[(i + G) * p + ia] * sY[(i + G) * q + ib];
+          for (int k = 0; k < 8; ++k) {
+            xa[k] = sA[(i + k * G) * pa + ia];
+            yb[k] = sY[(i + k * G) * q + ib];
           }
-          if (i < nb) s0 += st[i * p + ia] * sY[i * q + ib];
-          acc[u] += s0 + s1;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) s4[k & 3] += xa[k] * yb[k];
+        }
+      }
+      for (; i < nb; i += G) s4[0] += sA[i * pa + ia] * sY[i * q + ib];
+      return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    };
+    if (g < G) {
+      if (G > 1) {
+        acc[0] += dot(t - g * nout, true);   // one output per thread
+      } else {
+#pragma unroll
+        for (int u = 0; u < KOUT; ++u) {
+          const int o = t + u * kFThreads;
+          if (o < nout) acc[u] += dot(o, false);
         }
       }
     }
@@ -98,14 +123,15 @@ __device__ void block_xty(const double* X, const double* Y, int64_t rows, int p,
     for (int o = t; o < nout; o += kFThreads) {
       double v = 0.0;
       for (int k = 0; k < G; ++k) v += st[k * nout + o];
-      out[o] = v;
+      if (o < nout1) out[o] = v; else out2[o - nout1] = v;
     }
     bsync();
   } else {
 #pragma unroll
-    for (int u = 0; u < kXtyOut; ++u) {
+    for (int u = 0; u < KOUT; ++u) {
       const int o = t + u * kFThreads;
-      if (o < nout) out[o] = acc[u];
+      if (o < nout1) out[o] = acc[u];
+      else if (o < nout) out2[o - nout1] = acc[u];
     }
   }
 }
@@ -130,6 +156,8 @@ template <int RMAX>
 __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
   __shared__ double Ts[kRMax * kRMax];   // T, then its Cholesky factor
   __shared__ double st[kXtyStage];   // block_xty staging
+  // outputs per thread of the fused U^T A, A^T A pass (R_n <= 64, R <= RMAX)
+  constexpr int kVgOut = (kRMax * RMAX + RMAX * RMAX + kFThreads - 1) / kFThreads;
   __shared__ double red[kFWaves];
   __shared__ double sh[8];
   __shared__ int shi[4];
@@ -166,8 +194,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
     const int Rn = a.Rn[n];
     const double* Un = a.U64[n];
     const double* An = a.A[n];
-    block_xty(Un, An, a.I[n], Rn, R, false, a.V[n], st);
-    block_xty(An, An, a.I[n], R, R, false, a.Gram[n], st);
+    block_xty<kVgOut>(Un, An, a.I[n], Rn, R, false, a.V[n], st, a.Gram[n]);
   }
   bsync();
 
@@ -183,7 +210,8 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
       const int Rn = a.Rn[n];
       int64_t Cpost = coreSize / (Apre * Rn);
       // UtU in Ts (Rn <= 64)
-      block_xty(a.U64[n], a.U64[n], a.I[n], Rn, Rn, false, a.H, st);
+      block_xty<kRMax * kRMax / kFThreads>(a.U64[n], a.U64[n], a.I[n], Rn, Rn, false,
+                                            a.H, st);
       bsync();
       core_ttm_sq(src, bufs[cur], a.H, Apre, Rn, Cpost);
       bsync();
@@ -412,7 +440,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
         bsync();
       }
       if (n < N - 1) {
-        block_xty(An, An, In, R, R, true, a.scal + 8, st);
+        block_xty<1>(An, An, In, R, R, true, a.scal + 8, st);
         bsync();
         // column norms in LDS; 8 elements per thread and step, loads first
         for (int r = t; r < R; r += kFThreads) st[r] = sqrt(a.scal[8 + r]);
@@ -434,8 +462,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
         }
         bsync();
       }
-      block_xty(a.U64[n], An, In, Rn, R, false, a.V[n], st);
-      block_xty(An, An, In, R, R, false, a.Gram[n], st);
+      block_xty<kVgOut>(a.U64[n], An, In, Rn, R, false, a.V[n], st, a.Gram[n]);
       bsync();
     }
     // ---- fit ----------------------------------------------------------------
@@ -474,7 +501,7 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
   {
     const int n = N - 1;
     const double* An = a.A[n];
-    block_xty(An, An, a.I[n], R, R, true, a.scal + 8, st);
+    block_xty<1>(An, An, a.I[n], R, R, true, a.scal + 8, st);
     bsync();
     const int64_t cnt = a.I[n] * R;
     for (int64_t l = t; l < cnt; l += kFThreads) {
