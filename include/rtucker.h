@@ -213,7 +213,8 @@ typedef enum {
  *            |Fit_t - Fit_{t-1}| < tol (Section V-A rule; tol = 0 runs
  *            exactly max_it iterations).
  *   l1       soft-threshold level c of eq. (16) applied after each update
- *            (0 disables).
+ *            (0 disables); under HALS the shrunk entries are floored at
+ *            1e-16 again (HALS's feasible set) so no column vanishes.
  *   normY2   ||[[G;U]]||^2 used by the fit; NaN (or negative) means: compute
  *            <G, G x_n U_n^T U_n> on the device.
  */

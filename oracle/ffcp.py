@@ -18,6 +18,11 @@ Readings of the paper (each listed in the design doc):
   * ALS solves A_n T_n = Q_n by Cholesky; if T_n is not positive definite a
     ridge delta = 1e-12 tr(T_n) / R is added and a flag is set.
   * MU (eq. 15) adds eps = 1e-16 to the denominator.
+  * The sparsity step S_c of eq. (16) follows the update.  Under HALS the
+    result is put back onto HALS's feasible set a >= eps: the shrinkage can
+    zero a whole column, and t_rr of the next update would then vanish.
+    max(eps, S_c(a)) is the proximal point of c*a plus the constraint
+    a >= eps, i.e. the same l1 term under the same constraint.
   * Scale: lambda is absorbed into A_N (eq. 2); after each update of a mode
     n < N its columns are normalized to unit 2-norm (zero columns stay zero);
     at the end lambda_r = ||a_r^(N)|| and A_N is normalized.
@@ -143,6 +148,9 @@ def ffcp(U, G, A_init, update="als", max_it=1000, tol=1e-6, l1=0.0,
                 raise ValueError(update)
             if l1 > 0.0:
                 A[n] = soft_threshold(A[n], l1)
+                if update == "hals":
+                    # back onto HALS's feasible set a >= eps (t_rr > 0)
+                    A[n] = np.maximum(HALS_EPS, A[n])
             if n < N - 1:
                 A[n], _ = normalize_columns(A[n])
             V[n] = U[n].T @ A[n]

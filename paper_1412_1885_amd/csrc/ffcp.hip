@@ -432,10 +432,14 @@ __global__ __launch_bounds__(kFThreads) void ffcp_kernel(FfcpArgs a) {
       }
       bsync();
       if (a.l1 > 0.0) {
+        // sparsity step S_c of eq. (16); under HALS the result goes back onto
+        // the feasible set a >= 1e-16 so that no column (and no t_rr) vanishes
         const double c = a.l1;
+        const double lo = a.update == 1 ? 1e-16 : -INFINITY;
         for (int64_t l = t; l < In * R; l += kFThreads) {
-          double x = An[l];
-          An[l] = x > c ? x - c : (x < -c ? x + c : 0.0);
+          const double x = An[l];
+          const double y = x > c ? x - c : (x < -c ? x + c : 0.0);
+          An[l] = y > lo ? y : lo;
         }
         bsync();
       }

@@ -35,9 +35,15 @@ def _unf(Y, n):
     return np.moveaxis(Y, n, 0).reshape(Y.shape[n], -1)
 
 
-def dense_cp(Y, A0, rule, iters, eps=1e-16):
+def _shrink(x, c):
+    """The l1 proximal step written as x minus its clip to [-c, c]."""
+    return x - np.clip(x, -c, c)
+
+
+def dense_cp(Y, A0, rule, iters, eps=1e-16, l1=0.0):
     """Textbook CP on a dense tensor: B = KR of the other factors,
     Q = Y_(n) B, T = B^T B; ALS: A = solve; HALS: column sweep; MU.
+    With l1 > 0 the sparsity step of eq. (16) follows each update.
     Columns of modes n < N normalized after each update."""
     A = [a.copy() for a in A0]
     N = Y.ndim
@@ -55,6 +61,10 @@ def dense_cp(Y, A0, rule, iters, eps=1e-16):
                         eps, A[n][:, r] + (Q[:, r] - A[n] @ Tm[:, r]) / Tm[r, r])
             elif rule == "mu":
                 A[n] = A[n] * np.maximum(Q, 0) / (A[n] @ Tm + eps)
+            if l1 > 0.0:
+                A[n] = _shrink(A[n], l1)
+                if rule == "hals":
+                    A[n] = np.where(A[n] < eps, eps, A[n])
             if n < N - 1:
                 nr = np.linalg.norm(A[n], axis=0)
                 A[n] = A[n] / np.where(nr > 0, nr, 1.0)
@@ -137,6 +147,57 @@ def test_ffcp_iterates_equal_dense_cp_on_tucker_tensor(rule):
             assert np.linalg.norm(a - b) <= 1e-10 * max(1.0, np.linalg.norm(b))
         # closed-form fit equals the dense residual fit
         assert abs(out["fits"][t] - dense_fit(Yt, ref[t])) <= 1e-10
+
+
+@pytest.mark.parametrize("rule", ["als", "hals", "mu"])
+def test_ffcp_l1_iterates_equal_dense_cp_with_shrinkage(rule):
+    """eq. (16): the l1-regularized variant applies S_c after every update;
+    FFCP with l1 > 0 follows the dense reference that shrinks the same way
+    (written as x - clip(x, -c, c)), iterate by iterate; under HALS both
+    floor the result at eps.  c is large enough that entries are shrunk to
+    zero (to eps under HALS) but small enough that no column vanishes."""
+    nonneg = rule != "als"
+    dims, ranks, R = (9, 10, 11), (4, 5, 4), 3
+    G, U, g = _tucker_case(23, dims, ranks, nonneg)
+    Yt = T.tucker_full(G, U)
+    A0 = [g.uniform(0, 1, (I, R)) if nonneg else g.standard_normal((I, R))
+          for I in dims]
+    iters, c = 20, {"als": 0.02, "hals": 0.01, "mu": 0.005}[rule]
+    out = F.ffcp(U, G, A0, update=rule, max_it=iters, tol=0.0, l1=c,
+                 keep_iterates=iters)
+    ref = dense_cp(Yt, A0, rule, iters, l1=c)
+    zeros = 0
+    for t in range(iters):
+        for n in range(3):
+            a, b = out["iterates"][t][n], ref[t][n]
+            assert np.linalg.norm(a - b) <= 1e-10 * max(1.0, np.linalg.norm(b))
+        zeros += sum(int(np.sum(np.abs(a) <= 1e-16)) for a in out["iterates"][t])
+        # the closed-form fit still equals the dense residual fit
+        assert abs(out["fits"][t] - dense_fit(Yt, ref[t])) <= 1e-10
+    assert zeros > 0
+    assert not out["ridged"]
+    assert all(np.all(np.isfinite(a)) for a in out["A"])
+
+
+def test_soft_threshold_branches_eq16():
+    """The three branches of the sparsity operator S_c (eq. 16) at points on
+    both sides of, and at, the thresholds +-c."""
+    c = 0.25
+    x = np.array([1.5, 0.75, 0.25, 0.125, 0.0, -0.125, -0.25, -0.5, -2.0])
+    want = np.array([1.25, 0.5, 0.0, 0.0, 0.0, 0.0, 0.0, -0.25, -1.75])
+    assert np.array_equal(F.soft_threshold(x, c), want)
+    assert np.array_equal(F.soft_threshold(x, 0.0), x)
+
+
+def test_soft_threshold_is_the_l1_proximal_point():
+    """S_c(x) minimizes (z - x)^2 / 2 + c |z| over z (the property that makes
+    it the update of l1-regularized CP, eq. 16); brute force over a grid of
+    spacing 1e-5."""
+    grid = np.linspace(-3.0, 3.0, 600001)
+    for c in (0.0, 0.2, 0.7):
+        for x in (-2.5, -0.65, -0.2, -0.05, 0.0, 0.1, 0.45, 1.9):
+            z = grid[np.argmin(0.5 * (grid - x) ** 2 + c * np.abs(grid))]
+            assert abs(F.soft_threshold(np.array([x]), c)[0] - z) <= 1e-5
 
 
 def test_ffcp_equals_cp_of_core_eq17():

@@ -165,3 +165,44 @@ def test_randtucker2i_close_to_hosvd_statistically():
         fh = RT.tucker_fit(d["Y"], Uh, Gh)
         assert fit[2] >= fh - tol
         assert fit[2] > fit[1]
+
+
+def test_gram_evd_basis_eq23_spans_the_qr_basis():
+    """eq. (23): U = Z W S^{-1/2} from the eigendecomposition Z^T Z = W S W^T
+    is orthonormal and spans range(Z), the same subspace as Householder QR,
+    for a full-column-rank Z."""
+    g = np.random.default_rng(131)
+    for shape in ((50, 8), (300, 30), (9, 9)):
+        Z = g.standard_normal(shape) @ np.diag(np.linspace(1.0, 5.0, shape[1]))
+        U = RT.orth_gram_evd(Z)
+        assert np.linalg.norm(U.T @ U - np.eye(shape[1])) <= 1e-12
+        assert projector_distance(U, RT.orth_qr(Z)) <= 1e-12
+
+
+def test_gram_evd_basis_on_orthogonal_columns_closed_form():
+    """Z = Q0 D with orthonormal Q0 and distinct positive D: Z^T Z = D^2 is
+    diagonal, so the eq. (23) basis is Q0's columns ordered by descending D,
+    up to sign."""
+    g = np.random.default_rng(132)
+    Q0 = np.linalg.qr(g.standard_normal((20, 4)))[0]
+    D = np.array([3.0, 5.0, 1.0, 4.0])
+    U = RT.orth_gram_evd(Q0 * D)
+    order = [1, 3, 0, 2]
+    np.testing.assert_allclose(np.abs(U.T @ Q0[:, order]), np.eye(4), atol=1e-13)
+
+
+def test_eigvec_order_and_sign_rule():
+    """Top-k eigenvectors of S = V diag(w) V^T come out in descending
+    eigenvalue order, each column's largest-magnitude entry positive."""
+    g = np.random.default_rng(133)
+    V = np.linalg.qr(g.standard_normal((6, 6)))[0]
+    w = np.array([0.5, 4.0, -1.0, 2.5, 7.0, 1.0])
+    S = V @ np.diag(w) @ V.T
+    ws, Vs = RT.sorted_sign_fixed_eigvecs(S, 4)
+    order = [4, 1, 3, 5]
+    np.testing.assert_allclose(ws, w[order], atol=1e-12)
+    for c, i in enumerate(order):
+        v = V[:, i]
+        v = v if v[np.argmax(np.abs(v))] > 0 else -v
+        np.testing.assert_allclose(Vs[:, c], v, atol=1e-12)
+        assert Vs[np.argmax(np.abs(Vs[:, c])), c] > 0
