@@ -280,6 +280,34 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
             double* fit_trace, rt_ffcp_info* info, void* stream);
 
 /*
+ * Algorithm 1 with the dense tensor as its input (the problem statement
+ * "ffcp(Y, R)"): RandTucker2i compresses Y exactly as rt_tucker_rand does,
+ * then FFCP runs on the Tucker format it returns exactly as rt_ffcp does.
+ * The Tucker format lives in the workspace (the caller does not see it).
+ *
+ *   tdesc     the compression (rt_tucker_rand's description); precision
+ *             RT_F32 or RT_BF16_MIXED (RT_F64: RT_ERR_UNSUPPORTED, FFCP reads
+ *             an FP32 format).
+ *   fdesc     the fit (rt_ffcp's description); N, dims and ranks must equal
+ *             the Tucker output's (R_n, or R~_n with RT_FLAG_NO_TRUNCATE),
+ *             else RT_ERR_INVALID_ARG.
+ *   Y, Omega, Omega_t, Ybf16, tinfo: as rt_tucker_rand's Y, Omega, Omega_t,
+ *             Ybf16, info.
+ *   A_init, pad, A, lambda, fit_trace, finfo: as rt_ffcp's A_init, pad, A,
+ *             lambda, fit_trace, info.
+ *   ws        device workspace of ws_bytes >= rt_ffcp_dense_workspace().
+ * Every argument of both stages is checked before anything is enqueued.
+ * Errors: those of rt_tucker_rand and rt_ffcp.
+ */
+int rt_ffcp_dense_workspace(const rt_tucker_desc* tdesc, const rt_ffcp_desc* fdesc,
+                            size_t* bytes);
+int rt_ffcp_dense(const rt_tucker_desc* tdesc, const rt_ffcp_desc* fdesc, const void* Y,
+                  const void* const* Omega, const void* const* Omega_t, uint16_t* Ybf16,
+                  const float* const* A_init, const float* const* pad, void* ws,
+                  size_t ws_bytes, float* const* A, float* lambda, double* fit_trace,
+                  rt_tucker_info* tinfo, rt_ffcp_info* finfo, void* stream);
+
+/*
  * Mode-n product out = X x_n M^T (the contraction the paper writes
  * Y x_n U^T, eq. (1) and Algorithms 2-3): X viewed as [A, I, C] with
  * A = prod_{p<n} I_p, I = I_n, C = prod_{p>n} I_p; M is I x K row-major;

@@ -76,6 +76,18 @@ class RtError(RuntimeError):
         self.status = status
 
 
+RT_ERR_NONFINITE = -4
+
+
+class NonFiniteInput(RtError):
+    """The device saw a NaN or Inf in Y (rt_tucker_info.nonfinite).  The
+    call's outputs are attached as ``.out``."""
+
+    def __init__(self, out):
+        super().__init__(RT_ERR_NONFINITE, "Y holds a NaN or Inf value")
+        self.out = out
+
+
 def lib():
     """Load librtucker.so (raises if it has not been built)."""
     global _lib_handle
@@ -96,6 +108,12 @@ def lib():
         L.rt_ffcp.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
                               ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
                               ctypes.POINTER(vp), vp, vp, vp, vp]
+        L.rt_ffcp_dense_workspace.argtypes = [ctypes.POINTER(TuckerDesc),
+                                              ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
+        L.rt_ffcp_dense.argtypes = [ctypes.POINTER(TuckerDesc), ctypes.POINTER(FfcpDesc), vp,
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
+                                    ctypes.POINTER(vp), vp, vp, vp, vp, vp]
         L.rt_ttm.argtypes = [i32, i64, i64, i64, i32, vp, vp, vp, vp]
         L.rt_stream_pass.argtypes = [i32, i64, i64, i64, vp, vp, i32, vp, i32, vp, vp,
                                      vp, vp, sz, vp]
@@ -116,7 +134,7 @@ def lib():
         L.rt_version.restype = ctypes.c_char_p
         for f in ("rt_tucker_rand_workspace", "rt_tucker_bf16_copy_elems",
                   "rt_tucker_rand", "rt_ffcp_workspace",
-                  "rt_ffcp", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
+                  "rt_ffcp", "rt_ffcp_dense_workspace", "rt_ffcp_dense", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
                   "rt_stream_pass", "rt_profile_enable", "rt_profile_read",
                   "rt_mlp_workspace", "rt_mlp_sync_bf16", "rt_mlp_forward", "rt_mlp_grad",
                   "rt_mlp_train_step"):
@@ -219,11 +237,13 @@ def bf16_copy_shape(dims, ranks_tilde=None):
 
 def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
                 truncate=True, trace=False, ybf16=None, bf16_input=False,
-                dims=None, workspace=None, stream=None, sync=True):
+                dims=None, workspace=None, stream=None, sync=True,
+                check_finite=True):
     """rt_tucker_rand.  Y: device tensor (float32 / float64, or int16/uint16
     BF16 bit patterns with bf16_input).  omegas: N device matrices I_n x R~_n.
     omega_tildes: list over sweeps of N device matrices.  Returns a dict with
-    U (list), G, and when sync, info (numpy record) and the optional trace."""
+    U (list), G, and when sync, info (numpy record) and the optional trace.
+    With sync and check_finite, a NaN/Inf in Y raises NonFiniteInput."""
     torch = _torch()
     dims = list(Y.shape) if dims is None else list(dims)
     N = len(dims)
@@ -278,6 +298,8 @@ def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
     if sync:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         out["info"] = np.frombuffer(info.cpu().numpy().tobytes(), TUCKER_INFO_DTYPE)[0]
+        if check_finite and int(out["info"]["nonfinite"]) != 0:
+            raise NonFiniteInput(out)
     return out
 
 
@@ -347,6 +369,64 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
         out["info"] = inf
         if ft is not None:
             out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
+    return out
+
+
+def ffcp_dense_workspace(tdesc, fdesc):
+    n = ctypes.c_size_t(0)
+    _check(lib().rt_ffcp_dense_workspace(ctypes.byref(tdesc), ctypes.byref(fdesc),
+                                         ctypes.byref(n)))
+    return n.value
+
+
+def ffcp_dense(Y, omegas, omega_tildes, R, ranks=None, sweeps=1, precision="f32",
+               update="als", A_init=None, init=None, pad=None, max_it=1000, tol=1e-6,
+               l1=0.0, normY2=None, fit_trace=False, ybf16=None, stream=None,
+               sync=True, check_finite=True):
+    """rt_ffcp_dense: Algorithm 1 on the dense Y (RandTucker2i, then FFCP on
+    its Tucker format, in one call).  Arguments as tucker_rand and ffcp;
+    A_init / pad as ffcp's (I_n x R starts, or R_n x R coefficients)."""
+    torch = _torch()
+    dims = list(Y.shape)
+    N = len(dims)
+    rt = [int(o.shape[1]) for o in omegas]
+    rk = list(ranks) if ranks is not None else rt
+    tdesc = tucker_desc(dims, rt, rk, sweeps, precision)
+    if init is None:
+        init = "user" if A_init is not None else "hosvd"
+    fdesc = ffcp_desc(dims, rk, R, update, init, max_it, tol, l1, normY2)
+    _require_device(Y, "Y")
+    for n in range(N):
+        _require_device(omegas[n], f"omegas[{n}]", torch.float32)
+        for s_ in range(sweeps):
+            _require_device(omega_tildes[s_][n], f"omega_tildes[{s_}][{n}]", torch.float32)
+    dev = Y.device
+    if precision == "bf16" and ybf16 is None:
+        ybf16 = torch.empty(bf16_copy_shape(dims, rt), dtype=torch.int16, device=dev)
+    A = [torch.empty((dims[n], R), dtype=torch.float32, device=dev) for n in range(N)]
+    lam = torch.empty(R, dtype=torch.float32, device=dev)
+    tinfo = torch.zeros(TUCKER_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    finfo = torch.zeros(FFCP_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ft = torch.zeros(max_it, dtype=torch.float64, device=dev) if fit_trace else None
+    ws = _workspace(ffcp_dense_workspace(tdesc, fdesc), dev)
+    om = _ptr_array(omegas)
+    omt = _ptr_array([omega_tildes[s_][n] for s_ in range(sweeps) for n in range(N)])
+    _check(lib().rt_ffcp_dense(ctypes.byref(tdesc), ctypes.byref(fdesc), _ptr(Y), om, omt,
+                               _ptr(ybf16),
+                               _ptr_array(A_init) if A_init is not None else None,
+                               _ptr_array(pad) if pad is not None else None,
+                               _ptr(ws), ws.numel(), _ptr_array(A), _ptr(lam), _ptr(ft),
+                               _ptr(tinfo), _ptr(finfo), _stream_handle(stream)))
+    out = {"A": A, "lam": lam, "workspace": ws}
+    if sync:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        out["tucker_info"] = np.frombuffer(tinfo.cpu().numpy().tobytes(), TUCKER_INFO_DTYPE)[0]
+        inf = np.frombuffer(finfo.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]
+        out["info"] = inf
+        if ft is not None:
+            out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
+        if check_finite and int(out["tucker_info"]["nonfinite"]) != 0:
+            raise NonFiniteInput(out)
     return out
 
 

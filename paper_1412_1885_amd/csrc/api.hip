@@ -109,7 +109,8 @@ int validate_tucker(const rt_tucker_desc* d) {
     return kErrUnsupported;
   }
   if (d->precision == RT_BF16_MIXED)
-    RT_TRY(bf16_check_shape(d->dims[d->N - 2], d->dims[d->N - 1],
+    RT_TRY(bf16_check_shape(total / (d->dims[d->N - 2] * d->dims[d->N - 1]),
+                            d->dims[d->N - 2], d->dims[d->N - 1],
                             d->ranks_tilde[d->N - 2], d->ranks_tilde[d->N - 1]));
   return kOk;
 }
@@ -752,6 +753,139 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
     if (rc != kErrUnsupported) return rc;
   }
   return launch_ffcp(a, s);
+}
+
+namespace {
+
+// The FFCP stage of rt_ffcp_dense fits the Tucker format rt_tucker_rand
+// returns: same order and sizes, FP32.
+int validate_dense(const rt_tucker_desc* td, const rt_ffcp_desc* fd) {
+  RT_TRY(validate_tucker(td));
+  RT_TRY(validate_ffcp(fd));
+  if (td->precision == RT_F64) {
+    set_error("rt_ffcp_dense: FFCP reads an FP32 Tucker format (RT_F32 or "
+              "RT_BF16_MIXED)");
+    return kErrUnsupported;
+  }
+  if (fd->N != td->N) {
+    set_error("rt_ffcp_dense: FFCP N=%d differs from the tensor's N=%d", fd->N, td->N);
+    return kErrInvalid;
+  }
+  const bool trunc = !(td->flags & RT_FLAG_NO_TRUNCATE);
+  for (int n = 0; n < td->N; ++n) {
+    const int rn = trunc ? td->ranks[n] : td->ranks_tilde[n];
+    if (fd->dims[n] != td->dims[n] || fd->ranks[n] != rn) {
+      set_error("rt_ffcp_dense: mode %d of the FFCP description (I=%lld, R_n=%d) "
+                "differs from the Tucker output (I=%lld, R_n=%d)",
+                n, (long long)fd->dims[n], fd->ranks[n], (long long)td->dims[n], rn);
+      return kErrInvalid;
+    }
+  }
+  return kOk;
+}
+
+struct DensePlan {
+  void* tws;
+  size_t tbytes;
+  float* U[RT_MAX_MODES];
+  float* G;
+  void* fws;
+  size_t fbytes;
+  size_t plan(const rt_tucker_desc* td, const rt_ffcp_desc* fd, void* ws) {
+    Arena ar(ws);
+    if (td->precision == RT_F64) {
+      TuckerPlan<double> p;
+      tbytes = p.plan(td, nullptr);
+    } else {
+      TuckerPlan<float> p;
+      tbytes = p.plan(td, nullptr);
+    }
+    FfcpPlan fp;
+    fbytes = fp.plan(fd, nullptr);
+    tws = ar.take<char>(tbytes);
+    int64_t core = 1;
+    for (int n = 0; n < fd->N; ++n) {
+      U[n] = ar.take<float>(fd->dims[n] * fd->ranks[n]);
+      core *= fd->ranks[n];
+    }
+    G = ar.take<float>(core);
+    fws = ar.take<char>(fbytes);
+    return ar.need;
+  }
+};
+
+}  // namespace
+
+int rt_ffcp_dense_workspace(const rt_tucker_desc* tdesc, const rt_ffcp_desc* fdesc,
+                            size_t* bytes) {
+  RT_TRY(validate_dense(tdesc, fdesc));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return kErrInvalid;
+  }
+  DensePlan p;
+  *bytes = p.plan(tdesc, fdesc, nullptr);
+  return kOk;
+}
+
+int rt_ffcp_dense(const rt_tucker_desc* tdesc, const rt_ffcp_desc* fdesc, const void* Y,
+                  const void* const* Omega, const void* const* Omega_t, uint16_t* Ybf16,
+                  const float* const* A_init, const float* const* pad, void* ws,
+                  size_t ws_bytes, float* const* A, float* lambda, double* fit_trace,
+                  rt_tucker_info* tinfo, rt_ffcp_info* finfo, void* stream) {
+  RT_TRY(validate_dense(tdesc, fdesc));
+  RT_TRY(check_ptr(ws, "ws"));
+  DensePlan p;
+  const size_t need = p.plan(tdesc, fdesc, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return kErrWorkspace;
+  }
+  p.plan(tdesc, fdesc, ws);
+  // every argument of both stages is checked before the first launch: the
+  // FFCP stage's pointers here, the Tucker stage's by rt_tucker_rand itself
+  // (which enqueues nothing when it rejects an argument)
+  RT_TRY(check_ptr(lambda, "lambda"));
+  if (!A) {
+    set_error("A array must not be NULL");
+    return kErrInvalid;
+  }
+  const int N = fdesc->N, R = fdesc->R;
+  for (int n = 0; n < N; ++n) RT_TRY(check_ptr(A[n], "A[n]"));
+  const bool coeff = fdesc->init == RT_INIT_COEFF || fdesc->init == RT_INIT_COEFF_GUARDED;
+  const bool hosvd = fdesc->init == RT_INIT_HOSVD || fdesc->init == RT_INIT_COEFF_GUARDED;
+  if (fdesc->init == RT_INIT_USER || coeff) {
+    if (!A_init) {
+      set_error("A_init is NULL with RT_INIT_USER / RT_INIT_COEFF");
+      return kErrInvalid;
+    }
+    for (int n = 0; n < N; ++n) RT_TRY(check_ptr(A_init[n], "A_init[n]"));
+  }
+  if (hosvd) {
+    for (int n = 0; n < N; ++n) {
+      if (R > fdesc->ranks[n]) {
+        if (!pad || !pad[n]) {
+          set_error("HOSVD init with R > R_%d needs pad[%d]", n, n);
+          return kErrInvalid;
+        }
+        RT_TRY(check_ptr(pad[n], "pad[n]"));
+      }
+    }
+  }
+  if ((finfo && !aligned16(finfo)) || (fit_trace && !aligned16(fit_trace))) {
+    set_error("info / fit_trace not 16-byte aligned");
+    return kErrInvalid;
+  }
+  void* Uv[RT_MAX_MODES];
+  const float* Uc[RT_MAX_MODES];
+  for (int n = 0; n < N; ++n) {
+    Uv[n] = p.U[n];
+    Uc[n] = p.U[n];
+  }
+  RT_TRY(rt_tucker_rand(tdesc, Y, Omega, Omega_t, p.tws, p.tbytes, Uv, p.G, Ybf16, tinfo,
+                        nullptr, stream));
+  return rt_ffcp(fdesc, Uc, p.G, A_init, pad, p.fws, p.fbytes, A, lambda, fit_trace, finfo,
+                 stream);
 }
 
 int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,

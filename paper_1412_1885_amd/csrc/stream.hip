@@ -141,14 +141,14 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
           if (ct + 1 < nct) load_tile(r0, ct + 1, gnext);
           else if (rn < I1) load_tile(rn, 0, gnext);
           // stage the tile (wave-private; LDS accesses of a wave are ordered)
-          float ss = 0.f;
+          // squares in FP64: FLT_MAX^2 is finite there, so only a NaN or
+          // Inf in Y makes ||Y||^2 non-finite
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             *reinterpret_cast<float4*>(tile + swz(8 * u + lrow, lchunk)) = gcur[u];
-            ss += gcur[u].x * gcur[u].x + gcur[u].y * gcur[u].y +
-                  gcur[u].z * gcur[u].z + gcur[u].w * gcur[u].w;
+            const double x = gcur[u].x, y = gcur[u].y, z = gcur[u].z, w = gcur[u].w;
+            nacc += (x * x + y * y) + (z * z + w * w);
           }
-          nacc += static_cast<double>(ss);
           __builtin_amdgcn_wave_barrier();
 #pragma unroll
           for (int u = 0; u < 4; ++u) {

@@ -35,7 +35,7 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
 
 // BF16 precision form (stream_bf16.hip)
 size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2);
-int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2);
+int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2);
 // row stride (values) of the BF16 copy of rows of I2 values: I2 rounded up
 // to a multiple of 64
 int64_t bf16_copy_ld(int64_t I2);

@@ -54,6 +54,7 @@
 // that is not yet needed.  A workgroup holds about 246 VGPRs per lane and
 // 130 KB of LDS, so a CU runs one (8 wavefronts): the tiles in flight,
 // not the access pattern, bound a pass (3.7-4.2 TB/s at 1000^3).
+#include <cfloat>
 #include <utility>
 
 #include "stream.hpp"
@@ -384,18 +385,20 @@ __device__ __forceinline__ float4 load_group(const float* src, uint32_t gi, uint
 
 __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* Y,
                                                                     uint16_t* Yb, int I1,
-                                                                    int I2, int ldy,
+                                                                    int I2, int ldy, int nb,
                                                                     float* pmax,
                                                                     double* psum) {
   __shared__ float smax[kCvtThreads / 64];
   __shared__ double ssum[kCvtThreads / 64];
-  const int64_t a = blockIdx.y;
+  // one-dimensional grid of A * nb blocks: block b of slab a is a * nb + b
+  const int64_t a = blockIdx.x / static_cast<uint32_t>(nb);
+  const uint32_t blk = blockIdx.x - static_cast<uint32_t>(a) * static_cast<uint32_t>(nb);
   // I1 * ldy < 2^30 (shape check), so 32-bit group and value indexes
   const uint32_t q = static_cast<uint32_t>(ldy) / 4;   // groups per copy row
   const uint32_t ng = static_cast<uint32_t>(I1) * q;   // groups per copy slab
   const float* src = Y + a * I1 * I2;
   uint2* dst = reinterpret_cast<uint2*>(Yb + a * I1 * ldy);
-  const uint32_t g0 = blockIdx.x * (kCvtThreads * kCvtGroups) + threadIdx.x;
+  const uint32_t g0 = blk * (kCvtThreads * kCvtGroups) + threadIdx.x;
   float4 v[kCvtGroups];
 #pragma unroll
   for (int u = 0; u < kCvtGroups; ++u) v[u] = load_group(src, g0 + u * kCvtThreads, q, ng, I2);
@@ -411,7 +414,8 @@ __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* 
     mx = fmaxf(mx, fmaxf(fmaxf(ax, ay), fmaxf(az, aw)));
     const double dx = v[u].x, dy = v[u].y, dz = v[u].z, dw = v[u].w;
     sq += (dx * dx + dy * dy) + (dz * dz + dw * dw);
-    finite = finite && ax <= 3.4e38f && ay <= 3.4e38f && az <= 3.4e38f && aw <= 3.4e38f;
+    // NaN fails every comparison and Inf exceeds the largest finite float
+    finite = finite && ax <= FLT_MAX && ay <= FLT_MAX && az <= FLT_MAX && aw <= FLT_MAX;
   }
   if (!finite) sq = __longlong_as_double(0x7ff8000000000000LL);
   sq = wave_sum(sq);
@@ -430,9 +434,8 @@ __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* 
       m = fmaxf(m, smax[w]);
       t += ssum[w];
     }
-    const int64_t i = a * gridDim.x + blockIdx.x;
-    pmax[i] = m;
-    psum[i] = t;
+    pmax[blockIdx.x] = m;   // [a][blk]
+    psum[blockIdx.x] = t;
   }
 }
 
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(256) void slab_finish_kernel(const float* pmax,
   if (threadIdx.x == 0) {
     const float mm = fmaxf(fmaxf(rmax[0], rmax[1]), fmaxf(rmax[2], rmax[3]));
     int e = 0;
-    if (mm > 0.0f && mm <= 3.4e38f) e = ilogbf(mm);
+    if (mm > 0.0f && mm <= FLT_MAX) e = ilogbf(mm);
     e = e < -126 ? -126 : (e > 127 ? 127 : e);
     exps[a] = (e >= -kScaleWindow && e <= kScaleWindow) ? 0 : e;
     slab_sum[a] = (red[0] + red[1]) + (red[2] + red[3]);
@@ -588,13 +591,20 @@ size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
   return bf16_ws_layout(nullptr, A, I1, I2).bytes + 512;
 }
 
-int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
+int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2) {
   // a slab of the padded copy must stay below the masked-load offset
   if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 ||
       I1 * bf16_copy_ld(I2) * 2 > kOob - 64) {
     set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0, "
               "I_{N-1} I_N < 2^30 and sketch widths <= 32 (got %lld, %lld, %d, %d)",
               kMaxI1, (long long)I1, (long long)I2, K1, K2);
+    return kErrUnsupported;
+  }
+  // one-dimensional grids: A slabs (streaming passes), A x blocks per slab
+  // (conversion)
+  if (A * cvt_blocks(I1, I2) > 0x7fffffffLL) {
+    set_error("BF16 conversion: %lld slabs of %lld x %lld exceed 2^31 - 1 blocks",
+              (long long)A, (long long)I1, (long long)I2);
     return kErrUnsupported;
   }
   return kOk;
@@ -605,7 +615,7 @@ int bf16_check_shape(int64_t I1, int64_t I2, int K1, int K2) {
 int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
                      const float* B1, int K1, float* TA, float* TB, int stage,
                      hipStream_t s) {
-  RT_TRY(bf16_check_shape(c.I1, c.I2, B1 ? K1 : 0, K2));
+  RT_TRY(bf16_check_shape(c.A, c.I1, c.I2, B1 ? K1 : 0, K2));
   const int64_t l1 = (c.I1 + 63) / 64 * 64, l2 = (c.I2 + 63) / 64 * 64;
   char* base = static_cast<char*>(c.ws) + 1024 * sizeof(double) + 256;
   const BfWs w = bf16_ws_layout(base, c.A, c.I1, c.I2);
@@ -632,18 +642,13 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
     // the BF16 copy (padded rows) and the statistics in one read of Y, then
     // the slab exponents and the rare slabs that need a scale; every
     // contraction reads the copy
-    const int64_t nb = cvt_blocks(c.I1, c.I2);
-    if (c.A > 65535 || nb > 0x7fffffff) {
-      set_error("BF16 conversion: too many slabs (%lld)", (long long)c.A);
-      return kErrUnsupported;
-    }
+    const int64_t nb = cvt_blocks(c.I1, c.I2);   // A * nb < 2^31 (shape check)
     {
       ProfScope ps(kStageConvert, s);
-      hipLaunchKernelGGL(bf16_convert_kernel,
-                         dim3(static_cast<unsigned>(nb), static_cast<unsigned>(c.A)),
+      hipLaunchKernelGGL(bf16_convert_kernel, dim3(static_cast<unsigned>(c.A * nb)),
                          dim3(kCvtThreads), 0, s, static_cast<const float*>(c.y), c.ybf16,
                          static_cast<int>(c.I1), static_cast<int>(c.I2),
-                         static_cast<int>(c.ldy), w.pmax, w.psum);
+                         static_cast<int>(c.ldy), static_cast<int>(nb), w.pmax, w.psum);
       RT_LAUNCH_CHECK("bf16 convert");
     }
     ProfScope ps(kStageStats, s);
@@ -672,10 +677,6 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   a.K1 = B1 ? K1 : 0;
   a.TA = TA;
   a.TB = TB;
-  if (c.A > 0x7fffffff) {
-    set_error("BF16 streaming pass: too many slabs (%lld)", (long long)c.A);
-    return kErrUnsupported;
-  }
   const int grid = static_cast<int>(c.A);   // one workgroup per slab
   ProfScope ps(stage, s);
   if (B1) return launch_bf_half<true>(a, grid, s);

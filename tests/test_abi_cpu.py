@@ -164,3 +164,50 @@ def test_mlp_descriptor_validation():
     assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1
     d = P.mlp_desc(16, (20, 20, 20), 20, hidden=(100, 64))   # width not a multiple of 8
     assert P.lib().rt_mlp_workspace(ctypes.byref(d), ctypes.byref(n)) == -1
+
+
+def test_bf16_slab_count_checked_at_validation():
+    """The conversion's one-dimensional grid holds every (slab, block) pair:
+    300^4 (90,000 slabs) is accepted; a shape needing more than 2^31 - 1
+    blocks is rejected on the host before anything is launched."""
+    n = ctypes.c_size_t(0)
+    ok = P.tucker_desc([300, 300, 300, 300], [4, 4, 4, 4], [2, 2, 2, 2], precision="bf16")
+    assert P.lib().rt_tucker_rand_workspace(ctypes.byref(ok), ctypes.byref(n)) == 0
+    big = P.tucker_desc([2 ** 22, 2 ** 11, 1024, 4], [2, 2, 2, 2], [1, 1, 1, 1],
+                        precision="bf16")
+    assert P.lib().rt_tucker_rand_workspace(ctypes.byref(big), ctypes.byref(n)) == -2
+    assert "blocks" in P.last_error()
+
+
+def _dense_descs(**kw):
+    td = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7], sweeps=2)
+    fd = P.ffcp_desc([40, 50, 60], [5, 6, 7], 4, "als", "hosvd")
+    for k, v in kw.items():
+        setattr(td, k, v)
+    return td, fd
+
+
+def test_ffcp_dense_workspace_and_validation():
+    """rt_ffcp_dense: its workspace holds both stages; the FFCP description
+    must match the Tucker output and the compression must be FP32-output."""
+    L = P.lib()
+    n, nt, nf = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+    td, fd = _dense_descs()
+    assert L.rt_ffcp_dense_workspace(ctypes.byref(td), ctypes.byref(fd), ctypes.byref(n)) == 0
+    assert L.rt_tucker_rand_workspace(ctypes.byref(td), ctypes.byref(nt)) == 0
+    assert L.rt_ffcp_workspace(ctypes.byref(fd), ctypes.byref(nf)) == 0
+    assert n.value >= nt.value + nf.value
+    td, fd = _dense_descs()
+    fd.ranks[1] = 7                                   # not the Tucker output rank
+    assert L.rt_ffcp_dense_workspace(ctypes.byref(td), ctypes.byref(fd), ctypes.byref(n)) == -1
+    assert "differs" in P.last_error()
+    td, fd = _dense_descs(precision=2)                # FP64 compression
+    assert L.rt_ffcp_dense_workspace(ctypes.byref(td), ctypes.byref(fd), ctypes.byref(n)) == -2
+    td, fd = _dense_descs()
+    vp = ctypes.c_void_p
+    arr = (vp * 6)(*[256 * (i + 1) for i in range(6)])
+    # a NULL lambda is rejected before the compression is enqueued
+    rc = L.rt_ffcp_dense(ctypes.byref(td), ctypes.byref(fd), vp(4096), arr, arr, None,
+                         None, None, vp(1 << 20), n.value, arr, None, None, None, None,
+                         None)
+    assert rc == -1 and "lambda" in P.last_error()

@@ -199,14 +199,41 @@ def test_tucker_rank_deficient_sketch(P, precision):
                               ref["G"], ref["U"]) <= tol
 
 
-def test_tucker_nonfinite_flag(P):
-    d = synth.case_tucker(304, (20, 21, 22), (3, 3, 3), 30.0, (5, 5, 5))
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_tucker_nonfinite_flag(P, precision, bad):
+    """A NaN or Inf anywhere in Y sets the info flag (both streaming forms)
+    and the Python wrapper raises."""
+    d = synth.case_tucker(304, (20, 21, 24), (3, 3, 3), 30.0, (5, 5, 5))
     Y = synth.f32(d["Y"]).copy()
-    Y[3, 4, 5] = np.nan
+    Y[3, 4, 5] = bad
+    args = (dev(Y), [dev(synth.f32(o)) for o in d["omegas"]],
+            [[dev(synth.f32(o)) for o in d["omega_tildes"][0]]])
+    out = P.tucker_rand(*args, ranks=(3, 3, 3), sweeps=1, precision=precision,
+                        check_finite=False)
+    assert out["info"]["nonfinite"] == 1
+    with pytest.raises(P.NonFiniteInput):
+        P.tucker_rand(*args, ranks=(3, 3, 3), sweeps=1, precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_tucker_largest_finite_values_are_finite(P, precision):
+    """Values of magnitude FLT_MAX are finite: no flag, and ||Y||^2 is the
+    FP64 sum of squares (FLT_MAX^2 ~ 1.2e77 is an ordinary FP64 number).
+    In the precision form that slab is scaled by 2^-127 before rounding."""
+    d = synth.case_tucker(308, (6, 20, 24), (3, 3, 3), 30.0, (5, 5, 5))
+    Y = synth.f32(d["Y"]).copy()
+    fmax = np.finfo(np.float32).max
+    Y[2, 4, 5] = fmax
+    Y[2, 7, 9] = -fmax
     out = P.tucker_rand(dev(Y), [dev(synth.f32(o)) for o in d["omegas"]],
                         [[dev(synth.f32(o)) for o in d["omega_tildes"][0]]],
-                        ranks=(3, 3, 3), sweeps=1)
-    assert out["info"]["nonfinite"] == 1
+                        ranks=(3, 3, 3), sweeps=1, precision=precision)
+    assert out["info"]["nonfinite"] == 0
+    Y64 = Y.astype(np.float64)
+    n2 = float(np.sum(Y64 * Y64))
+    assert np.isfinite(out["info"]["normY2"])
+    assert abs(out["info"]["normY2"] - n2) <= 1e-6 * n2
 
 
 # ------------------------------------------------------------------ FFCP
@@ -441,8 +468,41 @@ def test_stream_pass_parity(P, shape, K):
     for got, want in ((TA, T.ttm_t(Y, B2, 2)), (TB, T.ttm_t(Y, B1, 1))):
         assert rel(host(got), want) <= 2e-6
         assert maxrel(host(got), want) <= 2e-6
-    # squares are summed in FP32 per 16-element tile, then in FP64
-    assert abs(n2 - np.sum(Y * Y)) <= 1e-6 * np.sum(Y * Y)
+    # squares are summed in FP64 (each square of an FP32 value is exact)
+    assert abs(n2 - np.sum(Y * Y)) <= 1e-12 * np.sum(Y * Y)
     TA2, TB2, _ = P.stream_pass(dev(Y), dev(B2))
     assert TB2 is None
     assert rel(host(TA2), T.ttm_t(Y, B2, 2)) <= 2e-6
+
+
+# ------------------------------------------------------------- ffcp_dense
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_ffcp_dense_is_tucker_then_ffcp(P, precision):
+    """rt_ffcp_dense (Algorithm 1 with input Y) runs the same kernels on the
+    same values as rt_tucker_rand followed by rt_ffcp, so its factors,
+    weights and fit trace are bit-identical to the two calls'; in FP32 its
+    fit trace also follows the oracle's (RandTucker2i, then FFCP from the
+    HOSVD start of the oracle's core) to FP32 rounding of the format."""
+    dims, R, rk, rt = (40, 44, 48), 4, (6, 6, 6), (8, 8, 8)
+    d = synth.case_cp_gaussian(seed_of("dense", precision), dims, R, 30.0, rt, sweeps=2)
+    Y = synth.f32(d["Y"])
+    om = [dev(synth.f32(o)) for o in d["omegas"]]
+    omt = [[dev(synth.f32(o)) for o in lst] for lst in d["omega_tildes"]]
+    kw = dict(update="als", init="hosvd", max_it=40, tol=0.0, fit_trace=True)
+    one = P.ffcp_dense(dev(Y), om, omt, R, ranks=rk, sweeps=2, precision=precision, **kw)
+    t = P.tucker_rand(dev(Y), om, omt, ranks=rk, sweeps=2, precision=precision)
+    two = P.ffcp(t["U"], t["G"], R, **kw)
+    for n in range(3):
+        assert torch.equal(one["A"][n], two["A"][n]), n
+    assert torch.equal(one["lam"], two["lam"])
+    assert np.array_equal(one["fits"], two["fits"])
+    assert one["tucker_info"]["normY2"] == t["info"]["normY2"]
+    if precision == "f32":
+        ref_t = RT.rand_tucker(Y.astype(np.float64),
+                               [synth.f32(o).astype(np.float64) for o in d["omegas"]],
+                               [[synth.f32(o).astype(np.float64) for o in lst]
+                                for lst in d["omega_tildes"]], sweeps=2, ranks=rk)
+        A0 = F.hosvd_init(ref_t["U"], ref_t["G"], R)
+        ref = F.ffcp(ref_t["U"], ref_t["G"], A0, update="als", max_it=40, tol=0.0)
+        np.testing.assert_allclose(one["fits"], ref["fits"], rtol=0, atol=1e-5)
