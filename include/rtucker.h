@@ -280,6 +280,23 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
             double* fit_trace, rt_ffcp_info* info, void* stream);
 
 /*
+ * rt_ffcp without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * rt_ffcp, minus ws / ws_bytes: the scratch is a static 32 MiB array of the
+ * library on each GPU (held until the process ends), so the call allocates
+ * nothing.  Problems whose rt_ffcp_workspace exceeds 32 MiB are rejected
+ * with RT_ERR_UNSUPPORTED before anything is enqueued (R = R_n = 20 needs
+ * about 1.3 MiB at I_n = 1000 in 3 modes and 17.5 MiB at I_n = 10^4 in 4).  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams or
+ * host threads) race and must be serialized by the caller; calls in order on
+ * one stream are safe.  Nothing in the array needs to start at zero.
+ */
+int rt_ffcp_noalloc(const rt_ffcp_desc* desc, const float* const* U, const float* G,
+                    const float* const* A_init, const float* const* pad, float* const* A,
+                    float* lambda, double* fit_trace, rt_ffcp_info* info, void* stream);
+
+/*
  * Algorithm 1 with the dense tensor as its input (the problem statement
  * "ffcp(Y, R)"): RandTucker2i compresses Y exactly as rt_tucker_rand does,
  * then FFCP runs on the Tucker format it returns exactly as rt_ffcp does.

@@ -108,6 +108,9 @@ def lib():
         L.rt_ffcp.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
                               ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
                               ctypes.POINTER(vp), vp, vp, vp, vp]
+        L.rt_ffcp_noalloc.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), vp, vp, vp, vp]
         L.rt_ffcp_dense_workspace.argtypes = [ctypes.POINTER(TuckerDesc),
                                               ctypes.POINTER(FfcpDesc), ctypes.POINTER(sz)]
         L.rt_ffcp_dense.argtypes = [ctypes.POINTER(TuckerDesc), ctypes.POINTER(FfcpDesc), vp,
@@ -134,7 +137,7 @@ def lib():
         L.rt_version.restype = ctypes.c_char_p
         for f in ("rt_tucker_rand_workspace", "rt_tucker_bf16_copy_elems",
                   "rt_tucker_rand", "rt_ffcp_workspace",
-                  "rt_ffcp", "rt_ffcp_dense_workspace", "rt_ffcp_dense", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
+                  "rt_ffcp", "rt_ffcp_noalloc", "rt_ffcp_dense_workspace", "rt_ffcp_dense", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
                   "rt_stream_pass", "rt_profile_enable", "rt_profile_read",
                   "rt_mlp_workspace", "rt_mlp_sync_bf16", "rt_mlp_forward", "rt_mlp_grad",
                   "rt_mlp_train_step"):
@@ -363,6 +366,40 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
                          _ptr(ws), ws.numel(), _ptr_array(A), _ptr(lam), _ptr(ft),
                          _ptr(info), _stream_handle(stream)))
     out = {"A": A, "lam": lam, "info_dev": info, "fit_trace_dev": ft, "workspace": ws}
+    if sync:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]
+        out["info"] = inf
+        if ft is not None:
+            out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
+    return out
+
+
+def ffcp_noalloc(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
+                 tol=1e-6, l1=0.0, normY2=None, fit_trace=False, stream=None, sync=True):
+    """rt_ffcp_noalloc: ffcp with the library's static scratch instead of a
+    workspace (arguments and results as ffcp)."""
+    torch = _torch()
+    N = len(U)
+    dims = [int(u.shape[0]) for u in U]
+    ranks = [int(u.shape[1]) for u in U]
+    if init is None:
+        init = "user" if A_init is not None else "hosvd"
+    desc = ffcp_desc(dims, ranks, R, update, init, max_it, tol, l1, normY2)
+    for n in range(N):
+        _require_device(U[n], f"U[{n}]", torch.float32)
+    _require_device(G, "G", torch.float32)
+    dev = G.device
+    A = [torch.empty((dims[n], R), dtype=torch.float32, device=dev) for n in range(N)]
+    lam = torch.empty(R, dtype=torch.float32, device=dev)
+    info = torch.zeros(FFCP_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ft = torch.zeros(max_it, dtype=torch.float64, device=dev) if fit_trace else None
+    _check(lib().rt_ffcp_noalloc(ctypes.byref(desc), _ptr_array(U), _ptr(G),
+                                 _ptr_array(A_init) if A_init is not None else None,
+                                 _ptr_array(pad) if pad is not None else None,
+                                 _ptr_array(A), _ptr(lam), _ptr(ft), _ptr(info),
+                                 _stream_handle(stream)))
+    out = {"A": A, "lam": lam}
     if sync:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/rtucker.h"
 #include "common.hpp"
@@ -547,6 +548,57 @@ __global__ void hosvd_pad_kernel(const double* W, const float* pad, double* V,
 }  // namespace
 }  // namespace rt
 
+namespace rt {
+namespace {
+
+// ---------------------------------------------------- rt_ffcp_noalloc
+
+// Scratch of rt_ffcp_noalloc: one copy per GPU, loaded with the code object
+// and held until the process ends.  Host code never passes `scratch` itself
+// to a kernel (on the host it is a stand-in, not a device address): it uses
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+}  // namespace rt
+
+static __device__ __align__(256) char scratch[rt::kNoallocScratchBytes];
+
+namespace rt {
+namespace {
+
+// Device address of this device's `scratch`, looked up once per device with
+// that device current.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d outside 0..%d", dev, kMaxDevices - 1);
+    return kErrNoDevice;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) {
+      set_error("hipGetSymbolAddress(scratch) returned NULL");
+      return kErrHip;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return kOk;
+}
+
+}  // namespace
+}  // namespace rt
+
 using namespace rt;
 
 extern "C" {
@@ -886,6 +938,24 @@ int rt_ffcp_dense(const rt_tucker_desc* tdesc, const rt_ffcp_desc* fdesc, const 
                         nullptr, stream));
   return rt_ffcp(fdesc, Uc, p.G, A_init, pad, p.fws, p.fbytes, A, lambda, fit_trace, finfo,
                  stream);
+}
+
+int rt_ffcp_noalloc(const rt_ffcp_desc* desc, const float* const* U, const float* G,
+                    const float* const* A_init, const float* const* pad, float* const* A,
+                    float* lambda, double* fit_trace, rt_ffcp_info* info, void* stream) {
+  RT_TRY(validate_ffcp(desc));
+  FfcpPlan P;
+  const size_t need = P.plan(desc, nullptr);
+  if (need > kNoallocScratchBytes) {
+    set_error("rt_ffcp_noalloc: this problem needs %zu bytes of scratch, above the "
+              "library's static %zu bytes (use rt_ffcp with a workspace)",
+              need, kNoallocScratchBytes);
+    return kErrUnsupported;
+  }
+  void* ws = nullptr;
+  RT_TRY(noalloc_scratch(&ws));
+  return rt_ffcp(desc, U, G, A_init, pad, ws, kNoallocScratchBytes, A, lambda, fit_trace,
+                 info, stream);
 }
 
 int rt_ttm(int32_t dtype, int64_t A, int64_t I, int64_t C, int32_t K,

@@ -211,3 +211,20 @@ def test_ffcp_dense_workspace_and_validation():
                          None, None, vp(1 << 20), n.value, arr, None, None, None, None,
                          None)
     assert rc == -1 and "lambda" in P.last_error()
+
+
+def test_ffcp_noalloc_rejects_oversized_problems_on_the_host():
+    """rt_ffcp_noalloc checks the description and the static scratch's size
+    limit before touching a device."""
+    L = P.lib()
+    vp = ctypes.c_void_p
+    arr = (vp * 4)(*[256 * (i + 1) for i in range(4)])
+    big = P.ffcp_desc([40000] * 4, [20] * 4, 20, "hals")
+    rc = L.rt_ffcp_noalloc(ctypes.byref(big), arr, vp(4096), arr, None, arr, vp(8192),
+                           None, None, None)
+    assert rc == -2 and "scratch" in P.last_error()
+    bad = P.ffcp_desc([30, 40, 50], [5, 6, 7], 4)
+    bad.R = 0
+    rc = L.rt_ffcp_noalloc(ctypes.byref(bad), arr, vp(4096), arr, None, arr, vp(8192),
+                           None, None, None)
+    assert rc == -1
