@@ -97,30 +97,43 @@ def stored_traffic(kernel, workload):
     return float(e["bytes_per_launch"])
 
 
-def cpu_baseline(Y, omegas, omega_tildes, ranks, slab, sweeps, bytes_per_elem):
+def cpu_baseline(Y, omegas, omega_tildes, ranks, slab, sweeps, bytes_per_elem, reps=3):
     """The FP64 oracle (untuned) on Y[:, :, :slab] with Omega_3 rows
     0..slab-1, with the step's number of sweeps; rate in the metric's unit
-    (the step's algorithmic bytes per element x elements / wall time)."""
+    (the step's algorithmic bytes per element x elements / wall time), the
+    median of ``reps`` runs with the BLAS threads pinned to the process's
+    CPU affinity set.  Also returns the oracle's last result."""
     from oracle import randtucker as RT
+    cores = len(os.sched_getaffinity(0))
+    limiter = None
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # threadpoolctl missing: report the affinity set
-        threads = len(os.sched_getaffinity(0))
-    Ys = Y[:, :, :slab].cpu().numpy().astype(np.float64)
-    om = [o.astype(np.float64) for o in omegas]
-    om[2] = om[2][:slab]
-    omt = [[o.astype(np.float64) for o in lst] for lst in omega_tildes[:sweeps]]
-    t0 = time.perf_counter()
-    RT.rand_tucker(Ys, om, omt, sweeps=sweeps, ranks=ranks)
-    dt = time.perf_counter() - t0
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=cores, user_api="blas")
+    except Exception:  # threadpoolctl missing: BLAS keeps its own count
+        pass
+    try:
+        Ys = Y[:, :, :slab].cpu().numpy().astype(np.float64)
+        om = [o.astype(np.float64) for o in omegas]
+        om[2] = om[2][:slab]
+        omt = [[o.astype(np.float64) for o in lst] for lst in omega_tildes[:sweeps]]
+        times, res = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = RT.rand_tucker(Ys, om, omt, sweeps=sweeps, ranks=ranks)
+            times.append(time.perf_counter() - t0)
+    finally:
+        if limiter is not None:
+            limiter.unregister()
+    dt = float(np.median(times))
     nbytes = bytes_per_elem * Ys.size
     where = ("the whole tensor" if slab >= Y.shape[2] else
              f"the {Ys.shape[0]}x{Ys.shape[1]}x{slab} mode-3 slab of the tensor")
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(threads),
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(cores),
             "kind": "oracle",
             "sample": (f"RandTucker2i S={sweeps} (sketches, QR, core, truncation) "
-                       f"in FP64 NumPy on {where}, {dt:.2f} s")}
+                       f"in FP64 NumPy on {where}; median of {reps} runs "
+                       f"({', '.join(f'{t:.2f}' for t in times)} s), BLAS threads "
+                       f"pinned to the {cores} CPUs of the affinity set")}, res, Ys
 
 
 def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
@@ -175,6 +188,8 @@ def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
         "converged": int(finfo["converged"]), "fit_core": float(finfo["fit"]),
         "init_used": int(finfo["init_used"]),
         "fit_y": float(fit_y), "normY2": float(tinfo["normY2"]),
+        "U": [u.double().cpu().numpy() for u in out["U"]],
+        "G": out["G"].double().cpu().numpy(),
     }
 
 
@@ -272,10 +287,72 @@ def train_learned_init(P, torch, synth, cores, epochs, I=300, R=20, rt=30):
         first = m if first is None else first
         last = m
     torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # matrix-product work of one sample: forward x W1..W3, backward dX and dW
+    # of each layer (3 products of 2 d_l d_{l+1} flop per layer)
+    dims = net.dims
+    per_sample = 3 * sum(2.0 * dims[l] * dims[l + 1] for l in range(3))
+    samples = net.step * 256
     return net, {"cores": cores, "core_tensor": f"{I}^3 CP rank {R}", "epochs": epochs,
-                 "steps": net.step, "generate_s": round(t_gen, 2),
-                 "train_s": round(time.perf_counter() - t0, 2),
+                 "steps": net.step, "batch": 256, "generate_s": round(t_gen, 2),
+                 "train_s": round(train_s, 3),
+                 "train_tflops": round(per_sample * samples / train_s / 1e12, 2),
+                 "train_mfma_frac_bf16": round(per_sample * samples / train_s / 1e12 /
+                                               PEAK_TFLOPS["bf16"], 5),
                  "loss_first_epoch": round(first, 5), "loss_last_epoch": round(last, 5)}
+
+
+def bf16_rounding_rms(Y):
+    """RMS of bf16_rne(Y) - Y (torch's round-to-nearest-even conversion),
+    mode-1 slab by slab."""
+    import torch
+    e2 = 0.0
+    for a in range(0, Y.shape[0], 100):
+        blk = Y[a:a + 100]
+        e2 += float(((blk.to(torch.bfloat16).to(torch.float32) - blk).double() ** 2).sum())
+    return (e2 / Y.numel()) ** 0.5
+
+
+def errors_vs_oracle(res, forms, ores, Y64, R, tol, max_it, rms_bf16=None):
+    """Error of each form's Tucker format and final fit against the FP64
+    oracle on the whole tensor (same Omega): projector distance of each U_n,
+    the aligned core error e_G, and |Fit_Y - Fit_Y(oracle)| where the oracle
+    fits its own core by FFCP-ALS from its HOSVD start to the same tolerance
+    and Fit_Y is evaluated against the tensor."""
+    from oracle import ffcp as F
+    from oracle.metrics import aligned_core_error, projector_distance
+    A0 = F.hosvd_init(ores["U"], ores["G"], R)
+    f = F.ffcp(ores["U"], ores["G"], A0, update="als", max_it=max_it, tol=tol)
+    fit_o = F.cp_fit_mttkrp(Y64, f["A"], f["lam"])
+    out = {"oracle_fit_y": fit_o, "oracle_ffcp_iterations": int(f["iterations"])}
+    for form in ("bf16", "f32", "f32_one_sweep"):
+        if form not in res or forms[form][1] != 2:
+            continue
+        r = res[form]
+        d = [projector_distance(r["U"][k], ores["U"][k]) for k in range(len(r["U"]))]
+        eG = aligned_core_error(r["G"], r["U"], ores["G"], ores["U"])
+        out[form] = {"d_U_max": max(d), "e_G": eG,
+                     "fit_y_abs_diff": abs(r["fit_y"] - fit_o)}
+    out["bounds"] = {"f32": {"d_U": 1e-4, "e_G": 1e-4, "fit_y": 1e-5},
+                     "bf16": {"fit_y": 1e-4}}
+    if rms_bf16 is not None:
+        # Wedin: d_n <= s_n / (gap_n - s_n), gap_n from the oracle's G~_(n),
+        # s_n = rms(E) (sqrt(I_n) + sqrt(prod_{p != n} I_p)) the norm of the
+        # BF16 rounding unfolded; the reported bound is twice the estimate
+        Gt = ores["Gt"]
+        est = []
+        for k in range(Gt.ndim):
+            sv = np.linalg.svd(np.moveaxis(Gt, k, 0).reshape(Gt.shape[k], -1),
+                               compute_uv=False)
+            gap = sv[R - 1] - sv[R]
+            In = Y64.shape[k]
+            s_n = rms_bf16 * (In ** 0.5 + (Y64.size / In) ** 0.5)
+            est.append(s_n / (gap - s_n) if gap > s_n else float("inf"))
+        out["bounds"]["bf16"]["d_U"] = 2.0 * max(est)
+        out["bounds"]["bf16"]["e_G"] = 2.0 * float(np.sqrt(np.sum(np.square(est)))) + 2.0 ** -9
+        out["bounds"]["bf16"]["wedin_estimates"] = est
+        out["bounds"]["bf16"]["rounding_rms"] = rms_bf16
+    return out
 
 
 def main():
@@ -316,9 +393,11 @@ def main():
     # (precision, sweeps, learned start).  The plain FP32 path runs the same
     # two sweeps as the precision form, so both reach the same subspaces and
     # the same fit; one FP32 sweep is timed as well, for context (on this
-    # workload its subspaces, and so its fit, are clearly worse).
-    forms = {"bf16": ("bf16", 2, True), "f32": ("f32", 2, False),
-             "f32_one_sweep": ("f32", 1, False)}
+    # workload its subspaces, and so its fit, are clearly worse).  The
+    # precision form from the HOSVD start isolates what the learned start
+    # gains.
+    forms = {"bf16": ("bf16", 2, True), "bf16_hosvd": ("bf16", 2, False),
+             "f32": ("f32", 2, False), "f32_one_sweep": ("f32", 1, False)}
     main_form = args.precision
     order = [f for f in forms if f != main_form] + [main_form]   # the step's form last
     res = {}
@@ -341,11 +420,18 @@ def main():
 
     value = alg_bytes(main_form) / (m["tucker_ms"] * 1e-3) / 1e9
 
-    # dominant kernel: the first sweep's streaming kernel (the plain path)
-    ms_k, n_k = m["prof"]["first_pass"]
-    t_k = ms_k / max(n_k, 1) * 1e-3
+    # The dominant contraction kernel: the first sweep's streaming kernel
+    # (two mode products in one read of Y).  Every Y-streaming kernel of the
+    # step's form is priced beside it.
     workload = f"cp{R}_congruent_{I}x{I}x{I}_f32"
+
+    def per_launch(stage):
+        ms_k, n_k = m["prof"].get(stage, (0.0, 0))
+        return ms_k / max(n_k, 1) * 1e-3 if n_k else None
+
+    kernels = {}
     if main_form == "f32":
+        t_k = per_launch("first_pass")
         flops = 2.0 * n * (rt + rt)   # Y x_3 Omega_3^T and Y x_2 Omega_2^T
         achieved = flops / t_k / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2),
@@ -355,26 +441,33 @@ def main():
                 "kernel": "dual_f32_kernel (first sweep: Y x_3 Omega_3^T and "
                           "Y x_2 Omega_2^T in one read of Y)",
                 "avg_ms": round(t_k * 1e3, 4)}
+        for stage, b in (("first_pass", 4), ("sweep_pass", 4), ("core_pass", 4)):
+            t = per_launch(stage)
+            if t:
+                kernels[stage] = {"bytes": b * n, "avg_ms": round(t * 1e3, 4),
+                                  "gbs": round(b * n / t / 1e9, 1),
+                                  "hbm_frac": round(b * n / t / 1e9 / HBM_PEAK_GBS, 4)}
     else:
-        # the longer of the precision form's two first-sweep kernels: the
-        # FP32 -> BF16 conversion (reads 4 B, writes 2 B per element) and the
-        # dual contraction on the BF16 copy (reads 2 B per element)
-        ms_c, n_c = m["prof"]["convert"]
-        t_c = ms_c / max(n_c, 1) * 1e-3
-        if t_c >= t_k:
-            t_k, kbytes, kname = t_c, (4 + 2) * n, "bf16_convert_kernel"
-            kdesc = ("bf16_convert_kernel (first sweep: FP32 read, scaled BF16 "
-                     "copy written)")
-        else:
-            kbytes, kname = 2 * n, "bf16_stream_kernel"
-            kdesc = ("bf16_stream_kernel<true,false,4> (first sweep: Y x_3 "
-                     "Omega_3^T and Y x_2 Omega_2^T from the BF16 copy)")
+        t_k = per_launch("first_pass")
+        kbytes = 2 * n
         achieved = kbytes / t_k / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(kname, workload),
-                "kernel": kdesc, "avg_ms": round(t_k * 1e3, 4)}
+                "traffic": stored_traffic("bf16_stream_kernel", workload),
+                "kernel": ("bf16_stream_kernel (first sweep: Y x_3 Omega_3^T and "
+                           "Y x_2 Omega_2^T from the BF16 copy, one read)"),
+                "avg_ms": round(t_k * 1e3, 4)}
+        for stage, b, kname in (("convert", 6, "bf16_convert_kernel (FP32 read, BF16 write)"),
+                                ("first_pass", 2, "bf16_stream_kernel, first sweep"),
+                                ("sweep_pass", 2, "bf16_stream_kernel, power sweep"),
+                                ("core_pass", 2, "bf16_stream_kernel, core pass")):
+            t = per_launch(stage)
+            if t:
+                kernels[stage] = {"kernel": kname, "bytes": b * n,
+                                  "avg_ms": round(t * 1e3, 4),
+                                  "gbs": round(b * n / t / 1e9, 1),
+                                  "hbm_frac": round(b * n / t / 1e9 / HBM_PEAK_GBS, 4)}
 
     if args.copy_calibration:
         # plain elementwise copy kernel of known traffic (reads 4 B, writes
@@ -387,10 +480,14 @@ def main():
 
     hals = None if args.no_hals else run_hals_1e4(P, torch, synth, 3)
 
-    cpu = None
+    cpu, errors = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab, forms[main_form][1],
-                           alg_bytes(main_form) // n)
+        cpu, ores, Ys = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab,
+                                     forms[main_form][1], alg_bytes(main_form) // n)
+        if args.cpu_slab >= I:
+            errors = errors_vs_oracle(res, forms, ores, Ys, R, args.tol, args.max_it,
+                                      bf16_rounding_rms(Y))
+        del Ys
 
     def summary(form):
         r = res[form]
@@ -439,6 +536,17 @@ def main():
         "time_to_fit_mixed_over_plain": round(
             (res["bf16"]["tucker_ms"] + res["bf16"]["init_ms"] + res["bf16"]["ffcp_ms"]) /
             (res["f32"]["tucker_ms"] + res["f32"]["init_ms"] + res["f32"]["ffcp_ms"]), 4),
+        "learned_gain": {
+            "ffcp_iterations_learned": res["bf16"]["iterations"],
+            "ffcp_iterations_hosvd": res["bf16_hosvd"]["iterations"],
+            "ffcp_ms_learned_incl_inference": round(res["bf16"]["init_ms"] +
+                                                    res["bf16"]["ffcp_ms"], 4),
+            "ffcp_ms_hosvd": round(res["bf16_hosvd"]["init_ms"] +
+                                   res["bf16_hosvd"]["ffcp_ms"], 4),
+            "note": "both arms: precision form, two sweeps, same tensor; the learned "
+                    "arm includes the network's inference and the HOSVD guard"},
+        "errors_vs_fp64_oracle": errors,
+        "kernels": kernels,
         "learned_init": learned,
         "hals_1e4_4way": hals,
         "normY2": m["normY2"],

@@ -4,40 +4,46 @@ factors with exactly 20 % zeros, |N(0, 0.01)| noise; the Section V-A
 construction), compressed by the precision form (two sweeps, Omega_n
 200 x 25, Omega~_n 15625 x 25, Tucker ranks 15) and factored by FFCP-HALS.
 
-The streaming view is [A = 40000 slabs, 200, 200]: the fused conversion runs
-40000 slab rows of blocks, and the contraction kernels take one 32-row block
-per wavefront.
+The streaming view is [A = 40000 slabs, 200, 200]: the conversion runs
+40000 x 5 blocks in one dimension, the contraction kernels one slab per
+workgroup.
 
-As at 1000^3 the oracle cannot run the whole method at this size, so:
+Checked on the whole tensor, in FP64 on the host:
 
-* sampled rows of the first sweep's sketches Z_1 and Z_4 (the sketch step of
-  Alg. 3 with the first test matrix), each from one 200^3 slice of Y, in
-  FP64 on the operands the path multiplies: the BF16 copy and the BF16
-  factor in the streamed contraction (mode 4 for Z_1, mode 3 for Z_4), the
-  FP32 values elsewhere;
-* ||Y||^2 as the plain FP64 sum of squares;
-* properties that hold at any size: orthonormal U_n and sweep-1 bases, the
-  Pythagoras bound ||G|| <= ||Y||, and FFCP-HALS's non-decreasing fit with
-  nonnegative factors.
+* the first sweep's sketches Z_n element-wise, recomputed from the operands
+  the path multiplies (Y and the streamed test matrix rounded to BF16 here,
+  independently of the library; every slab's exponent is 0, checked).  Each
+  entry sums 8e6 products accumulated in FP32 in stages of 200 (streamed
+  contraction), 200 and 200 (the other two modes) and the split sketch
+  product: 1e-4 of max |Z_n| as at 1000^3;
+* the second sweep's sketches and the core, recomputed from the bases the
+  library returned (the same bound);
+* ||Y||^2 as the plain FP64 sum of squares; orthonormal bases.
 
-Tolerance of the sketch rows (norm-wise relative) 1e-4, from the same count
-as at 1000^3: each entry sums 8e6 products accumulated in FP32 in stages of
-200 (streamed contraction), 200 and 200 (the other two modes) and the split
-sketch product.
+Against the FP64 oracle: both sides run the whole method (precision form on
+the device, FP64 on the host, same Omega with Omega_1's first 40 rows) on the
+mode-1 slab Y[0:40] (3.2e8 entries); the subspaces within twice the Wedin
+estimate of the BF16 rounding (as at 1000^3).  FFCP-HALS on the full tensor's
+Tucker format: non-decreasing fit, nonnegative factors.
 """
 
 import numpy as np
 import pytest
 
 import synth
+from oracle import randtucker as RT
+from oracle.metrics import aligned_core_error, projector_distance
+
+from _fullsize import bf16_round, dev64, maxrel, path_core, path_sketches
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-I, R, RT, RN = 200, 15, 25, 15
+I, R, RT_, RN, N = 200, 15, 25, 15, 4
 DIMS = (I, I, I, I)
-ROWS = (0, 97, 199)
+TOL_Z = 1e-4
+SLAB = 40
 
 
 @pytest.fixture(scope="module")
@@ -51,7 +57,7 @@ def P():
 @pytest.fixture(scope="module")
 def work():
     dev = torch.device("cuda:0")
-    d = synth.nonneg_cp_device(1886, DIMS, R, (RT,) * 4, sweeps=2, device=dev)
+    d = synth.nonneg_cp_device(1886, DIMS, R, (RT_,) * 4, sweeps=2, device=dev)
     om32 = synth.f32(d["omegas"])
     omt32 = [synth.f32(x) for x in d["omega_tildes"]]
     A0 = [synth.f32(a) for a in synth.init_factors(d["init_rng"], DIMS, R, nonneg=True)]
@@ -61,14 +67,15 @@ def work():
             "omt_d": [[torch.from_numpy(o).to(dev) for o in lst] for lst in omt32]}
 
 
-def bf16_round(x):
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
-    return r.view(np.float32).astype(np.float64)
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+def host_bf16(Y, rows=10):
+    out = np.empty(tuple(Y.shape), dtype=np.float64)
+    n2 = 0.0
+    for a in range(0, Y.shape[0], rows):
+        blk = Y[a:a + rows].cpu().numpy()
+        b64 = blk.astype(np.float64)
+        n2 += float(np.sum(b64 * b64))
+        out[a:a + rows] = bf16_round(blk)
+    return out, n2
 
 
 def test_fullsize_4way_precision_form_and_hals(P, work):
@@ -76,39 +83,33 @@ def test_fullsize_4way_precision_form_and_hals(P, work):
     out = P.tucker_rand(w["Y"], w["om_d"], w["omt_d"], ranks=(RN,) * 4, sweeps=2,
                         precision="bf16", trace=True)
     torch.cuda.synchronize()
+    mx = float(w["Y"].abs().max())
+    assert 0.0 < mx and np.frexp(mx)[1] - 1 <= 100
+    assert float(w["Y"].reshape(I * I, -1).abs().amax(dim=1).min()) >= 2.0 ** -100
+    Yb, n2 = host_bf16(w["Y"])
     om = [o.astype(np.float64) for o in w["om32"]]
-    omt = [o.astype(np.float64) for o in w["omt32"][0]]
-    Z1 = out["trace"]["Z"][0].cpu().numpy().astype(np.float64)
-    Z4 = out["trace"]["Z"][3].cpu().numpy().astype(np.float64)
-    o3b, o4b = bf16_round(w["om32"][2]), bf16_round(w["om32"][3])
-    for i in ROWS:
-        # Z_1 row i: Y[i] (modes 2, 3, 4); mode 4 streamed in BF16
-        S = bf16_round(w["Y"][i].cpu().numpy())
-        X = np.tensordot(S, o4b, axes=([2], [0]))             # j2, j3, k4
-        X = np.tensordot(X, om[2], axes=([1], [0]))           # j2, k4, k3
-        X = np.tensordot(om[1], X, axes=([0], [0]))           # k2, k4, k3
-        X = X.transpose(0, 2, 1)                              # k2, k3, k4
-        assert rel(Z1[i], X.reshape(-1) @ omt[0]) <= 1e-4, ("Z_1", i)
-        # Z_4 row i: Y[..., i] (modes 1, 2, 3); mode 3 streamed in BF16
-        S = bf16_round(w["Y"][:, :, :, i].contiguous().cpu().numpy())
-        X = np.tensordot(S, o3b, axes=([2], [0]))             # j1, j2, k3
-        X = np.tensordot(X, om[1], axes=([1], [0]))           # j1, k3, k2
-        X = np.tensordot(om[0], X, axes=([0], [0]))           # k1, k3, k2
-        X = X.transpose(0, 2, 1)                              # k1, k2, k3
-        assert rel(Z4[i], X.reshape(-1) @ omt[3]) <= 1e-4, ("Z_4", i)
-    for n in range(4):
-        U = out["U"][n].cpu().numpy().astype(np.float64)
+    Zx = path_sketches(Yb, om, [o.astype(np.float64) for o in w["omt32"][0]], bf16=True)
+    for n in range(N):
+        e = maxrel(dev64(out["trace"]["Z"][n]), Zx[n])
+        assert e <= TOL_Z, ("sweep-1 Z vs exact-input FP64", n, e)
+    del Zx
+    Q1 = [dev64(out["trace"]["Q"][n]) for n in range(N)]
+    Q2 = [dev64(out["trace"]["Q"][N + n]) for n in range(N)]
+    Zp = path_sketches(Yb, Q1, [o.astype(np.float64) for o in w["omt32"][1]], bf16=True)
+    for n in range(N):
+        e = maxrel(dev64(out["trace"]["Z"][N + n]), Zp[n])
+        assert e <= TOL_Z, ("sweep-2 Z from the returned bases", n, e)
+    del Zp
+    e = maxrel(dev64(out["trace"]["Gt"]), path_core(Yb, Q2, bf16=True))
+    assert e <= TOL_Z, ("core from the returned bases", e)
+    del Yb
+    for n in range(N):
+        U = dev64(out["U"][n])
         assert np.linalg.norm(U.T @ U - np.eye(RN)) <= 1e-5, n
-        Q = out["trace"]["Q"][n].cpu().numpy().astype(np.float64)
-        assert np.linalg.norm(Q.T @ Q - np.eye(RT)) <= 1e-5, n
-    n2 = 0.0
-    for a0 in range(0, I, 10):
-        blk = w["Y"][a0:a0 + 10].cpu().numpy().astype(np.float64)
-        n2 += float(np.sum(blk * blk))
+        for q in (Q1[n], Q2[n]):
+            assert np.linalg.norm(q.T @ q - np.eye(RT_)) <= 1e-5, n
     assert abs(out["info"]["normY2"] - n2) <= 1e-9 * n2
     assert out["info"]["nonfinite"] == 0
-    G = out["G"].cpu().numpy().astype(np.float64)
-    assert float(np.sum(G * G)) <= n2 * (1 + 1e-5)
 
     # FFCP-HALS (nonnegative) on the Tucker format, from U[0,1] factors
     f = P.ffcp(out["U"], out["G"], R, update="hals",
@@ -122,5 +123,39 @@ def test_fullsize_4way_precision_form_and_hals(P, work):
     # for this model at 40^4); a rank-15 nonnegative fit from a random start
     # reaches most of that
     assert 0.9 < fits[-1] < 0.99
-    for n in range(4):
+    for n in range(N):
         assert float(f["A"][n].min()) >= 0.0, n
+
+
+def test_slab_precision_form_vs_fp64_oracle(P, work):
+    """The whole method on Y[0:40] on both sides (a fresh device call on the
+    slab): d(U_n) within twice the Wedin estimate of the BF16 rounding, e_G
+    within twice their root-sum-square plus 2^-9."""
+    w = work
+    Ys = w["Y"][:SLAB].contiguous()
+    om_d = [w["om_d"][0][:SLAB].contiguous()] + w["om_d"][1:]
+    out = P.tucker_rand(Ys, om_d, w["omt_d"], ranks=(RN,) * 4, sweeps=2,
+                        precision="bf16")
+    Y64 = Ys.double().cpu().numpy()
+    Yb = bf16_round(Ys.cpu().numpy())
+    om = [o.astype(np.float64) for o in w["om32"]]
+    om[0] = om[0][:SLAB]
+    omt = [[o.astype(np.float64) for o in lst] for lst in w["omt32"]]
+    tk = RT.rand_tucker(Y64, om, omt, sweeps=2, ranks=(RN,) * 4)
+    rms = float(np.sqrt(np.mean((Yb - Y64) ** 2)))
+    del Yb, Y64
+    U = [dev64(u) for u in out["U"]]
+    d = [projector_distance(U[n], tk["U"][n]) for n in range(N)]
+    eG = aligned_core_error(dev64(out["G"]), U, tk["G"], tk["U"])
+    dims = Ys.shape
+    total = float(np.prod(dims))
+    bound = []
+    for n in range(N):
+        sv = np.linalg.svd(np.moveaxis(tk["Gt"], n, 0).reshape(RT_, -1), compute_uv=False)
+        gap = sv[RN - 1] - sv[RN]
+        s_n = rms * (np.sqrt(dims[n]) + np.sqrt(total / dims[n]))
+        bound.append(s_n / (gap - s_n) if gap > s_n else np.inf)
+    print(f"slab: d(U_n) {d}, e_G {eG}, Wedin estimates {bound}", flush=True)
+    for n in range(N):
+        assert d[n] <= 2.0 * bound[n], (n, d[n], bound[n])
+    assert eG <= 2.0 * float(np.sqrt(np.sum(np.square(bound)))) + 2.0 ** -9, (eG, bound)
