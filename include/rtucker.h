@@ -74,8 +74,11 @@ typedef enum {
 #define RT_FLAG_BF16_INPUT 0x2u  /* RT_BF16_MIXED only: Y already holds the
                                     BF16 copy (uint16 bit patterns); no FP32
                                     pass and no conversion                  */
-#define RT_FLAG_GAUSS_SEIDEL 0x4u /* reserved: paper-literal loop order;
-                                     currently RT_ERR_UNSUPPORTED           */
+#define RT_FLAG_GAUSS_SEIDEL 0x4u /* the loop order of Algorithm 3 as
+                                     printed: mode n's sketch uses the bases
+                                     modes < n received in the same sweep
+                                     (two passes over Y per sweep instead of
+                                     one)                                   */
 
 /*
  * Problem description of rt_tucker_rand.
@@ -142,7 +145,8 @@ int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems);
  *
  * For each sweep s = 1..sweeps and every mode n (Jacobi order: every mode of
  * a sweep uses the bases of the previous sweep; sweep 1 uses Omega_p, the
- * random initial U^(p) that Algorithm 3 starts from):
+ * random initial U^(p) that Algorithm 3 starts from; with
+ * RT_FLAG_GAUSS_SEIDEL the modes p < n use the bases of the current sweep):
  *     X_n = Y x_{p != n} B_p^T,    Z_n = X_(n) Omega~_n^(s),
  *     Q_n = orth(Z_n)   (FP64 Householder QR, signs so that diag(R) >= 0)
  * then the core G~ = Y x_1 Q_1^T ... x_N Q_N^T (the core projection of Algorithm 3) and,
@@ -177,7 +181,8 @@ int rt_tucker_bf16_copy_elems(const rt_tucker_desc* desc, int64_t* elems);
  *   stream     hipStream_t.
  * Errors: RT_ERR_INVALID_ARG (bad description, NULL required pointer,
  * misalignment), RT_ERR_WORKSPACE (ws_bytes too small), RT_ERR_UNSUPPORTED
- * (flag not implemented), RT_ERR_HIP (a launch failed).
+ * (a shape the precision form's kernels do not take), RT_ERR_HIP (a launch
+ * failed).
  */
 int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
                    const void* const* Omega, const void* const* Omega_t,

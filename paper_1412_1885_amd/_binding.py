@@ -205,13 +205,16 @@ def _workspace(nbytes, device):
 # --------------------------------------------------------------- entry points
 
 def tucker_desc(dims, ranks_tilde, ranks=None, sweeps=1, precision="f32",
-                truncate=True, bf16_input=False):
+                truncate=True, bf16_input=False, order="jacobi"):
+    if order not in ("jacobi", "gauss_seidel"):
+        raise ValueError(f"order must be 'jacobi' or 'gauss_seidel', not {order!r}")
     d = TuckerDesc()
     d.N = len(dims)
     d.sweeps = sweeps
     d.precision = PRECISIONS[precision]
     d.flags = (0 if truncate else RT_FLAG_NO_TRUNCATE) | \
-        (RT_FLAG_BF16_INPUT if bf16_input else 0)
+        (RT_FLAG_BF16_INPUT if bf16_input else 0) | \
+        (RT_FLAG_GAUSS_SEIDEL if order == "gauss_seidel" else 0)
     for n, I in enumerate(dims):
         d.dims[n] = int(I)
         d.ranks_tilde[n] = int(ranks_tilde[n])
@@ -241,7 +244,7 @@ def bf16_copy_shape(dims, ranks_tilde=None):
 def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
                 truncate=True, trace=False, ybf16=None, bf16_input=False,
                 dims=None, workspace=None, stream=None, sync=True,
-                check_finite=True):
+                check_finite=True, order="jacobi"):
     """rt_tucker_rand.  Y: device tensor (float32 / float64, or int16/uint16
     BF16 bit patterns with bf16_input).  omegas: N device matrices I_n x R~_n.
     omega_tildes: list over sweeps of N device matrices.  Returns a dict with
@@ -251,7 +254,7 @@ def tucker_rand(Y, omegas, omega_tildes, ranks=None, sweeps=1, precision="f32",
     dims = list(Y.shape) if dims is None else list(dims)
     N = len(dims)
     rt = [int(o.shape[1]) for o in omegas]
-    desc = tucker_desc(dims, rt, ranks, sweeps, precision, truncate, bf16_input)
+    desc = tucker_desc(dims, rt, ranks, sweeps, precision, truncate, bf16_input, order)
     fdt = torch.float64 if precision == "f64" else torch.float32
     _require_device(Y, "Y")
     for n in range(N):

@@ -70,10 +70,6 @@ int validate_tucker(const rt_tucker_desc* d) {
     set_error("unknown flag bits 0x%x", d->flags);
     return kErrInvalid;
   }
-  if (d->flags & RT_FLAG_GAUSS_SEIDEL) {
-    set_error("Gauss-Seidel sweep order is not implemented");
-    return kErrUnsupported;
-  }
   if ((d->flags & RT_FLAG_BF16_INPUT) && d->precision != RT_BF16_MIXED) {
     set_error("RT_FLAG_BF16_INPUT requires RT_BF16_MIXED");
     return kErrInvalid;
@@ -299,29 +295,61 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
   StreamCtx sc = make_stream_ctx(d, Yv, Ybf16, P.stream_ws, P.stream_bytes,
                                  P.scal + 0, P.iflags + 0);
 
-  for (int sw = 0; sw < d->sweeps; ++sw) {
-    // streamed pass: TA = Y x_last B_last^T, TB = Y x_second B_second^T
-    RT_TRY(stream_dual<T>(sc, sw, B[last], P.K[last], B[second], P.K[second], P.TA,
-                          P.TB, s));
-    {
-      ProfScope ps(kStageContract, s);
-      for (int n = 0; n < N; ++n)
-        RT_TRY(sketch_from_intermediate<T>(P, n, B,
-                                           static_cast<const T*>(Omt[sw * N + n]), s));
+  // QR of the sketches of modes n0..n1-1 into Q (one batched launch)
+  auto qr_modes = [&](int n0, int n1) {
+    ProfScope ps(kStageQr, s);
+    QrBatch qb{};
+    qb.nb = n1 - n0;
+    qb.bit0 = n0;
+    qb.need = P.iflags + 4;
+    for (int n = n0; n < n1; ++n) {
+      qb.Z[n - n0] = P.Z[n];
+      qb.Q[n - n0] = P.Q[n];
+      qb.work[n - n0] = P.qrwork[n];
+      qb.I[n - n0] = P.I[n];
+      qb.K[n - n0] = P.K[n];
     }
-    {
-      ProfScope ps(kStageQr, s);
-      QrBatch qb{};
-      qb.nb = N;
-      qb.need = P.iflags + 4;
-      for (int n = 0; n < N; ++n) {
-        qb.Z[n] = P.Z[n];
-        qb.Q[n] = P.Q[n];
-        qb.work[n] = P.qrwork[n];
-        qb.I[n] = P.I[n];
-        qb.K[n] = P.K[n];
+    return launch_qr<T>(qb, P.iflags + 1, s);
+  };
+  const bool gauss_seidel = (d->flags & RT_FLAG_GAUSS_SEIDEL) != 0;
+  int pass = 0;   // streamed passes so far (the first one converts / takes ||Y||^2)
+
+  for (int sw = 0; sw < d->sweeps; ++sw) {
+    const T* const* Omt_s = reinterpret_cast<const T* const*>(Omt) + sw * N;
+    if (!gauss_seidel) {
+      // Jacobi: one streamed pass, TA = Y x_last B_last^T and
+      // TB = Y x_second B_second^T, serves every mode of the sweep
+      RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
+                            P.TB, s));
+      {
+        ProfScope ps(kStageContract, s);
+        for (int n = 0; n < N; ++n) RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], s));
       }
-      RT_TRY(launch_qr<T>(qb, P.iflags + 1, s));
+      RT_TRY(qr_modes(0, N));
+    } else {
+      // Gauss-Seidel (the loop of Algorithm 3 as printed): mode n's sketch
+      // uses the bases modes < n received in this sweep.  Modes < N-1 are
+      // reached from TA = Y x_last B_last^T, which only mode N-1 changes, so
+      // one pass serves them one after the other; mode N-1 needs
+      // TB = Y x_second Q_second^T with the new basis of mode N-2: a second
+      // pass (its TA is not used).
+      RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
+                            P.TB, s));
+      for (int n = 0; n < last; ++n) {
+        {
+          ProfScope ps(kStageContract, s);
+          RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], s));
+        }
+        RT_TRY(qr_modes(n, n + 1));
+        B[n] = P.Q[n];
+      }
+      RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
+                            P.TB, s));
+      {
+        ProfScope ps(kStageContract, s);
+        RT_TRY(sketch_from_intermediate<T>(P, last, B, Omt_s[last], s));
+      }
+      RT_TRY(qr_modes(last, N));
     }
     if (trace) {
       for (int n = 0; n < N; ++n) {
@@ -340,7 +368,7 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
   }
 
   // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first, then the rest
-  RT_TRY(stream_single<T>(sc, d->sweeps, B[last], P.K[last], P.TA, s));
+  RT_TRY(stream_single<T>(sc, pass, B[last], P.K[last], P.TA, s));
   {
     ProfScope ps(kStageContract, s);
     int64_t D[RT_MAX_MODES];

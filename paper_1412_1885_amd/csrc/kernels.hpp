@@ -95,6 +95,7 @@ struct QrBatch {
   int K[16];
   int nb;
   int32_t* need;  // per-matrix flag: CholeskyQR2 failed, Householder ran
+  int bit0;       // matrix m reports rank deficiency as bit bit0 + m
 };
 template <typename T>
 int launch_qr(const QrBatch& b, int32_t* rank_flag, hipStream_t s);

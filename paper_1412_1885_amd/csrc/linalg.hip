@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kQrThreads) void householder_kernel(
       rdiag[j] = beta;
       sc[0] = scale;
       W[j * I + j] = beta;
-      if (beta == 0.0 && rank_flag) atomicOr(rank_flag, 1 << m);
+      if (beta == 0.0 && rank_flag) atomicOr(rank_flag, 1 << (b.bit0 + m));
     }
     __syncthreads();
     const double scale = sc[0];

@@ -283,6 +283,46 @@ def nonneg_cp_device(case, dims, R, ranks_tilde, zero_frac=0.2, noise_sigma=0.01
             "init_rng": g["init"]}
 
 
+def tucker_device(case, dims, ranks, snr_db, ranks_tilde, sweeps=2, device="cuda"):
+    """The Tucker-model workload of ``case_tucker`` (N(0,1) core, orthonormal
+    random factors, Gaussian noise at an exact SNR) built in device memory:
+    core, factors and the method's randoms from the same seeded numpy
+    streams; Y* = G x_1 U_1 ... x_N U_N formed in FP64 by torch, one mode
+    product at a time (mode-n unfolding times U_n^T); the noise from torch's
+    generator seeded with the case's noise stream and scaled to the exact
+    SNR; the sum rounded once to FP32."""
+    import torch
+    g = rngs(case)
+    G = g["factors"].standard_normal(tuple(ranks))
+    U = orthonormal_factors(g["factors"], dims, ranks)
+    om = omegas(g["omega"], dims, ranks_tilde)
+    omt = [omega_tildes(g["omega_t1"], ranks_tilde)]
+    if sweeps >= 2:
+        omt.append(omega_tildes(g["omega_t2"], ranks_tilde))
+    noise_seed = int(g["noise"].integers(0, 2**62))
+    X = torch.from_numpy(G).to(device)
+    for n, u in enumerate(U):
+        Ut = torch.from_numpy(u).to(device)                   # I_n x R_n
+        X = torch.movedim(torch.tensordot(X, Ut, dims=([n], [1])), -1, n).contiguous()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(noise_seed)
+    Xf = X.reshape(X.shape[0], -1)
+    e2 = 0.0
+    for r0 in range(0, Xf.shape[0], 8):        # the noise's norm, then its scale
+        e2 += float(torch.randn(Xf[r0:r0 + 8].shape, dtype=torch.float64, device=device,
+                                generator=gen).pow_(2).sum())
+    s = (float((Xf * Xf).sum()) / (e2 * 10.0 ** (snr_db / 10.0))) ** 0.5
+    gen.manual_seed(noise_seed)
+    for r0 in range(0, Xf.shape[0], 8):        # the same noise again, added
+        blk = Xf[r0:r0 + 8]
+        blk.add_(torch.randn(blk.shape, dtype=torch.float64, device=device,
+                             generator=gen).mul_(s))
+    Y32 = X.to(torch.float32)
+    del X, Xf
+    return {"Y": Y32, "G_true": G, "U_true": U, "omegas": om, "omega_tildes": omt,
+            "init_rng": g["init"]}
+
+
 def mlp_weights(case, dims):
     """He-initialized weights of the learned initializer: W_l ~ N(0, 2/fan_in)
     (d_l x d_{l+1}), zero biases; FP32 values (returned as float32 arrays)."""

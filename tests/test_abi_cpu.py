@@ -111,11 +111,16 @@ def test_bf16_copy_length():
     assert L.rt_tucker_bf16_copy_elems(ctypes.byref(d), ctypes.byref(n)) == -1
 
 
-def test_gauss_seidel_flag_reports_unsupported():
-    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7])
-    d.flags |= B.RT_FLAG_GAUSS_SEIDEL
-    rc, _ = _ws(d)
-    assert rc == -2
+def test_gauss_seidel_order_accepted():
+    """RT_FLAG_GAUSS_SEIDEL selects the printed loop order of Algorithm 3;
+    the workspace is the Jacobi form's (the same buffers, used in turn)."""
+    d = P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7], order="gauss_seidel")
+    assert d.flags & B.RT_FLAG_GAUSS_SEIDEL
+    rc, n_gs = _ws(d)
+    rc2, n_j = _ws(P.tucker_desc([40, 50, 60], [10, 11, 12], [5, 6, 7]))
+    assert rc == 0 and rc2 == 0 and n_gs == n_j
+    with pytest.raises(ValueError):
+        P.tucker_desc([4, 5, 6], [2, 2, 2], order="random")
 
 
 def test_tucker_rand_rejects_null_and_misaligned_pointers_before_launch():

@@ -79,7 +79,7 @@ def test_ttm_parity(P, shape, K, dtype):
 
 # ------------------------------------------------------------ tucker_rand
 
-def run_tucker(P, d, ranks, sweeps, precision="f32", truncate=True):
+def run_tucker(P, d, ranks, sweeps, precision="f32", truncate=True, order="jacobi"):
     tdt = torch.float64 if precision == "f64" else torch.float32
     cast = (lambda a: a) if precision == "f64" else synth.f32
     Y = cast(d["Y"])
@@ -88,10 +88,10 @@ def run_tucker(P, d, ranks, sweeps, precision="f32", truncate=True):
     out = P.tucker_rand(dev(Y, tdt), [dev(o, tdt) for o in om],
                         [[dev(o, tdt) for o in lst] for lst in omt],
                         ranks=ranks, sweeps=sweeps, precision=precision,
-                        truncate=truncate, trace=True)
+                        truncate=truncate, trace=True, order=order)
     ref = RT.rand_tucker(np.asarray(Y, np.float64), [np.asarray(o, np.float64) for o in om],
                          [[np.asarray(o, np.float64) for o in lst] for lst in omt],
-                         sweeps=sweeps, ranks=ranks if truncate else None)
+                         sweeps=sweeps, ranks=ranks if truncate else None, order=order)
     return out, ref, np.asarray(Y, np.float64)
 
 
@@ -197,6 +197,80 @@ def test_tucker_rank_deficient_sketch(P, precision):
         assert projector_distance(host(out["U"][n]), ref["U"][n]) <= tol
     assert aligned_core_error(host(out["G"]), [host(u) for u in out["U"]],
                               ref["G"], ref["U"]) <= tol
+
+
+# ------------------------------------------------- Gauss-Seidel sweep order
+
+def test_tucker_gauss_seidel_c1_fp64(P):
+    """The loop of Algorithm 3 as printed (mode n's sketch uses the bases
+    modes < n received in the same sweep) on the 100^3 FP64 workload, two
+    sweeps, against the oracle's order="gauss_seidel"."""
+    d = synth.case_cp_gaussian(1, (100, 100, 100), 10, 40.0, (15, 15, 15), sweeps=2)
+    out, ref, Y = run_tucker(P, d, (10, 10, 10), 2, "f64", order="gauss_seidel")
+    check_tucker(out, ref, Y, 3, 2, 1e-12, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+@pytest.mark.parametrize("dims,ranks,rt", [((64, 72, 81), (6, 7, 8), (12, 13, 14)),
+                                           ((18, 20, 22, 24), (4, 5, 6, 7), (6, 7, 8, 9)),
+                                           ((9, 70, 260), (3, 3, 3), (9, 12, 12))])
+def test_tucker_gauss_seidel_fp32(P, sweeps, dims, ranks, rt):
+    """Every sketch but the first reads bases the device computed earlier in
+    the sweep, so its input differs from the oracle's by FP32 rounding
+    amplified through the trailing (noise) directions of those bases: each
+    sketch is checked, element-wise at 1e-5, against the oracle's sketch
+    step applied to the bases the device returned for the same point of the
+    loop (the Gauss-Seidel dependence written out here); the first sketch of
+    the first sweep, and the final bases and core, against the oracle run."""
+    d = synth.case_tucker(seed_of("gs", dims), dims, ranks, 25.0, rt, sweeps=2)
+    out, ref, Y = run_tucker(P, d, ranks, sweeps, "f32", order="gauss_seidel")
+    N = len(dims)
+    om = [synth.f32(o).astype(np.float64) for o in d["omegas"]]
+    omt = [[synth.f32(o).astype(np.float64) for o in lst] for lst in d["omega_tildes"]]
+    Qs = [[host(out["trace"]["Q"][s * N + n]) for n in range(N)] for s in range(sweeps)]
+    assert maxrel(host(out["trace"]["Z"][0]), ref["Z"][0][0]) <= 1e-5
+    for s in range(sweeps):
+        prev = om if s == 0 else Qs[s - 1]
+        for n in range(N):
+            bases = [Qs[s][p] if p < n else prev[p] for p in range(N)]
+            want = RT.sketch(Y, bases, omt[s][n], n)
+            e = maxrel(host(out["trace"]["Z"][s * N + n]), want)
+            assert e <= 1e-5, ("Z", s, n, e)
+            q = Qs[s][n]
+            assert np.linalg.norm(q.T @ q - np.eye(q.shape[1])) <= 1e-4
+    for n in range(N):
+        assert projector_distance(host(out["U"][n]), ref["U"][n]) <= 2e-4, ("U", n)
+    eG = aligned_core_error(host(out["G"]), [host(u) for u in out["U"]], ref["G"], ref["U"])
+    assert eG <= 2e-4
+
+
+def test_gauss_seidel_differs_from_jacobi_after_the_first_mode(P):
+    """In the first sweep both orders sketch mode 1 from the same Gaussian
+    bases (identical sketches); every later mode sees the updated bases in
+    the Gauss-Seidel order only."""
+    d = synth.case_tucker(309, (30, 34, 36), (4, 4, 4), 30.0, (8, 8, 8), sweeps=1)
+    a, _, _ = run_tucker(P, d, (4, 4, 4), 1, "f32", order="jacobi")
+    b, _, _ = run_tucker(P, d, (4, 4, 4), 1, "f32", order="gauss_seidel")
+    assert torch.equal(a["trace"]["Z"][0], b["trace"]["Z"][0])
+    for n in (1, 2):
+        assert rel(host(b["trace"]["Z"][n]), host(a["trace"]["Z"][n])) > 1e-2
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_tucker_gauss_seidel_bf16_vs_fp64_oracle(P, sweeps):
+    """The precision form in the Gauss-Seidel order against the FP64 oracle
+    in that order on the unrounded tensor: each subspace within
+    4 2^-9 ||Y|| / gap_n (the BF16 rounding of Y, Wedin)."""
+    dims, R, rt = (40, 120, 96), (5, 5, 5), (12, 12, 12)
+    d = synth.case_tucker(413, dims, R, 30.0, rt, sweeps=2)
+    out, ref, Y = run_tucker(P, d, R, sweeps, "bf16", order="gauss_seidel")
+    nY = np.linalg.norm(Y)
+    for n in range(3):
+        sv = np.linalg.svd(T.unfold(Y, n), compute_uv=False)
+        bound = 4 * 2.0 ** -9 * nY / (sv[R[n] - 1] - sv[R[n]])
+        assert projector_distance(host(out["U"][n]), ref["U"][n]) <= bound, n
+    eG = aligned_core_error(host(out["G"]), [host(u) for u in out["U"]], ref["G"], ref["U"])
+    assert eG <= 4 * 2.0 ** -9 * nY / np.linalg.norm(ref["G"]) + 1e-4
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
