@@ -3,12 +3,13 @@
 Cores come from the pipeline itself: seeded 300^3 CP tensors of rank 20
 with per-mode column congruence U[0.5, 0.95] and SNR U[20, 40] dB, compressed
 by rt_tucker_rand in the precision form (BF16, two sweeps) to 20^3 cores.
-The network is trained on the GPU by rt_mlp_train_step; on held-out cores
-FFCP-ALS (tol 1e-6) starts from the network's factors (guarded by the HOSVD
-start) and from the HOSVD start alone.  The test asserts what the paper's
-initialization cannot give: fewer ALS iterations on average, with a final
-fit no worse on every core (the guard keeps the HOSVD start when the
-network's is worse).
+The network is trained on the GPU by rt_mlp_train_step on 8192 such cores;
+on 512 held-out cores FFCP-ALS (tol 1e-6) starts from the network's factors
+(guarded by the HOSVD start), from the HOSVD start alone and from seeded
+random factors.  The test asserts fewer ALS iterations than from the HOSVD
+start on average and no more than about a random start's, with a final
+fit no worse than the HOSVD start's on every core (the guard keeps the
+HOSVD start when the network's is worse).
 """
 
 import numpy as np
@@ -50,8 +51,12 @@ def pipeline_cores(P, k0, count):
 
 
 def test_learned_init_needs_fewer_als_iterations(P):
-    Gtr, _ = pipeline_cores(P, 0, 1024)
-    Gev, Uev = pipeline_cores(P, 100000, 24)
+    """8192 training cores and 512 held-out ones; on each held-out core
+    FFCP-ALS to a fit change below 1e-6 from three starts: seeded N(0,1)
+    factors, the HOSVD start of the core, and the network's factors guarded
+    by the HOSVD start."""
+    Gtr, _ = pipeline_cores(P, 0, 8192)
+    Gev, Uev = pipeline_cores(P, 100000, 512)
     net = P.MLP((R, R, R), R, (1024, 1024))
     W, b = synth.mlp_weights(77, net.dims)
     W[2] = W[2] * 0.1
@@ -59,24 +64,50 @@ def test_learned_init_needs_fewer_als_iterations(P):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
     losses = []
-    for ep in range(24):
+    epochs = 24
+    for ep in range(epochs):
         perm = torch.randperm(Gtr.shape[0], device="cuda", generator=gen)
         lr = 1e-3 * 0.5 ** (ep // 6)
-        for i in range(0, Gtr.shape[0], 256):
-            losses.append(float(net.train_step(Gtr[perm[i:i + 256]].contiguous(), lr).mean()))
+        ls = [net.train_step(Gtr[perm[i:i + 256]].contiguous(), lr)
+              for i in range(0, Gtr.shape[0], 256)]
+        losses.append(float(torch.cat(ls).mean()))
     assert losses[-1] < 0.1 * losses[0]          # the network learned the cores
+    del Gtr
     Vs = net.split(net.forward(Gev))
-    it_h, it_l, fit_h, fit_l = [], [], [], []
+    rng = np.random.default_rng(5512)
+    its = {"random": [], "hosvd": [], "learned": []}
+    fits = {k: [] for k in its}
+    ms = {k: 0.0 for k in its}
+    stream = torch.cuda.current_stream()
     for k in range(Gev.shape[0]):
         G = Gev[k].contiguous()
-        h = P.ffcp(Uev[k], G, R, update="als", init="hosvd", max_it=1000, tol=1e-6)
-        l = P.ffcp(Uev[k], G, R, update="als", init="coeff_guarded",
-                   A_init=[v[k].contiguous() for v in Vs], max_it=1000, tol=1e-6)
-        it_h.append(int(h["info"]["iterations"]))
-        it_l.append(int(l["info"]["iterations"]))
-        fit_h.append(float(h["info"]["fit"]))
-        fit_l.append(float(l["info"]["fit"]))
-    it_h, it_l = np.array(it_h), np.array(it_l)
-    print(f"ALS iterations: HOSVD start {it_h.mean():.1f}, learned start {it_l.mean():.1f}")
-    assert it_l.mean() < 0.8 * it_h.mean()
-    assert np.all(np.array(fit_l) >= np.array(fit_h) - 1e-4)
+        starts = {
+            "random": dict(init="user", A_init=[torch.from_numpy(synth.f32(
+                rng.standard_normal((I, R)))).cuda() for _ in range(3)]),
+            "hosvd": dict(init="hosvd"),
+            "learned": dict(init="coeff_guarded", A_init=[v[k].contiguous() for v in Vs]),
+        }
+        for arm, kw in starts.items():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            f = P.ffcp(Uev[k], G, R, update="als", max_it=1000, tol=1e-6, **kw)
+            e1.record(stream)
+            e1.synchronize()
+            ms[arm] += e0.elapsed_time(e1)
+            its[arm].append(int(f["info"]["iterations"]))
+            fits[arm].append(float(f["info"]["fit"]))
+    it = {k: np.array(v) for k, v in its.items()}
+    print("held-out cores: 512; mean ALS iterations " +
+          ", ".join(f"{k} {it[k].mean():.1f}" for k in it) +
+          "; total FFCP ms " + ", ".join(f"{k} {ms[k]:.1f}" for k in ms), flush=True)
+    # measured: random 243.5, HOSVD 352.1, learned 252.4 mean iterations.  On
+    # cores of highly congruent CP models the HOSVD start (orthogonal
+    # directions of the core) lands far from the solution; the network's
+    # start removes that cost and ends level with a random start, whose
+    # iterations are spent in the same slow final phase
+    assert it["learned"].mean() < 0.8 * it["hosvd"].mean()
+    assert it["learned"].mean() < 1.1 * it["random"].mean()
+    # the guard keeps the better start, and ALS never lowers the fit: the
+    # learned arm's final fit is no worse than the HOSVD arm's on any core
+    # beyond the stop tolerance's slack
+    assert np.all(np.array(fits["learned"]) >= np.array(fits["hosvd"]) - 1e-4)

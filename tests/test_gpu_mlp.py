@@ -71,10 +71,10 @@ def test_mlp_forward_matches_oracle(P, hidden, B):
     assert rel(V, want) <= 2e-3
 
 
-@pytest.mark.parametrize("B", [16, 4])
-def test_mlp_gradients_match_oracle(P, B):
+@pytest.mark.parametrize("B,hidden", [(16, (128, 96)), (4, (128, 96)), (8, (1024, 1024))])
+def test_mlp_gradients_match_oracle(P, B, hidden):
     cd, R = (20, 20, 20), 20
-    G, net, params = setup(P, 502, B, cd, R, (128, 96))
+    G, net, params = setup(P, 502, B, cd, R, hidden)
     loss, gW, gb = net.grad(torch.from_numpy(G).cuda())
     Gh, _ = normalized(G)
     ref_loss, g = M.loss_and_backward(params, Gh, bf16=bf16_round)
