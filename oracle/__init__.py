@@ -20,4 +20,4 @@ index-wise, so this choice does not change any result.
 Parity status per function is listed in each module header.
 """
 
-from . import tensor, randtucker, ffcp, metrics, mlp  # noqa: F401
+from . import tensor, randtucker, ffcp, metrics, mlp, rng  # noqa: F401
