@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--no-hals", action="store_true",
                     help="skip the 10^4-per-mode FFCP-HALS side measurement")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the Algorithm 2 side measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
                     help="also run K plain device copies of Y (HBM counter "
                          "calibration under a profiler)")
@@ -137,20 +139,24 @@ def cpu_baseline(Y, omegas, omega_tildes, ranks, slab, sweeps, bytes_per_elem, r
 
 
 def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
-             warmup, tol, max_it, ybf16, net=None):
+             warmup, tol, max_it, ybf16, net=None, A_random=None, order="jacobi"):
     """Time `steps` calls of tucker_rand [+ MLP start] + ffcp in one form;
-    returns timings, the last outputs and the per-stage event totals."""
+    returns timings, the last outputs and the per-stage event totals.
+    Start: the network's (guarded by HOSVD) when net is given, the given
+    random factors when A_random is, else HOSVD."""
     stream = torch.cuda.current_stream()
 
     def step(tws, fws, ev):
         ev[0].record(stream)
         out = P.tucker_rand(Y, om_d, omt_d[:sweeps], ranks=ranks, sweeps=sweeps,
                             precision=precision, workspace=tws, ybf16=ybf16,
-                            sync=False)
+                            sync=False, order=order)
         ev[1].record(stream)
         if net is not None:     # learned start, kept only if it beats HOSVD's
             V = net.forward(out["G"].reshape((1,) + tuple(ranks)))
             init = dict(init="coeff_guarded", A_init=[v[0] for v in net.split(V)])
+        elif A_random is not None:
+            init = dict(init="user", A_init=A_random)
         else:
             init = dict(init="hosvd")
         ev[2].record(stream)
@@ -188,6 +194,10 @@ def run_form(P, torch, Y, om_d, omt_d, ranks, R, precision, sweeps, steps,
         "converged": int(finfo["converged"]), "fit_core": float(finfo["fit"]),
         "init_used": int(finfo["init_used"]),
         "fit_y": float(fit_y), "normY2": float(tinfo["normY2"]),
+        # Fit of the Tucker format against Y (orthonormal U):
+        # 1 - sqrt(||Y||^2 - ||G||^2) / ||Y||
+        "tucker_fit": float(1.0 - np.sqrt(max(tinfo["normY2"] - tinfo["normG2"], 0.0) /
+                                          tinfo["normY2"])),
         "U": [u.double().cpu().numpy() for u in out["U"]],
         "G": out["G"].double().cpu().numpy(),
     }
@@ -389,6 +399,8 @@ def main():
     if args.train_cores > 0:
         net, learned = train_learned_init(P, torch, synth, args.train_cores,
                                           args.train_epochs)
+    A_random = [torch.from_numpy(a).to(dev) for a in
+                synth.f32(synth.init_factors(d["init_rng"], dims, R))]
 
     # (precision, sweeps, learned start).  The plain FP32 path runs the same
     # two sweeps as the precision form, so both reach the same subspaces and
@@ -396,16 +408,20 @@ def main():
     # workload its subspaces, and so its fit, are clearly worse).  The
     # precision form from the HOSVD start isolates what the learned start
     # gains.
-    forms = {"bf16": ("bf16", 2, True), "bf16_hosvd": ("bf16", 2, False),
-             "f32": ("f32", 2, False), "f32_one_sweep": ("f32", 1, False)}
+    forms = {"bf16": ("bf16", 2, "learned"), "bf16_hosvd": ("bf16", 2, "hosvd"),
+             "bf16_random": ("bf16", 2, "random"), "f32": ("f32", 2, "hosvd"),
+             "f32_one_sweep": ("f32", 1, "hosvd"),
+             "f32_gauss_seidel": ("f32", 2, "hosvd")}
     main_form = args.precision
     order = [f for f in forms if f != main_form] + [main_form]   # the step's form last
     res = {}
     for form in order:
-        prec, sw, learned_start = forms[form]
+        prec, sw, start = forms[form]
         res[form] = run_form(P, torch, Y, om_d, omt_d, ranks, R, prec, sw,
                              args.steps, args.warmup, args.tol, args.max_it, ybf16,
-                             net if learned_start else None)
+                             net if start == "learned" else None,
+                             A_random if start == "random" else None,
+                             "gauss_seidel" if form.endswith("gauss_seidel") else "jacobi")
     m = res[main_form]
 
     # algorithmic HBM bytes of the Tucker stage (each pass reads Y once):
@@ -416,7 +432,8 @@ def main():
 
     def alg_bytes(form):
         prec, sw, _ = forms[form]
-        return (4 * (sw + 1) if prec == "f32" else 4 + 2 + 2 * sw) * n
+        passes = 2 * sw + 1 if form.endswith("gauss_seidel") else sw + 1
+        return (4 * passes if prec == "f32" else 4 + 2 + 2 * (passes - 1)) * n
 
     value = alg_bytes(main_form) / (m["tucker_ms"] * 1e-3) / 1e9
 
@@ -480,6 +497,33 @@ def main():
 
     hals = None if args.no_hals else run_hals_1e4(P, torch, synth, 3)
 
+    # Algorithm 2 (sequential RandTucker, dense counter-based Gaussian test
+    # matrices) on the same tensor, R~ = 30 in every mode: time, bytes and
+    # the captured energy beside the Jacobi RandTucker2i's at the same width
+    seq = None
+    if not args.no_sequential:
+        stream = torch.cuda.current_stream()
+        out_s = P.tucker_sequential(Y, (rt,) * 3, 14121885)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(3)]
+        for a, b in evs:
+            a.record(stream)
+            out_s = P.tucker_sequential(Y, (rt,) * 3, 14121885, sync=False)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms_s = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        g2 = float((out_s["G"].double() ** 2).sum())
+        y2 = m["normY2"]
+        rows1 = I * I
+        seq = {"workload": f"{I}^3 FP32, R~ = {rt} per mode, no truncation",
+               "ms": round(ms_s, 4),
+               "bytes": {"tensor_passes": 2 * 4 * n, "omega_1": 2 * 4 * rows1 * rt},
+               "tucker_fit_rt": 1.0 - float(np.sqrt(max(y2 - g2, 0.0) / y2)),
+               "note": "two passes over Y (sketch, then projection) and the dense "
+                       "Omega_1 written and read; RandTucker2i reads Y (S + 1) times "
+                       "with Kronecker-structured test matrices"}
+        del out_s
+
     cpu, errors = None, None
     if not args.no_cpu_baseline:
         cpu, ores, Ys = cpu_baseline(Y, om32, omt32, ranks, args.cpu_slab,
@@ -491,11 +535,15 @@ def main():
 
     def summary(form):
         r = res[form]
-        learned_start = forms[form][2] and net is not None
+        learned_start = forms[form][2] == "learned" and net is not None
+        start = {"learned": "learned (guarded by HOSVD)", "hosvd": "HOSVD",
+                 "random": "seeded N(0,1) factors"}[forms[form][2]]
         return {"precision": forms[form][0], "sweeps": forms[form][1],
+                "order": "gauss_seidel" if form.endswith("gauss_seidel") else "jacobi",
+                "tucker_fit": r["tucker_fit"],
                 "tucker_ms": round(r["tucker_ms"], 4),
                 "tucker_gbs": round(alg_bytes(form) / (r["tucker_ms"] * 1e-3) / 1e9, 1),
-                "start": "learned (guarded by HOSVD)" if learned_start else "HOSVD",
+                "start": start,
                 "start_kept": r["init_used"] if learned_start else None,
                 "init_ms": round(r["init_ms"], 4),
                 "ffcp_ms": round(r["ffcp_ms"], 4),
@@ -539,16 +587,30 @@ def main():
         "learned_gain": {
             "ffcp_iterations_learned": res["bf16"]["iterations"],
             "ffcp_iterations_hosvd": res["bf16_hosvd"]["iterations"],
+            "ffcp_iterations_random": res["bf16_random"]["iterations"],
             "ffcp_ms_learned_incl_inference": round(res["bf16"]["init_ms"] +
                                                     res["bf16"]["ffcp_ms"], 4),
             "ffcp_ms_hosvd": round(res["bf16_hosvd"]["init_ms"] +
                                    res["bf16_hosvd"]["ffcp_ms"], 4),
-            "note": "both arms: precision form, two sweeps, same tensor; the learned "
+            "ffcp_ms_random": round(res["bf16_random"]["ffcp_ms"], 4),
+            "fit_y": {k: res[k]["fit_y"] for k in ("bf16", "bf16_hosvd", "bf16_random")},
+            "note": "all arms: precision form, two sweeps, same tensor; the learned "
                     "arm includes the network's inference and the HOSVD guard"},
+        "gauss_seidel_vs_jacobi": {
+            "note": "plain FP32, two sweeps: the printed loop order of Algorithm 3 "
+                    "takes two passes over Y per sweep, the Jacobi order one",
+            "bytes": {"jacobi": alg_bytes("f32"), "gauss_seidel": alg_bytes("f32_gauss_seidel")},
+            "tucker_ms": {"jacobi": round(res["f32"]["tucker_ms"], 4),
+                          "gauss_seidel": round(res["f32_gauss_seidel"]["tucker_ms"], 4)},
+            "tucker_fit": {"jacobi": res["f32"]["tucker_fit"],
+                           "gauss_seidel": res["f32_gauss_seidel"]["tucker_fit"]},
+            "fit_y": {"jacobi": res["f32"]["fit_y"],
+                      "gauss_seidel": res["f32_gauss_seidel"]["fit_y"]}},
         "errors_vs_fp64_oracle": errors,
         "kernels": kernels,
         "learned_init": learned,
         "hals_1e4_4way": hals,
+        "sequential_alg2": seq,
         "normY2": m["normY2"],
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -190,6 +190,51 @@ int rt_tucker_rand(const rt_tucker_desc* desc, const void* Y,
                    uint16_t* Ybf16, rt_tucker_info* info,
                    const rt_tucker_trace* trace, void* stream);
 
+/*
+ * Sequential RandTucker (Algorithm 2, Section IV-A) with dense Gaussian test
+ * matrices drawn on the device.  For n = 1..N:
+ *     Z_n = Y_(n) Omega_n,  U_n = orth(Z_n)  (FP64 QR, diag(R) >= 0),
+ *     Y <- Y x_n U_n^T,
+ * where Omega_n has one row per index of the other modes in their current
+ * sizes (modes < n already shrunk to R~_k; row-major order of those
+ * indices, increasing mode) and R~_n columns.  The last tensor is the core
+ * G (R~_1 x ... x R~_N).  Entry (r, k) of Omega_n is produced from
+ * (seed, n, r, k) alone by rt_gaussian_matrix's generator.  Two passes over
+ * the full tensor; Omega_1 (prod_{k>1} I_k x R~_1) is materialized in the
+ * workspace.
+ *   N 2..RT_MAX_MODES; precision RT_F32 or RT_F64 (others:
+ *   RT_ERR_UNSUPPORTED); dims I_n >= 1; 1 <= R~_n <= min(I_n, RT_MAX_SKETCH).
+ */
+typedef struct {
+  int32_t N;
+  int32_t precision;
+  uint64_t seed;
+  int64_t dims[RT_MAX_MODES];
+  int32_t ranks_tilde[RT_MAX_MODES];
+} rt_sequential_desc;
+
+int rt_tucker_sequential_workspace(const rt_sequential_desc* desc, size_t* bytes);
+/*   Y         device, I_1 x ... x I_N row-major, FP32 or FP64 (precision).
+ *   U         host array of N device outputs U_n, I_n x R~_n (same type).
+ *   G         device output core, R~_1 x ... x R~_N (same type).
+ *   Omega_out NULL, or a host array of N device buffers (entries may be NULL)
+ *             receiving each Omega_n as used (rows x R~_n, same type).
+ * Errors: RT_ERR_INVALID_ARG, RT_ERR_UNSUPPORTED, RT_ERR_WORKSPACE, RT_ERR_HIP. */
+int rt_tucker_sequential(const rt_sequential_desc* desc, const void* Y, void* ws,
+                         size_t ws_bytes, void* const* U, void* G, void* const* Omega_out,
+                         void* stream);
+/*
+ * The counter-based Gaussian matrix of Alg. 2's test matrices: out[r][k]
+ * (rows x cols row-major, device, dtype RT_F32 or RT_F64) is entry (r, k) for
+ * mode `mode`: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC
+ * 2011) on counter (r mod 2^32, r div 2^32, k, mode) and key (seed mod 2^32,
+ * seed div 2^32), then Box-Muller in FP64 on the first two output words x0,
+ * x1: u1 = (x0 + 1) 2^-32, u2 = (x1 + 1/2) 2^-32,
+ * value = sqrt(-2 ln u1) cos(2 pi u2), rounded to dtype.
+ */
+int rt_gaussian_matrix(int32_t dtype, uint64_t seed, int32_t mode, int64_t rows, int32_t cols,
+                       void* out, void* stream);
+
 /* FFCP update rules (the factor update of Algorithm 1). */
 typedef enum {
   RT_ALS = 0,  /* eq. (14): A = U G_(n)(KR V) (hadamard A^T A)^{-1}        */

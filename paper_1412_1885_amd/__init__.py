@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     ffcp_desc, ffcp_workspace, ffcp, ffcp_noalloc, ffcp_dense_workspace, ffcp_dense, ttm, cp_fit_dense,
     rt_tucker_rand, rt_ffcp, rt_ttm, rt_cp_fit_dense, rt_stream_pass,
     stream_pass, profile_enable, profile_read,
+    sequential_desc, tucker_sequential, gaussian_matrix,
     LIB_PATH, TUCKER_INFO_DTYPE, FFCP_INFO_DTYPE,
     MLP, mlp_desc,
 )

@@ -59,6 +59,13 @@ class MlpDesc(ctypes.Structure):
                 ("core_dims", ctypes.c_int32 * 8)]
 
 
+class SequentialDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("seed", ctypes.c_uint64),
+                ("dims", ctypes.c_int64 * RT_MAX_MODES),
+                ("ranks_tilde", ctypes.c_int32 * RT_MAX_MODES)]
+
+
 class MlpParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p * 3) for k in ("W", "b", "Wb", "mW", "vW", "mb", "vb")]
 
@@ -108,6 +115,11 @@ def lib():
         L.rt_ffcp.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
                               ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz,
                               ctypes.POINTER(vp), vp, vp, vp, vp]
+        L.rt_tucker_sequential_workspace.argtypes = [ctypes.POINTER(SequentialDesc),
+                                                     ctypes.POINTER(sz)]
+        L.rt_tucker_sequential.argtypes = [ctypes.POINTER(SequentialDesc), vp, vp, sz,
+                                           ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp]
+        L.rt_gaussian_matrix.argtypes = [i32, ctypes.c_uint64, i32, i64, i32, vp, vp]
         L.rt_ffcp_noalloc.argtypes = [ctypes.POINTER(FfcpDesc), ctypes.POINTER(vp), vp,
                                       ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, vp, vp, vp]
@@ -137,7 +149,8 @@ def lib():
         L.rt_version.restype = ctypes.c_char_p
         for f in ("rt_tucker_rand_workspace", "rt_tucker_bf16_copy_elems",
                   "rt_tucker_rand", "rt_ffcp_workspace",
-                  "rt_ffcp", "rt_ffcp_noalloc", "rt_ffcp_dense_workspace", "rt_ffcp_dense", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
+                  "rt_ffcp", "rt_ffcp_noalloc", "rt_tucker_sequential_workspace",
+                  "rt_tucker_sequential", "rt_gaussian_matrix", "rt_ffcp_dense_workspace", "rt_ffcp_dense", "rt_ttm", "rt_cp_fit_workspace", "rt_cp_fit_dense",
                   "rt_stream_pass", "rt_profile_enable", "rt_profile_read",
                   "rt_mlp_workspace", "rt_mlp_sync_bf16", "rt_mlp_forward", "rt_mlp_grad",
                   "rt_mlp_train_step"):
@@ -375,6 +388,62 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
         out["info"] = inf
         if ft is not None:
             out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
+    return out
+
+
+def sequential_desc(dims, ranks_tilde, seed, precision="f32"):
+    d = SequentialDesc()
+    d.N = len(dims)
+    d.precision = PRECISIONS[precision]
+    d.seed = int(seed)
+    for n, I in enumerate(dims):
+        d.dims[n] = int(I)
+        d.ranks_tilde[n] = int(ranks_tilde[n])
+    return d
+
+
+def tucker_sequential(Y, ranks_tilde, seed, keep_omegas=False, stream=None, sync=True):
+    """rt_tucker_sequential: Algorithm 2 with the device's counter-based
+    Gaussian test matrices.  Y: device float32 / float64 tensor.  Returns
+    U (list), G and, with keep_omegas, the test matrices as used."""
+    torch = _torch()
+    dims = list(Y.shape)
+    N = len(dims)
+    precision = "f64" if Y.dtype == torch.float64 else "f32"
+    desc = sequential_desc(dims, ranks_tilde, seed, precision)
+    _require_device(Y, "Y")
+    n = ctypes.c_size_t(0)
+    _check(lib().rt_tucker_sequential_workspace(ctypes.byref(desc), ctypes.byref(n)))
+    dev = Y.device
+    ws = _workspace(n.value, dev)
+    U = [torch.empty((dims[k], ranks_tilde[k]), dtype=Y.dtype, device=dev) for k in range(N)]
+    G = torch.empty(list(ranks_tilde), dtype=Y.dtype, device=dev)
+    oms = None
+    if keep_omegas:
+        oms = []
+        for k in range(N):
+            rows = 1
+            for q in range(N):
+                if q != k:
+                    rows *= ranks_tilde[q] if q < k else dims[q]
+            oms.append(torch.empty((rows, ranks_tilde[k]), dtype=Y.dtype, device=dev))
+    _check(lib().rt_tucker_sequential(ctypes.byref(desc), _ptr(Y), _ptr(ws), ws.numel(),
+                                      _ptr_array(U), _ptr(G),
+                                      _ptr_array(oms) if oms is not None else None,
+                                      _stream_handle(stream)))
+    if sync:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return {"U": U, "G": G, "omegas": oms, "workspace": ws}
+
+
+def gaussian_matrix(rows, cols, mode, seed, dtype=None, device="cuda", stream=None):
+    """rt_gaussian_matrix: the counter-based Gaussian test matrix (device)."""
+    torch = _torch()
+    dtype = torch.float32 if dtype is None else dtype
+    out = torch.empty((rows, cols), dtype=dtype, device=device)
+    code = PRECISIONS["f64"] if dtype == torch.float64 else PRECISIONS["f32"]
+    _check(lib().rt_gaussian_matrix(code, int(seed), int(mode), int(rows), int(cols),
+                                    _ptr(out), _stream_handle(stream)))
     return out
 
 
