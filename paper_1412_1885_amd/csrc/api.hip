@@ -108,7 +108,8 @@ int validate_tucker(const rt_tucker_desc* d) {
   if (d->precision == RT_BF16_MIXED)
     RT_TRY(bf16_check_shape(total / (d->dims[d->N - 2] * d->dims[d->N - 1]),
                             d->dims[d->N - 2], d->dims[d->N - 1],
-                            d->ranks_tilde[d->N - 2], d->ranks_tilde[d->N - 1]));
+                            d->ranks_tilde[d->N - 2], d->ranks_tilde[d->N - 1],
+                            (d->flags & RT_FLAG_BF16_INPUT) != 0));
   return kOk;
 }
 
@@ -126,6 +127,7 @@ struct TuckerPlan {
   int32_t* iflags; // [0] nonfinite [1] rank
   T* TA;
   T* TB;
+  T* Cs;   // TA x_{N-1} B_{N-1}^T per slab, [prod_{p<N-1} I_p, R~_{N-1}, R~_N]
   T* X0;
   T* X1;
   T* Z[RT_MAX_MODES];
@@ -168,6 +170,7 @@ struct TuckerPlan {
     iflags = ar.take<int32_t>(8 + 16);
     TA = ar.take<T>(sizeTA);
     TB = ar.take<T>(sizeTB);
+    Cs = ar.take<T>(sizeTA / I[second] * K[second]);
     X0 = ar.take<T>(chain);
     X1 = ar.take<T>(chain);
     for (int n = 0; n < N; ++n) {
@@ -227,18 +230,25 @@ int contract_chain(const T* base, int64_t* D, int N, const int* modes,
 }
 
 // Z_n = X_(n) Omega~_n from the streamed intermediate T (TA for n < N-1,
-// TB for n = N-1): W_n = Omega~_n expanded by B_p in every mode p that T
-// still holds at full size (p != n), then Z_n[i, r] = sum_{a,c} T[a,i,c]
-// W_n[a,c,r] (split-K product).
+// TB for n = N-1; for n < N-2, when the pass made it, C = TA x_{N-1}
+// B_{N-1}^T, 1/I_{N-1}-th of TA's size): W_n = Omega~_n expanded by B_p in
+// every mode p that T still holds at full size (p != n), then
+// Z_n[i, r] = sum_{a,c} T[a,i,c] W_n[a,c,r] (split-K product).
 template <typename T, typename Plan>
-int sketch_from_intermediate(Plan& P, int n, const T* const* B, const T* Omt,
+int sketch_from_intermediate(Plan& P, int n, const T* const* B, const T* Omt, bool use_c,
                              hipStream_t s) {
   const int N = P.N, last = N - 1, second = N - 2;
   int64_t D[RT_MAX_MODES];
   for (int p = 0; p < N; ++p) D[p] = P.I[p];
   const T* base;
+  // modes the intermediate already holds at R~_p
+  const bool from_c = use_c && n < second;
   const int contracted = (n != last) ? last : second;
-  if (n != last) {
+  if (from_c) {
+    base = P.Cs;
+    D[last] = P.K[last];
+    D[second] = P.K[second];
+  } else if (n != last) {
     base = P.TA;
     D[last] = P.K[last];
   } else {
@@ -258,7 +268,7 @@ int sketch_from_intermediate(Plan& P, int n, const T* const* B, const T* Omt,
   int cur = 0;
   for (int q = 0; q < nw; ++q) {
     const int p = wm[q];
-    if (p == contracted) continue;  // T already holds this mode at K_p
+    if (p == contracted || (from_c && p == second)) continue;  // held at K_p
     int64_t Apre = 1, Cpost = P.K[n];
     for (int r = 0; r < q; ++r) Apre *= Wd[r];
     for (int r = q + 1; r < nw; ++r) Cpost *= Wd[r];
@@ -319,11 +329,13 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     if (!gauss_seidel) {
       // Jacobi: one streamed pass, TA = Y x_last B_last^T and
       // TB = Y x_second B_second^T, serves every mode of the sweep
+      bool cdone = false;
       RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
-                            P.TB, s));
+                            P.TB, N >= 3 ? P.Cs : nullptr, &cdone, s));
       {
         ProfScope ps(kStageContract, s);
-        for (int n = 0; n < N; ++n) RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], s));
+        for (int n = 0; n < N; ++n)
+          RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], cdone, s));
       }
       RT_TRY(qr_modes(0, N));
     } else {
@@ -333,21 +345,24 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       // one pass serves them one after the other; mode N-1 needs
       // TB = Y x_second Q_second^T with the new basis of mode N-2: a second
       // pass (its TA is not used).
+      // (C = TA x_{N-1} B_{N-1}^T holds the previous basis of mode N-1,
+      // which is what modes < N-1 use in this order)
+      bool cdone = false;
       RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
-                            P.TB, s));
+                            P.TB, N >= 3 ? P.Cs : nullptr, &cdone, s));
       for (int n = 0; n < last; ++n) {
         {
           ProfScope ps(kStageContract, s);
-          RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], s));
+          RT_TRY(sketch_from_intermediate<T>(P, n, B, Omt_s[n], cdone, s));
         }
         RT_TRY(qr_modes(n, n + 1));
         B[n] = P.Q[n];
       }
       RT_TRY(stream_dual<T>(sc, pass++, B[last], P.K[last], B[second], P.K[second], P.TA,
-                            P.TB, s));
+                            P.TB, nullptr, nullptr, s));
       {
         ProfScope ps(kStageContract, s);
-        RT_TRY(sketch_from_intermediate<T>(P, last, B, Omt_s[last], s));
+        RT_TRY(sketch_from_intermediate<T>(P, last, B, Omt_s[last], false, s));
       }
       RT_TRY(qr_modes(last, N));
     }
@@ -367,17 +382,26 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     for (int n = 0; n < N; ++n) B[n] = P.Q[n];
   }
 
-  // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first, then the rest
-  RT_TRY(stream_single<T>(sc, pass, B[last], P.K[last], P.TA, s));
+  // core G~ = Y x_1 Q_1^T ... x_N Q_N^T: streamed mode first (with mode
+  // N-1 inside the pass where it can), then the rest
+  bool cdone = false;
+  RT_TRY(stream_single<T>(sc, pass, B[last], P.K[last], B[second], P.K[second], P.TA,
+                          N >= 3 ? P.Cs : nullptr, &cdone, s));
   {
     ProfScope ps(kStageContract, s);
     int64_t D[RT_MAX_MODES];
     for (int p = 0; p < N; ++p) D[p] = P.I[p];
     D[last] = P.K[last];
     const T* src = P.TA;
+    int pstart = last - 1;
+    if (cdone) {
+      src = P.Cs;
+      D[second] = P.K[second];
+      pstart = second - 1;
+    }
     T* bufs[2] = {P.X0, P.X1};
     int cur = 0;
-    for (int p = last - 1; p >= 1; --p) {  // innermost remaining mode first
+    for (int p = pstart; p >= 1; --p) {  // innermost remaining mode first
       int64_t Apre = 1, Cpost = 1;
       for (int q = 0; q < p; ++q) Apre *= D[q];
       for (int q = p + 1; q < N; ++q) Cpost *= D[q];
@@ -1047,17 +1071,19 @@ int rt_stream_pass(int32_t dtype, int64_t A, int64_t I1, int64_t I2,
     if (TB)
       return stream_dual<float>(sc, 0, static_cast<const float*>(B2), K2,
                                 static_cast<const float*>(B1), K1,
-                                static_cast<float*>(TA), static_cast<float*>(TB), s);
-    return stream_single<float>(sc, 0, static_cast<const float*>(B2), K2,
-                                static_cast<float*>(TA), s);
+                                static_cast<float*>(TA), static_cast<float*>(TB), nullptr,
+                                nullptr, s);
+    return stream_single<float>(sc, 0, static_cast<const float*>(B2), K2, nullptr, 0,
+                                static_cast<float*>(TA), nullptr, nullptr, s);
   }
   if (dtype == RT_F64) {
     if (TB)
       return stream_dual<double>(sc, 0, static_cast<const double*>(B2), K2,
                                  static_cast<const double*>(B1), K1,
-                                 static_cast<double*>(TA), static_cast<double*>(TB), s);
-    return stream_single<double>(sc, 0, static_cast<const double*>(B2), K2,
-                                 static_cast<double*>(TA), s);
+                                 static_cast<double*>(TA), static_cast<double*>(TB),
+                                 nullptr, nullptr, s);
+    return stream_single<double>(sc, 0, static_cast<const double*>(B2), K2, nullptr, 0,
+                                 static_cast<double*>(TA), nullptr, nullptr, s);
   }
   set_error("rt_stream_pass: dtype %d unsupported", dtype);
   return kErrInvalid;

@@ -23,6 +23,8 @@
 // The K index of each MFMA is a permutation of the contracted index applied
 // identically to both operands.  ||Y||^2 (FP64) and a non-finite check ride
 // along on the staged values, which cover every element exactly once.
+// TA and TB are written with non-temporal stores: they are read once, by
+// a later kernel, and normal stores of them slowed the read stream.
 #include "stream.hpp"
 
 #include "kernels.hpp"
@@ -187,7 +189,8 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
-            if (row < I1 && m < K2) p.TA[(a * I1 + row) * K2 + m] = accp[v];
+            if (row < I1 && m < K2)
+              __builtin_nontemporal_store(accp[v], p.TA + (a * I1 + row) * K2 + m);
           }
         }
       } else {
@@ -203,7 +206,8 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
           float s = 0.f;
           for (int w = 0; w < wps; ++w) s += stage[(g * wps + w) * kTile + rl * 32 + n];
           const int row = r0 + rl;
-          if (live && row < I1 && n < K2) p.TA[(a * I1 + row) * K2 + n] = s;
+          if (live && row < I1 && n < K2)
+            __builtin_nontemporal_store(s, p.TA + (a * I1 + row) * K2 + n);
         }
         __syncthreads();
       }
@@ -217,7 +221,8 @@ __global__ __launch_bounds__(kThreads) void dual_f32_kernel(DualArgs p) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
               const int j = 8 * (v >> 2) + 4 * h + (v & 3);
-              if (j < K1 && col < I2) p.TB[(a * K1 + j) * I2 + col] = accq[ct][v];
+              if (j < K1 && col < I2)
+                __builtin_nontemporal_store(accq[ct][v], p.TB + (a * K1 + j) * I2 + col);
             }
           }
         }
@@ -371,10 +376,11 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
 
 template <typename T>
 int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1,
-                int K1, T* TA, T* TB, hipStream_t s) {
+                int K1, T* TA, T* TB, T* C, bool* c_done, hipStream_t s) {
+  if (c_done) *c_done = false;
   if (c.precision == RT_BF16_MIXED) {
     if constexpr (sizeof(T) == sizeof(float))
-      return bf16_stream_pass(c, sweep == 0, B2, K2, B1, K1, TA, TB,
+      return bf16_stream_pass(c, sweep == 0, B2, K2, B1, K1, TA, TB, C, c_done,
                               sweep == 0 ? kStageFirstPass : kStageSweepPass, s);
     set_error("BF16 mixed precision computes in FP32");
     return kErrUnsupported;
@@ -400,12 +406,13 @@ int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1,
 }
 
 template <typename T>
-int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
-                  hipStream_t s) {
+int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1, int K1,
+                  T* TA, T* C, bool* c_done, hipStream_t s) {
+  if (c_done) *c_done = false;
   if (c.precision == RT_BF16_MIXED) {
     if constexpr (sizeof(T) == sizeof(float))
-      return bf16_stream_pass(c, sweep == 0, B2, K2, nullptr, 0, TA, nullptr,
-                              kStageCorePass, s);
+      return bf16_stream_pass(c, sweep == 0, B2, K2, C ? B1 : nullptr, C ? K1 : 0, TA,
+                              nullptr, C, c_done, kStageCorePass, s);
     set_error("BF16 mixed precision computes in FP32");
     return kErrUnsupported;
   }
@@ -426,14 +433,13 @@ int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
   return launch_ttm<T>(Y, B2, TA, c.A * c.I1, c.I2, 1, K2, s);
 }
 
-template int stream_dual<float>(const StreamCtx&, int, const float*, int,
-                                const float*, int, float*, float*, hipStream_t);
-template int stream_dual<double>(const StreamCtx&, int, const double*, int,
-                                 const double*, int, double*, double*,
-                                 hipStream_t);
-template int stream_single<float>(const StreamCtx&, int, const float*, int,
-                                  float*, hipStream_t);
-template int stream_single<double>(const StreamCtx&, int, const double*, int,
-                                   double*, hipStream_t);
+template int stream_dual<float>(const StreamCtx&, int, const float*, int, const float*, int,
+                                float*, float*, float*, bool*, hipStream_t);
+template int stream_dual<double>(const StreamCtx&, int, const double*, int, const double*,
+                                 int, double*, double*, double*, bool*, hipStream_t);
+template int stream_single<float>(const StreamCtx&, int, const float*, int, const float*, int,
+                                  float*, float*, bool*, hipStream_t);
+template int stream_single<double>(const StreamCtx&, int, const double*, int, const double*,
+                                   int, double*, double*, bool*, hipStream_t);
 
 }  // namespace rt

@@ -35,20 +35,28 @@ StreamCtx make_stream_ctx(const rt_tucker_desc* d, const void* y,
 
 // BF16 precision form (stream_bf16.hip)
 size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2);
-int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2);
+int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2,
+                     bool bf16_input);
 // row stride (values) of the BF16 copy of rows of I2 values: I2 rounded up
 // to a multiple of 64
 int64_t bf16_copy_ld(int64_t I2);
-// stage: profiling stage that brackets the streaming kernel itself
+// stage: profiling stage that brackets the streaming kernel itself.
+// TA / TB / C may be null (not computed); C (the slab-local product
+// TA x_{N-1} B1^T, [A, K1, K2]) is made only by the column-split pass:
+// *c_done tells whether it was.
 int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
-                     const float* B1, int K1, float* TA, float* TB, int stage,
-                     hipStream_t s);
+                     const float* B1, int K1, float* TA, float* TB, float* C, bool* c_done,
+                     int stage, hipStream_t s);
 
+// C (nullable): also C = TA x_{N-1} B1^T per slab where the pass can make
+// it (the precision form's column-split pass); *c_done says whether it did.
 template <typename T>
 int stream_dual(const StreamCtx& c, int sweep, const T* B2, int K2,
-                const T* B1, int K1, T* TA, T* TB, hipStream_t s);
+                const T* B1, int K1, T* TA, T* TB, T* C, bool* c_done, hipStream_t s);
+// Core pass: TA = Y x_N B2^T, or (C given and made, *c_done) only
+// C = TA x_{N-1} B1^T per slab without writing TA.
 template <typename T>
-int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, T* TA,
-                  hipStream_t s);
+int stream_single(const StreamCtx& c, int sweep, const T* B2, int K2, const T* B1, int K1,
+                  T* TA, T* C, bool* c_done, hipStream_t s);
 
 }  // namespace rt

@@ -67,6 +67,7 @@ namespace rt {
 namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kBW = 8;                 // wavefronts per workgroup
@@ -83,6 +84,7 @@ constexpr int kB1Pad = 8;              // halfwords of padding per B1^T row in L
 // that drain less often: 16 steps took the core pass from 0.50 to 0.47 ms.
 constexpr int kUnroll = 16;
 static_assert(kCT * kYtStride * 2 <= kWaveLds, "transposed tile fits the wave's region");
+static_assert(2 * 32 * 32 * 4 <= kWaveLds, "two TA row blocks fit the wave's region");
 
 struct BfArgs {
   const uint16_t* Y;      // BF16 bit patterns (the scaled copy or the caller's)
@@ -103,6 +105,15 @@ __device__ __forceinline__ v8bf as_v8bf(uint4 u) { return __builtin_bit_cast(v8b
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
   return static_cast<uint32_t>(f32_to_bf16_rne(lo)) |
          (static_cast<uint32_t>(f32_to_bf16_rne(hi)) << 16);
+}
+
+// The same two roundings with gfx950's packed conversion instruction
+// (round to nearest even; equal to pack2 for every non-NaN input, checked
+// on the device against it)
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2_hw(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{lo, hi}, v2bf));
 }
 
 // Operands of one 32 x 64 tile for one lane: 4 chunks of 8 BF16 values.
@@ -162,11 +173,15 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // B2^T operand of column tile ct for this lane (row lr of B2^T).
-__device__ __forceinline__ void load_b2(const BfArgs& a, int ct, int lr, int g, v8bf* b2) {
+__device__ __forceinline__ void load_b2t(const uint16_t* B2t, int ldb2, int ct, int lr, int g,
+                                         v8bf* b2) {
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     b2[q] = as_v8bf(*reinterpret_cast<const uint4*>(
-        a.B2t + static_cast<int64_t>(lr) * a.ldb2 + ct * kCT + 16 * q + 8 * g));
+        B2t + static_cast<int64_t>(lr) * ldb2 + ct * kCT + 16 * q + 8 * g));
+}
+__device__ __forceinline__ void load_b2(const BfArgs& a, int ct, int lr, int g, v8bf* b2) {
+  load_b2t(a.B2t, a.ldb2, ct, lr, g, b2);
 }
 
 // RBW: steps per column tile (the row blocks a wave owns, rounded up to 1, 2
@@ -200,24 +215,32 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
   const int64_t base = slab * slab_elems;
   const __amdgpu_buffer_rsrc_t rs = slab_rsrc(a.Y + base, slab_elems * 2);
 
-  // step s: column tile s / RBW, row block w + kBW (s % RBW)
-  Tile ring[kSlots];
-#pragma unroll
-  for (int k = 0; k + 1 < kSlots; ++k)
-    load_tile<HALF>(rs, a, w + kBW * (k % RBW), lr, (k / RBW) * kCT, g, ring[k]);
-  // B2^T of column tile ct in b2[ct % 2], loaded one column tile ahead
-  v8bf b2[2][4];
-  load_b2(a, 0, lr, g, b2[0]);
+  // Prologue, in the order the loop's steady state has its loads in
+  // flight: B2^T of the current column tile older than the tiles of the
+  // ring.  The compiler's wait counts at the loop head hold for both the
+  // entry and the back edge; with B2^T issued after the ring here, the
+  // first step of every loop trip waited for all tiles in flight.
   if constexpr (DOQ) {
-    // B1^T for the whole slab, rows padded against bank conflicts
+    // B1^T for the whole slab, rows padded against bank conflicts (its
+    // loads complete here, before anything else is in flight)
     const int rowc = a.ldb1 / 8;
     for (int l = threadIdx.x; l < 32 * rowc; l += kBThreads) {
       const int k = l / rowc, cc = l - k * rowc;
       *reinterpret_cast<uint4*>(b1s + k * ldb1s + 8 * cc) =
           *reinterpret_cast<const uint4*>(a.B1t + static_cast<int64_t>(k) * a.ldb1 + 8 * cc);
     }
-    __syncthreads();
   }
+  // B2^T of column tile ct in b2[ct % 2], loaded one column tile ahead
+  v8bf b2[2][4];
+  load_b2(a, 0, lr, g, b2[0]);
+  __builtin_amdgcn_sched_barrier(0);   // issued before the ring's tiles
+  // step s: column tile s / RBW, row block w + kBW (s % RBW)
+  Tile ring[kSlots];
+#pragma unroll
+  for (int k = 0; k + 1 < kSlots; ++k)
+    load_tile<HALF>(rs, a, w + kBW * (k % RBW), lr, (k / RBW) * kCT, g, ring[k]);
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (DOQ) __syncthreads();   // B1^T visible to every wave
 
   v16f accA[RBW];
 #pragma unroll
@@ -300,13 +323,18 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
                 red[(w * 32 + m) * kCT + 32 * sh + lr] = accB[sh][v];
               }
             __syncthreads();
-            for (int l = threadIdx.x; l < 32 * kCT; l += kBThreads) {
-              const int m = l / kCT, n = l % kCT;
-              float sum = 0.0f;
+            // four consecutive columns per thread (I2 % 4 == 0, so a
+            // group is wholly inside or outside the slab), non-temporal
+            for (int l = threadIdx.x; l < 32 * kCT / 4; l += kBThreads) {
+              const int m = l / (kCT / 4), n = 4 * (l % (kCT / 4));
+              v4f sum = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-              for (int ww = 0; ww < kBW; ++ww) sum += red[(ww * 32 + m) * kCT + n];
+              for (int ww = 0; ww < kBW; ++ww)
+                sum += *reinterpret_cast<const v4f*>(red + (ww * 32 + m) * kCT + n);
               if (m < a.K1 && c0 + n < a.I2)
-                a.TB[(slab * a.K1 + m) * a.I2 + c0 + n] = sum * up;
+                __builtin_nontemporal_store(
+                    sum * up,
+                    reinterpret_cast<v4f*>(a.TB + (slab * a.K1 + m) * a.I2 + c0 + n));
             }
             __syncthreads();
           }
@@ -317,17 +345,39 @@ __global__ __launch_bounds__(kBThreads) void bf16_stream_kernel(BfArgs a) {
       __builtin_amdgcn_sched_barrier(0);
     });
   }
-  // TA rows of this wave's blocks
+  // TA rows of this wave's blocks.  A row block of TA (32 rows of K2
+  // values) is one contiguous span of the output; it goes through the
+  // wave's LDS region (free after the last column tile) so that each store
+  // instruction writes 64 consecutive values.  Scattered stores straight
+  // from the MFMA layout (two partial rows per instruction) left the CU
+  // idle for a long tail at the end of every slab.
+  float* st = reinterpret_cast<float*>(smem + w * kWaveLds);
+  const int K2 = a.K2;
 #pragma unroll
   for (int i = 0; i < RBW; ++i) {
     const int rb = w + kBW * i;
-    if (rb < nrb) {
+    if (rb < nrb) {   // wave-uniform
+      float* sb = st + (i & 1) * (32 * 32);
+      if (lr < K2) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int m = 8 * (v / 4) + 4 * g + (v % 4);
-        const int r = rb * 32 + m;
-        if (r < a.I1 && lr < a.K2)
-          a.TA[(slab * a.I1 + r) * a.K2 + lr] = accA[i][v] * up;
+        for (int v = 0; v < 16; ++v) sb[(8 * (v / 4) + 4 * g + (v % 4)) * K2 + lr] = accA[i][v] * up;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int rows = a.I1 - rb * 32 < 32 ? a.I1 - rb * 32 : 32;
+      const int64_t o = (slab * a.I1 + rb * 32) * K2;
+      const int cnt = rows * K2;
+      float* dst = a.TA + o;
+      // non-temporal: written once, read by a later kernel (normal stores
+      // of the 120 MB of TA at 1000^3 cost about three times their share
+      // of the pass's bytes)
+      if (((o | cnt) & 3) == 0) {   // wave-uniform
+        for (int l = 4 * lane; l < cnt; l += 256)
+          __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(sb + l),
+                                      reinterpret_cast<v4f*>(dst + l));
+      } else {
+        for (int l = lane; l < cnt; l += 64) __builtin_nontemporal_store(sb[l], dst + l);
       }
     }
   }
@@ -408,8 +458,9 @@ __global__ __launch_bounds__(kCvtThreads) void bf16_convert_kernel(const float* 
 #pragma unroll
   for (int u = 0; u < kCvtGroups; ++u) {
     const uint32_t gi = g0 + u * kCvtThreads;
-    if (gi < ng)
-      dst[gi] = make_uint2(pack2(v[u].x, v[u].y), pack2(v[u].z, v[u].w));
+    if (gi < ng)   // non-temporal: the copy is read again only by later passes
+      __builtin_nontemporal_store(v2u{pack2(v[u].x, v[u].y), pack2(v[u].z, v[u].w)},
+                                  reinterpret_cast<v2u*>(dst) + gi);
     const float ax = fabsf(v[u].x), ay = fabsf(v[u].y), az = fabsf(v[u].z), aw = fabsf(v[u].w);
     mx = fmaxf(mx, fmaxf(fmaxf(ax, ay), fmaxf(az, aw)));
     const double dx = v[u].x, dy = v[u].y, dz = v[u].z, dw = v[u].w;
@@ -506,10 +557,11 @@ int stats_grid(int64_t A) { return static_cast<int>(A < 1024 ? A : 1024); }
 template <bool DOQ, bool HALF, int RBW>
 int launch_bf(const BfArgs& a, int grid, hipStream_t s) {
   auto k = bf16_stream_kernel<DOQ, HALF, RBW>;
-  const size_t lds = DOQ ? static_cast<size_t>(kBW) * kWaveLds +
-                               static_cast<size_t>(32) * (a.ldb1 + kB1Pad) * 2
-                         : 0;
-  if (lds > 0) {
+  // per-wave regions (transposed tile / TB partial, then the TA staging),
+  // plus B1^T for the dual pass
+  const size_t lds = static_cast<size_t>(kBW) * kWaveLds +
+                     (DOQ ? static_cast<size_t>(32) * (a.ldb1 + kB1Pad) * 2 : 0);
+  {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
@@ -535,6 +587,436 @@ int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
   // rows that start 8-byte aligned (ldy % 8 == 4) take the half-chunk loads
   if ((a.ldy & 7) != 0) return launch_bf_rbw<DOQ, true>(a, grid, s);
   return launch_bf_rbw<DOQ, false>(a, grid, s);
+}
+
+// ---------------------------------------------------------------------------
+// Column-split pass, for slabs of 7..16 column tiles (384 < I2 <= 1024).
+//
+// Wave w owns the column tiles w and w + 8 of the slab (CPW = 2; CPW = 1
+// when the slab has at most 8) and walks its 32-row blocks from top to
+// bottom, so the 8 waves read one row block, a contiguous span of the slab,
+// at a time.  For each 32 x 64 tile:
+//   TA partial += M_tile B2_tile       (K = the tile's columns; the wave's
+//                                      B2^T operands stay in registers)
+//   TB_j       += B1_block^T M_tile    (K = the block's rows, B operand from
+//                                      the transposed copy in the wave's LDS)
+// After its tiles of a row block a wave parks its TA partial in LDS; one
+// barrier per row block, then the partials are summed over the 8 waves in a
+// fixed order into the block's TA rows, which are stored and kept in LDS for
+//   C += B1_block^T TA_block           (FP32 MFMA: the mode-(N-1) product of
+//                                      TA inside the slab, K1 x K2 per slab)
+// TB is complete in each wave at the end (its columns, every row).  Both
+// passes of the method that need TA only through C (the core, and the
+// sketches of modes < N-1) read 3.6 MB instead of 120 MB at 1000^3.
+//
+// FIRST: the tiles come from the FP32 tensor.  The pass writes the BF16 copy
+// at scale 2^0 and the slab's max|Y| and ||Y||^2 (FP64, NaN if a value is
+// not finite), and multiplies the BF16-rounded values, so one read of Y
+// replaces the conversion pass and the first sweep's read of the copy.  The
+// rare slabs whose exponent puts them outside the window are converted again
+// afterwards and their products recomputed from the scaled copy
+// (only_scaled).
+struct CsArgs {
+  const float* Yf;        // FIRST: FP32 tensor [A][I1][I2]
+  uint16_t* Yb;           // BF16 copy [A][I1][ldy]: written (FIRST) or read
+  const int32_t* exps;    // per-slab exponent (not FIRST)
+  float* smax;            // FIRST: per-slab max|Y|
+  double* ssum;           // FIRST: per-slab sum of squares
+  int only_scaled;        // skip the slabs whose exponent is 0
+  int I1, I2, ldy, nct;
+  const uint16_t* B2t;    // [32][ldb2] BF16, zero beyond (K2, I2)
+  int ldb2, K2;
+  const uint16_t* B1t;    // [32][ldb1] BF16, zero beyond (K1, I1) (DOQ)
+  int ldb1, K1;
+  const float* B1;        // [I1][K1] FP32 (C)
+  float* TA;              // [A][I1][K2] or null
+  float* TB;              // [A][K1][I2] (DOQ)
+  float* C;               // [A][K1][K2] or null
+};
+
+constexpr int kCsRed = kBW * 32 * 32;   // floats of one TA-partial buffer
+constexpr int kYtBytes = kCT * kYtStride * 2;   // a wave's transposed tile
+constexpr int kStPitch = 144;                   // bytes per row of a staged BF16 tile (padded)
+constexpr int kStBytes = 32 * kStPitch;
+static_assert(kYtBytes % 16 == 0 && kStPitch % 16 == 0, "16-byte LDS accesses");
+
+// per-wave LDS of the column-split pass: the transposed tile (TB), then the
+// staged copy tile (FIRST)
+constexpr int cs_wave_bytes(bool first, bool doq) {
+  return (doq ? kYtBytes : 0) + (first ? kStBytes : 0);
+}
+
+template <bool F>
+struct CsTile {
+  v4u v[F ? 8 : 4];   // FP32: 2 x 4 values per 8-column chunk; BF16: 8 values
+};
+
+// Tile of step (row block t, column tile ct): lane (lr, g) takes row
+// 32 t + lr and, for chunk q, columns 64 ct + 16 q + 8 g .. + 7.  Masked
+// lanes (rows past the slab, tiles past the last) read past the buffer
+// range and get zeros.
+template <bool FIRST>
+__device__ __forceinline__ void cs_load(__amdgpu_buffer_rsrc_t rs, const CsArgs& a, int t,
+                                        int ct, int lr, int g, CsTile<FIRST>& T) {
+  const int r = t * 32 + lr;
+  const bool rok = r < a.I1 && ct < a.nct;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (FIRST) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = ct * kCT + 16 * q + 8 * g + 4 * h;
+        const bool ok = rok && c < a.I2;   // I2 % 4 == 0: all four or none
+        const int off = ok ? ((ok ? r : 0) * a.I2 + (ok ? c : 0)) * 4 : kOob;
+        T.v[2 * q + h] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      }
+    } else {
+      const int c = ct * kCT + 16 * q + 8 * g;
+      const bool ok = rok && c < a.I2;     // I2 % 8 == 0 or zero padding
+      const int off = ok ? ((ok ? r : 0) * a.ldy + (ok ? c : 0)) * 2 : kOob;
+      T.v[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    }
+  }
+}
+
+template <bool FIRST, bool DOQ, int CPW>
+__global__ __launch_bounds__(kBThreads) void bf16_cs_kernel(CsArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  constexpr int kSlots = FIRST ? 2 : 4;   // tiles in registers (FP32 tiles are twice as big)
+  constexpr int kTrip = 4;                // steps per loop trip
+  constexpr int kRpt = kTrip / CPW;       // row blocks per trip (even)
+  static_assert(kTrip % kSlots == 0 && kTrip % CPW == 0 && kRpt % 2 == 0, "static indexing");
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 31, g = lane >> 5;
+  // LDS: per-wave regions (transposed tile for TB, staged copy tile), two
+  // TA-partial buffers, two reduced TA blocks, statistics
+  constexpr int kWave = cs_wave_bytes(FIRST, DOQ);
+  uint16_t* yt = reinterpret_cast<uint16_t*>(smem + w * kWave);
+  char* stg = smem + w * kWave + (DOQ ? kYtBytes : 0);
+  float* red = reinterpret_cast<float*>(smem + kBW * kWave);
+  float* tab = red + 2 * kCsRed;
+  double* sred = reinterpret_cast<double*>(tab + 2 * 1024);
+  float* mred = reinterpret_cast<float*>(sred + kBW);
+
+  const int64_t slab = blockIdx.x;
+  int e = 0;
+  if constexpr (!FIRST) {
+    e = a.exps[slab];
+    if (a.only_scaled && e == 0) return;   // workgroup-uniform
+  }
+  const float up = ldexpf(1.0f, e);
+  const int nrb = (a.I1 + 31) / 32;
+  const int nsteps = (nrb * CPW + kTrip - 1) / kTrip * kTrip;   // masked steps past the end
+  const int64_t slab_b = static_cast<int64_t>(a.I1) * a.ldy;
+  const __amdgpu_buffer_rsrc_t rs =
+      FIRST ? slab_rsrc(a.Yf + slab * a.I1 * a.I2, static_cast<int64_t>(a.I1) * a.I2 * 4)
+            : slab_rsrc(a.Yb + slab * slab_b, slab_b * 2);
+  // C is made by the passes over the copy only (the FIRST pass has no
+  // registers to spare for it)
+  const bool wantC = !FIRST && a.C != nullptr, wantA = a.TA != nullptr;
+
+  // operands that do not change along the slab, then the first row
+  // block's, then the ring: the loop head's wait counts then hold for the
+  // entry as for the back edge
+  v8bf b2[CPW][4];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int ct = w + kBW * j < a.nct ? w + kBW * j : 0;   // masked tiles: any valid row
+    load_b2t(a.B2t, a.ldb2, ct, lr, g, b2[j]);
+  }
+  // B1^T of row block t (TB's A operand), loaded one row block ahead, and
+  // B1 rows of block t (C's A operand, rows 4w .. 4w+3), loaded at the
+  // block's first step and used at the end of the next block: slot t % 2
+  uint4 b1r[2][2];
+  float b1c[2][2];
+  auto load_b1t = [&](int t, int slot) __attribute__((always_inline)) {
+    const int tc = t < nrb ? t : nrb - 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      b1r[slot][h] = *reinterpret_cast<const uint4*>(
+          a.B1t + static_cast<int64_t>(lr) * a.ldb1 + tc * 32 + 16 * h + 8 * g);
+  };
+  auto load_b1c = [&](int t, int slot) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const int row = t * 32 + 4 * w + 2 * t2 + g;
+      const bool ok = wantC && row < a.I1 && lr < a.K1;
+      b1c[slot][t2] = ok ? a.B1[static_cast<int64_t>(ok ? row : 0) * a.K1 + lr] : 0.0f;
+    }
+  };
+  if constexpr (DOQ) load_b1t(0, 0);
+  __builtin_amdgcn_sched_barrier(0);
+  CsTile<FIRST> ring[kSlots];
+#pragma unroll
+  for (int k = 0; k + 1 < kSlots; ++k)
+    cs_load<FIRST>(rs, a, k / CPW, w + kBW * (k % CPW), lr, g, ring[k]);
+  __builtin_amdgcn_sched_barrier(0);
+
+  v16f accA, accC;
+  v16f accB[CPW][2];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    accA[v] = 0.0f;
+    accC[v] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      accB[j][0][v] = 0.0f;
+      accB[j][1][v] = 0.0f;
+    }
+  }
+  uint32_t mxb = 0;   // FIRST: the lane's largest |Y| bit pattern
+  double sq = 0.0;
+
+  // C += B1_block^T TA_block for row block t (rows 4w .. 4w+3 of the block)
+  auto c_step = [&](int slot, int buf) __attribute__((always_inline)) {
+    const float* tb = tab + buf * 1024;
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2)
+      accC = __builtin_amdgcn_mfma_f32_32x32x2f32(b1c[slot][t2],
+                                                  tb[(4 * w + 2 * t2 + g) * 32 + lr], accC,
+                                                  0, 0, 0);
+  };
+
+  for (int s0 = 0; s0 < nsteps; s0 += kTrip) {
+    static_for<kTrip>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      constexpr int j = u % CPW;              // column tile of the wave
+      constexpr int tl = u / CPW;             // row block within the trip
+      constexpr int par = tl % 2;             // parity of the row block
+      const int t = s0 / CPW + tl;
+      const int ct = w + kBW * j;
+      if constexpr (j == 0) {
+        if constexpr (DOQ) load_b1t(t + 1, par ^ 1);
+        if constexpr (!FIRST) load_b1c(t, par);
+      }
+      {
+        constexpr int up_ = u + kSlots - 1;   // step whose tile is loaded now
+        const int sp = s0 + up_;
+        cs_load<FIRST>(rs, a, sp / CPW, w + kBW * (up_ % CPW), lr, g,
+                       ring[up_ % kSlots]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      CsTile<FIRST>& cur = ring[u % kSlots];
+      uint4 yb[4];
+      if constexpr (FIRST) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float x[8];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            x[4 * h + 0] = __uint_as_float(cur.v[2 * q + h].x);
+            x[4 * h + 1] = __uint_as_float(cur.v[2 * q + h].y);
+            x[4 * h + 2] = __uint_as_float(cur.v[2 * q + h].z);
+            x[4 * h + 3] = __uint_as_float(cur.v[2 * q + h].w);
+          }
+          yb[q] = make_uint4(pack2_hw(x[0], x[1]), pack2_hw(x[2], x[3]),
+                             pack2_hw(x[4], x[5]), pack2_hw(x[6], x[7]));
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t ab = __float_as_uint(x[k]) & 0x7fffffffu;
+            mxb = mxb > ab ? mxb : ab;
+            sq = fma(static_cast<double>(x[k]), static_cast<double>(x[k]), sq);
+          }
+          // keep the statistics here: left alone, the compiler sinks them
+          // to the end of the loop trip and keeps four tiles live for them
+          asm volatile("" : "+v"(mxb), "+v"(sq));
+        }
+        // the copy (rows of the slab, every column of the tile: the
+        // padding past I2 was loaded as zeros).  The tile goes through the
+        // wave's LDS so that each store instruction writes 8 whole rows of
+        // 128 bytes; stored from the MFMA layout (32 rows x 32 bytes per
+        // instruction) the copy's writes ran at a third of the bandwidth.
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<uint4*>(stg + lr * kStPitch + 32 * q + 16 * g) = yb[q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ct < a.nct) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rl = 8 * i + (lane >> 3), r = t * 32 + rl;
+            const v4u v = *reinterpret_cast<const v4u*>(stg + rl * kStPitch + 16 * (lane & 7));
+            if (r < a.I1)
+              __builtin_nontemporal_store(
+                  v, reinterpret_cast<v4u*>(a.Yb + slab * slab_b + static_cast<int64_t>(r) * a.ldy +
+                                            ct * kCT + 8 * (lane & 7)));
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          yb[q] = make_uint4(cur.v[q].x, cur.v[q].y, cur.v[q].z, cur.v[q].w);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yb[q]), b2[j][q], accA, 0, 0, 0);
+        if constexpr (DOQ) {
+          const uint32_t wds[4] = {yb[q].x, yb[q].y, yb[q].z, yb[q].w};
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            yt[(16 * q + 8 * g + k) * kYtStride + lr] =
+                static_cast<uint16_t>(wds[k >> 1] >> (16 * (k & 1)));
+        }
+      }
+      if constexpr (DOQ) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int sh = 0; sh < 2; ++sh) {
+            const v8bf yc = as_v8bf(*reinterpret_cast<const uint4*>(
+                yt + (32 * sh + lr) * kYtStride + 16 * h + 8 * g));
+            accB[j][sh] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(b1r[par][h]), yc,
+                                                                accB[j][sh], 0, 0, 0);
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      if constexpr (j == CPW - 1) {
+        // row block t done in this wave: park the TA partial, then sum the
+        // 8 partials (fixed order) into the block's TA rows
+        float* rp = red + par * kCsRed + w * 1024;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          rp[(8 * (v / 4) + 4 * g + (v % 4)) * 32 + lr] = accA[v];
+          accA[v] = 0.0f;
+        }
+        __syncthreads();
+        // the previous block's C product: its TA block was completed
+        // before this barrier
+        if constexpr (!FIRST)
+          if (wantC && t >= 1) c_step(par ^ 1, par ^ 1);
+        for (int o = threadIdx.x; o < 1024; o += kBThreads) {
+          float sum = 0.0f;
+#pragma unroll
+          for (int ww = 0; ww < kBW; ++ww) sum += red[par * kCsRed + ww * 1024 + o];
+          sum *= up;
+          if (wantC) tab[par * 1024 + o] = sum;
+          const int row = t * 32 + o / 32, k = o % 32;
+          if (wantA && row < a.I1 && k < a.K2)
+            __builtin_nontemporal_store(sum, a.TA + (slab * a.I1 + row) * a.K2 + k);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  }
+  // the last row block's C product, then C summed over the waves
+  const int tlast = nsteps / CPW - 1;
+  __syncthreads();
+  if constexpr (!FIRST)
+    if (wantC) c_step(tlast & 1, tlast & 1);
+  if constexpr (FIRST) {
+    // a pattern above FLT_MAX's is an Inf or a NaN
+    if (mxb > 0x7f7fffffu) sq = __longlong_as_double(0x7ff8000000000000LL);
+    sq = wave_sum(sq);
+    const float mx = wave_max(__uint_as_float(mxb > 0x7f7fffffu ? 0x7f800000u : mxb));
+    if (lane == 0) {
+      sred[w] = sq;
+      mred[w] = mx;
+    }
+  }
+  if (!FIRST && wantC) {
+    float* rp = red + w * 1024;   // every reduction of the loop has finished
+#pragma unroll
+    for (int v = 0; v < 16; ++v) rp[(8 * (v / 4) + 4 * g + (v % 4)) * 32 + lr] = accC[v];
+  }
+  __syncthreads();
+  if (wantC) {
+    for (int o = threadIdx.x; o < 1024; o += kBThreads) {
+      const int k1 = o / 32, k2 = o % 32;
+      float sum = 0.0f;
+#pragma unroll
+      for (int ww = 0; ww < kBW; ++ww) sum += red[ww * 1024 + o];
+      if (k1 < a.K1 && k2 < a.K2)
+        __builtin_nontemporal_store(sum, a.C + (slab * a.K1 + k1) * a.K2 + k2);
+    }
+  }
+  if constexpr (FIRST) {
+    if (threadIdx.x == 0) {
+      float m = mred[0];
+      double t = sred[0];
+#pragma unroll
+      for (int ww = 1; ww < kBW; ++ww) {
+        m = fmaxf(m, mred[ww]);
+        t += sred[ww];
+      }
+      a.smax[slab] = m;
+      a.ssum[slab] = t;
+    }
+  }
+  if constexpr (DOQ) {
+    // TB: the slab's K1 x I2 block is one contiguous span of the output.
+    // Staged through LDS 16 rows at a time (the TA-partial buffers are
+    // free), then written with 16-byte stores in order.
+    float* tbs = red;   // [16][1024]
+    static_assert(2 * kCsRed >= 16 * 1024, "TB staging fits");
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();   // the previous use of the buffers is over
+#pragma unroll
+      for (int j = 0; j < CPW; ++j) {
+        const int ct = w + kBW * j;
+        if (ct < a.nct) {
+#pragma unroll
+          for (int sh = 0; sh < 2; ++sh)
+#pragma unroll
+            for (int v = 8 * half; v < 8 * half + 8; ++v) {
+              const int k1l = 8 * (v / 4) + 4 * g + (v % 4) - 16 * half;
+              tbs[k1l * 1024 + ct * kCT + 32 * sh + lr] = accB[j][sh][v] * up;
+            }
+        }
+      }
+      __syncthreads();
+      const int rows = a.K1 - 16 * half < 16 ? a.K1 - 16 * half : 16;
+      if (rows > 0) {
+        float* dst = a.TB + (slab * a.K1 + 16 * half) * a.I2;   // I2 % 4 == 0: aligned
+        const int cnt = rows * a.I2;
+        for (int o = 4 * threadIdx.x; o < cnt; o += 4 * kBThreads) {
+          const int k1l = o / a.I2, col = o - k1l * a.I2;
+          __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(tbs + k1l * 1024 + col),
+                                      reinterpret_cast<v4f*>(dst + o));
+        }
+      }
+    }
+  }
+}
+
+// LDS of the column-split pass
+size_t cs_lds_bytes(bool first, bool doq) {
+  return static_cast<size_t>(kBW) * cs_wave_bytes(first, doq) +
+         (2 * kCsRed + 2 * 1024) * sizeof(float) + kBW * (sizeof(double) + sizeof(float));
+}
+
+template <bool FIRST, bool DOQ, int CPW>
+int launch_cs(const CsArgs& a, int64_t grid, hipStream_t s) {
+  auto k = bf16_cs_kernel<FIRST, DOQ, CPW>;
+  const size_t lds = cs_lds_bytes(FIRST, DOQ);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds));
+  if (e != hipSuccess) return hip_fail(e, "bf16 column-split LDS attribute");
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(grid)), dim3(kBThreads), lds, s, a);
+  RT_LAUNCH_CHECK("bf16 column-split pass");
+  return kOk;
+}
+
+template <bool FIRST, bool DOQ>
+int launch_cs_cpw(const CsArgs& a, int64_t grid, hipStream_t s) {
+  if (a.nct <= kBW) return launch_cs<FIRST, DOQ, 1>(a, grid, s);
+  return launch_cs<FIRST, DOQ, 2>(a, grid, s);
+}
+
+int launch_cs_first(const CsArgs& a, bool doq, bool first, int64_t grid, hipStream_t s) {
+  if (first) return doq ? launch_cs_cpw<true, true>(a, grid, s) : launch_cs_cpw<true, false>(a, grid, s);
+  return doq ? launch_cs_cpw<false, true>(a, grid, s) : launch_cs_cpw<false, false>(a, grid, s);
 }
 
 }  // namespace
@@ -591,18 +1073,35 @@ size_t bf16_stream_workspace_bytes(int64_t A, int64_t I1, int64_t I2) {
   return bf16_ws_layout(nullptr, A, I1, I2).bytes + 512;
 }
 
-int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2) {
+namespace {
+
+// The column-split pass takes slabs of 7..16 column tiles whose rows start
+// 16-byte aligned (the padded copy, or a caller's BF16 tensor with
+// I2 % 8 == 0) and whose FP32 and BF16 slabs stay below the masked-load
+// offset; it has no limit on the number of rows.
+bool cs_ok(int64_t I1, int64_t I2, int64_t ldy) {
+  const int64_t nct = (I2 + kCT - 1) / kCT;
+  return nct >= 7 && nct <= 2 * kBW && ldy % 8 == 0 && I1 * ldy * 2 <= kOob - 64 &&
+         I1 * I2 * 4 <= kOob - 64;
+}
+
+}  // namespace
+
+int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2, bool bf16_input) {
+  const int64_t ldy = bf16_input ? I2 : bf16_copy_ld(I2);
+  const bool cs = cs_ok(I1, I2, ldy);
   // a slab of the padded copy must stay below the masked-load offset
-  if (I1 > kMaxI1 || I2 % 4 != 0 || K1 > 32 || K2 > 32 ||
+  if ((I1 > kMaxI1 && !cs) || I2 % 4 != 0 || K1 > 32 || K2 > 32 ||
       I1 * bf16_copy_ld(I2) * 2 > kOob - 64) {
-    set_error("BF16 streaming pass needs I_{N-1} <= %d, I_N %% 4 == 0, "
-              "I_{N-1} I_N < 2^30 and sketch widths <= 32 (got %lld, %lld, %d, %d)",
+    set_error("BF16 streaming pass needs I_{N-1} <= %d (or 384 < I_N <= 1024), "
+              "I_N %% 4 == 0, I_{N-1} I_N < 2^30 and sketch widths <= 32 "
+              "(got %lld, %lld, %d, %d)",
               kMaxI1, (long long)I1, (long long)I2, K1, K2);
     return kErrUnsupported;
   }
   // one-dimensional grids: A slabs (streaming passes), A x blocks per slab
   // (conversion)
-  if (A * cvt_blocks(I1, I2) > 0x7fffffffLL) {
+  if (A > 0x7fffffffLL || (!cs && A * cvt_blocks(I1, I2) > 0x7fffffffLL)) {
     set_error("BF16 conversion: %lld slabs of %lld x %lld exceed 2^31 - 1 blocks",
               (long long)A, (long long)I1, (long long)I2);
     return kErrUnsupported;
@@ -610,12 +1109,24 @@ int bf16_check_shape(int64_t A, int64_t I1, int64_t I2, int K1, int K2) {
   return kOk;
 }
 
-// One BF16 streaming pass.  first: statistics + FP32 read + BF16 write
-// (unless the input is already BF16).  B1 == nullptr: TA only.
+// One BF16 streaming pass: TA = Y x_N B2^T (when TA is given), TB = Y
+// x_{N-1} B1^T (when TB is given) and C = TA x_{N-1} B1^T per slab (when C
+// is given and the slab shape takes the column-split pass: *c_done tells;
+// without TB such a pass does not write TA).
+// first: the pass also takes the statistics and, for an FP32 input, makes
+// the BF16 copy.
 int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
-                     const float* B1, int K1, float* TA, float* TB, int stage,
-                     hipStream_t s) {
-  RT_TRY(bf16_check_shape(c.A, c.I1, c.I2, B1 ? K1 : 0, K2));
+                     const float* B1, int K1, float* TA, float* TB, float* C, bool* c_done,
+                     int stage, hipStream_t s) {
+  RT_TRY(bf16_check_shape(c.A, c.I1, c.I2, B1 ? K1 : 0, K2, c.bf16_input));
+  const bool cs = cs_ok(c.I1, c.I2, c.ldy);
+  if (c_done) *c_done = false;
+  if (!cs) C = nullptr;
+  if (C && !TB) TA = nullptr;   // the core pass needs TA only through C
+  if (!TA && !C) {
+    set_error("BF16 streaming pass without an output");
+    return kErrInvalid;
+  }
   const int64_t l1 = (c.I1 + 63) / 64 * 64, l2 = (c.I2 + 63) / 64 * 64;
   char* base = static_cast<char*>(c.ws) + 1024 * sizeof(double) + 256;
   const BfWs w = bf16_ws_layout(base, c.A, c.I1, c.I2);
@@ -633,11 +1144,69 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   hipLaunchKernelGGL(prep_bt_kernel, dim3((32 * l2 + 255) / 256), dim3(256), 0, s, B2,
                      static_cast<int>(c.I2), K2, B2t, static_cast<int>(l2));
   RT_LAUNCH_CHECK("prep B2");
-  if (B1) {
+  if (TB) {
     hipLaunchKernelGGL(prep_bt_kernel, dim3((32 * l1 + 255) / 256), dim3(256), 0, s,
                        B1, static_cast<int>(c.I1), K1, B1t, static_cast<int>(l1));
     RT_LAUNCH_CHECK("prep B1");
   }
+
+  if (cs) {
+    CsArgs a{};
+    a.Yf = static_cast<const float*>(c.y);
+    a.Yb = c.ybf16;
+    a.exps = exps;
+    a.smax = w.pmax;    // one value per slab
+    a.ssum = w.psum;
+    a.I1 = static_cast<int>(c.I1);
+    a.I2 = static_cast<int>(c.I2);
+    a.ldy = static_cast<int>(c.ldy);
+    a.nct = static_cast<int>((c.I2 + kCT - 1) / kCT);
+    a.B2t = B2t;
+    a.ldb2 = static_cast<int>(l2);
+    a.K2 = K2;
+    a.B1t = B1t;
+    a.ldb1 = static_cast<int>(l1);
+    a.K1 = B1 ? K1 : 0;
+    a.B1 = B1;
+    a.TA = TA;
+    a.TB = TB;
+    a.C = C;
+    if (first && !c.bf16_input) {
+      // one read of Y: the BF16 copy at scale 2^0, the statistics and the
+      // products of the rounded values; then the slab exponents, and the
+      // slabs that need a scale are converted again and recomputed.  This
+      // pass makes no C (TA is written instead).
+      if (!TA) {
+        set_error("the first BF16 pass writes TA");
+        return kErrInvalid;
+      }
+      C = nullptr;
+      a.C = nullptr;
+      {
+        ProfScope ps(stage, s);
+        RT_TRY(launch_cs_first(a, TB != nullptr, true, c.A, s));
+      }
+      ProfScope ps(kStageStats, s);
+      hipLaunchKernelGGL(slab_finish_kernel, dim3(static_cast<unsigned>(c.A)), dim3(256), 0, s,
+                         w.pmax, w.psum, 1, exps, w.slab_sum);
+      RT_LAUNCH_CHECK("slab finish");
+      hipLaunchKernelGGL(bf16_rescale_kernel, dim3(static_cast<unsigned>(c.A)), dim3(256), 0,
+                         s, static_cast<const float*>(c.y), c.ybf16, exps,
+                         static_cast<int>(c.I1), static_cast<int>(c.I2),
+                         static_cast<int>(c.ldy));
+      RT_LAUNCH_CHECK("bf16 rescale");
+      a.only_scaled = 1;
+      RT_TRY(launch_cs_first(a, TB != nullptr, false, c.A, s));
+      RT_TRY(launch_sum_partials(w.slab_sum, static_cast<int>(c.A), c.norm_out, c.nonfinite,
+                                 s));
+    } else {
+      ProfScope ps(stage, s);
+      RT_TRY(launch_cs_first(a, TB != nullptr, false, c.A, s));
+    }
+    if (c_done) *c_done = C != nullptr;
+    return kOk;
+  }
+
   if (first && !c.bf16_input) {
     // the BF16 copy (padded rows) and the statistics in one read of Y, then
     // the slab exponents and the rare slabs that need a scale; every
@@ -674,12 +1243,12 @@ int bf16_stream_pass(const StreamCtx& c, bool first, const float* B2, int K2,
   a.K2 = K2;
   a.B1t = B1t;
   a.ldb1 = static_cast<int>(l1);
-  a.K1 = B1 ? K1 : 0;
+  a.K1 = TB ? K1 : 0;
   a.TA = TA;
   a.TB = TB;
   const int grid = static_cast<int>(c.A);   // one workgroup per slab
   ProfScope ps(stage, s);
-  if (B1) return launch_bf_half<true>(a, grid, s);
+  if (TB) return launch_bf_half<true>(a, grid, s);
   return launch_bf_half<false>(a, grid, s);
 }
 

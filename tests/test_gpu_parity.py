@@ -273,14 +273,15 @@ def test_tucker_gauss_seidel_bf16_vs_fp64_oracle(P, sweeps):
     assert eG <= 4 * 2.0 ** -9 * nY / np.linalg.norm(ref["G"]) + 1e-4
 
 
+@pytest.mark.parametrize("dims", [(20, 21, 24), (6, 40, 520)])
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
-def test_tucker_nonfinite_flag(P, precision, bad):
-    """A NaN or Inf anywhere in Y sets the info flag (both streaming forms)
-    and the Python wrapper raises."""
-    d = synth.case_tucker(304, (20, 21, 24), (3, 3, 3), 30.0, (5, 5, 5))
+def test_tucker_nonfinite_flag(P, precision, bad, dims):
+    """A NaN or Inf anywhere in Y sets the info flag (both streaming forms,
+    narrow and wide slabs) and the Python wrapper raises."""
+    d = synth.case_tucker(304, dims, (3, 3, 3), 30.0, (5, 5, 5))
     Y = synth.f32(d["Y"]).copy()
-    Y[3, 4, 5] = bad
+    Y[min(3, dims[0] - 1), 4, 5] = bad
     args = (dev(Y), [dev(synth.f32(o)) for o in d["omegas"]],
             [[dev(synth.f32(o)) for o in d["omega_tildes"][0]]])
     out = P.tucker_rand(*args, ranks=(3, 3, 3), sweeps=1, precision=precision,
@@ -290,12 +291,13 @@ def test_tucker_nonfinite_flag(P, precision, bad):
         P.tucker_rand(*args, ranks=(3, 3, 3), sweeps=1, precision=precision)
 
 
+@pytest.mark.parametrize("dims", [(6, 20, 24), (6, 20, 520)])
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
-def test_tucker_largest_finite_values_are_finite(P, precision):
+def test_tucker_largest_finite_values_are_finite(P, precision, dims):
     """Values of magnitude FLT_MAX are finite: no flag, and ||Y||^2 is the
     FP64 sum of squares (FLT_MAX^2 ~ 1.2e77 is an ordinary FP64 number).
     In the precision form that slab is scaled by 2^-127 before rounding."""
-    d = synth.case_tucker(308, (6, 20, 24), (3, 3, 3), 30.0, (5, 5, 5))
+    d = synth.case_tucker(308, dims, (3, 3, 3), 30.0, (5, 5, 5))
     Y = synth.f32(d["Y"]).copy()
     fmax = np.finfo(np.float32).max
     Y[2, 4, 5] = fmax
