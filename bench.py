@@ -67,6 +67,9 @@ def parse():
                     help="skip the 10^4-per-mode FFCP-HALS side measurement")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the Algorithm 2 side measurement")
+    ap.add_argument("--tucker-only", action="store_true",
+                    help="time only the Tucker stage of the chosen form (short "
+                         "runs under a profiler) and print its stage times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
                     help="also run K plain device copies of Y (HBM counter "
                          "calibration under a profiler)")
@@ -76,7 +79,8 @@ def parse():
 # source file of each kernel whose HBM traffic is stored in profiles/
 KERNEL_SOURCE = {"dual_f32_kernel": "stream.hip",
                  "bf16_convert_kernel": "stream_bf16.hip",
-                 "bf16_stream_kernel": "stream_bf16.hip"}
+                 "bf16_stream_kernel": "stream_bf16.hip",
+                 "bf16_cs_kernel": "stream_bf16.hip"}
 
 
 def source_digest(kernel):
@@ -365,6 +369,35 @@ def errors_vs_oracle(res, forms, ores, Y64, R, tol, max_it, rms_bf16=None):
     return out
 
 
+def tucker_only(args, P, torch, Y, om_d, omt_d, ranks, ybf16):
+    """The Tucker stage alone (two sweeps in the chosen form), then the
+    calibration copies: the command the kernel-trace and counter profiles
+    under profiles/ were taken with."""
+    kw = dict(ranks=ranks, sweeps=2, precision=args.precision, ybf16=ybf16)
+    out = None
+    for _ in range(max(args.warmup, 1)):
+        out = P.tucker_rand(Y, om_d, omt_d, workspace=out and out["workspace"], **kw)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = P.tucker_rand(Y, om_d, omt_d, workspace=out["workspace"], sync=False, **kw)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    prof = P.profile_read()
+    P.profile_enable(False)
+    if args.copy_calibration:
+        dst = torch.empty(Y.shape, dtype=torch.float64, device=Y.device)
+        for _ in range(args.copy_calibration):
+            dst.copy_(Y)
+        torch.cuda.synchronize()
+        del dst
+    print(json.dumps({"tucker_only": args.precision, "steps": args.steps,
+                      "ms_per_step": round(wall, 4),
+                      "stages_ms": {k: round(v[0] / max(v[1], 1), 4)
+                                    for k, v in prof.items() if v[1] > 0}}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -394,6 +427,10 @@ def main():
     omt_d = [[torch.from_numpy(o).to(dev) for o in lst] for lst in omt32]
     ybf16 = torch.empty(P.bf16_copy_shape(dims), dtype=torch.int16, device=dev)
     torch.cuda.synchronize()
+
+    if args.tucker_only:
+        tucker_only(args, P, torch, Y, om_d, omt_d, ranks, ybf16)
+        return
 
     net, learned = None, None
     if args.train_cores > 0:
@@ -465,26 +502,45 @@ def main():
                                   "gbs": round(b * n / t / 1e9, 1),
                                   "hbm_frac": round(b * n / t / 1e9 / HBM_PEAK_GBS, 4)}
     else:
+        # bytes each pass must move: Y (FP32 in the first pass, BF16 after),
+        # the BF16 copy written by a fused first pass, the FP32 outputs TA
+        # (A I_2 R~_3), TB (A R~_2 I_3) and C (A R~_2 R~_3)
+        A_, I1_, I2_ = n // (dims[-2] * dims[-1]), dims[-2], dims[-1]
+        ta, tb, cc = 4 * A_ * I1_ * rt, 4 * A_ * rt * I2_, 4 * A_ * rt * rt
+        fused = per_launch("convert") is None   # wide slabs: conversion in the first pass
+        if fused:
+            passes = (("first_pass", 6 * n + ta + tb,
+                       "bf16_cs_kernel<true,true,2>: FP32 Y read once; BF16 copy, "
+                       "TA = Y x_3 Omega_3^T and TB = Y x_2 Omega_2^T"),
+                      ("sweep_pass", 2 * n + ta + tb + cc,
+                       "bf16_cs_kernel<false,true,2>: second sweep from the copy; TA, TB "
+                       "and C = TA x_2 Q_2^T"),
+                      ("core_pass", 2 * n + cc,
+                       "bf16_cs_kernel<false,false,2>: core pass, C = Y x_3 Q_3^T x_2 Q_2^T "
+                       "per slab"))
+        else:
+            passes = (("convert", 6 * n, "bf16_convert_kernel (FP32 read, BF16 write)"),
+                      ("first_pass", 2 * n + ta + tb, "bf16_stream_kernel, first sweep"),
+                      ("sweep_pass", 2 * n + ta + tb, "bf16_stream_kernel, second sweep"),
+                      ("core_pass", 2 * n + ta, "bf16_stream_kernel, core pass"))
+        kname = "bf16_cs_kernel" if fused else "bf16_stream_kernel"
+        kbytes = dict((st, b) for st, b, _ in passes)["first_pass"]
         t_k = per_launch("first_pass")
-        kbytes = 2 * n
         achieved = kbytes / t_k / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic("bf16_stream_kernel", workload),
-                "kernel": ("bf16_stream_kernel (first sweep: Y x_3 Omega_3^T and "
-                           "Y x_2 Omega_2^T from the BF16 copy, one read)"),
+                "traffic": stored_traffic(kname, workload),
+                "kernel": dict((st, k) for st, _, k in passes)["first_pass"],
+                "bytes_per_launch": kbytes,
                 "avg_ms": round(t_k * 1e3, 4)}
-        for stage, b, kname in (("convert", 6, "bf16_convert_kernel (FP32 read, BF16 write)"),
-                                ("first_pass", 2, "bf16_stream_kernel, first sweep"),
-                                ("sweep_pass", 2, "bf16_stream_kernel, power sweep"),
-                                ("core_pass", 2, "bf16_stream_kernel, core pass")):
+        for stage, b, kn in passes:
             t = per_launch(stage)
             if t:
-                kernels[stage] = {"kernel": kname, "bytes": b * n,
+                kernels[stage] = {"kernel": kn, "bytes": b,
                                   "avg_ms": round(t * 1e3, 4),
-                                  "gbs": round(b * n / t / 1e9, 1),
-                                  "hbm_frac": round(b * n / t / 1e9 / HBM_PEAK_GBS, 4)}
+                                  "gbs": round(b / t / 1e9, 1),
+                                  "hbm_frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
 
     if args.copy_calibration:
         # plain elementwise copy kernel of known traffic (reads 4 B, writes
