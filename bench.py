@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--tucker-only", action="store_true",
                     help="time only the Tucker stage of the chosen form (short "
                          "runs under a profiler) and print its stage times")
+    ap.add_argument("--hals-only", action="store_true",
+                    help="run only the FFCP-HALS fits on the 10^4-per-mode workload (short "
+                         "runs under a profiler) and print their record")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
                     help="also run K plain device copies of Y (HBM counter "
                          "calibration under a profiler)")
@@ -414,6 +417,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.hals_only:
+        print(json.dumps({"hals_1e4_4way": run_hals_1e4(P, torch, synth, args.steps)}),
+              flush=True)
+        return
 
     I, R, rt = args.size, 20, 30
     dims = (I, I, I)

@@ -285,7 +285,11 @@ typedef struct {
 /* Written by the device. */
 typedef struct {
   int32_t iterations; /* iterations run                                  */
-  int32_t converged;  /* 1 if the tolerance test stopped the loop        */
+  int32_t converged;  /* 1 if the tolerance test stopped the loop; -1
+                         if a grid barrier of the multi-workgroup form
+                         gave up (results undefined; not expected: the
+                         cooperative launch keeps every workgroup
+                         resident)                                       */
   int32_t ridged;     /* 1 if a Cholesky failed and the ridge
                          1e-12 tr(T)/R was added                         */
   int32_t init_used;  /* RT_INIT_COEFF_GUARDED: 1 if the caller's start
@@ -307,6 +311,11 @@ int rt_ffcp_workspace(const rt_ffcp_desc* desc, size_t* bytes);
  * Fit after mode N in closed form: ||Yt||^2 - 2 sum(H_N * V_N) +
  * 1^T (hadamard_p A_p^T A_p) 1 (FP64).  Arithmetic is FP64 on the device;
  * U, G, A_init are read as FP32 and the outputs written as FP32.
+ * Execution: unconstrained ALS without S_c runs in the compressed space in
+ * one workgroup; the other rules run in one workgroup too, or, when the
+ * longest mode has 2048 rows or more, in one cooperative launch of up to
+ * 256 workgroups (each owning a chunk of every mode's rows, cross products
+ * summed from per-workgroup partials in a fixed order).
  *
  *   U        host array of N device FP32 matrices I_n x R_n.
  *   G        device FP32 core R_1 x ... x R_N.
@@ -337,7 +346,7 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
  * library on each GPU (held until the process ends), so the call allocates
  * nothing.  Problems whose rt_ffcp_workspace exceeds 32 MiB are rejected
  * with RT_ERR_UNSUPPORTED before anything is enqueued (R = R_n = 20 needs
- * about 1.3 MiB at I_n = 1000 in 3 modes and 17.5 MiB at I_n = 10^4 in 4).  Every call on one GPU shares
+ * about 2.9 MiB at I_n = 1000 in 3 modes and 19.0 MiB at I_n = 10^4 in 4).  Every call on one GPU shares
  * that GPU's array: calls that overlap in time on one GPU (other streams or
  * host threads) race and must be serialized by the caller; calls in order on
  * one stream are safe.  Nothing in the array needs to start at zero.

@@ -385,6 +385,9 @@ def ffcp(U, G, R, update="als", A_init=None, init=None, pad=None, max_it=1000,
     if sync:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]
+        if int(inf["converged"]) < 0:
+            raise RtError(-1, "FFCP: a grid barrier of the multi-workgroup form gave up "
+                              "(results undefined)")
         out["info"] = inf
         if ft is not None:
             out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]
@@ -475,6 +478,9 @@ def ffcp_noalloc(U, G, R, update="als", A_init=None, init=None, pad=None, max_it
     if sync:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         inf = np.frombuffer(info.cpu().numpy().tobytes(), FFCP_INFO_DTYPE)[0]
+        if int(inf["converged"]) < 0:
+            raise RtError(-1, "FFCP: a grid barrier of the multi-workgroup form gave up "
+                              "(results undefined)")
         out["info"] = inf
         if ft is not None:
             out["fits"] = ft.cpu().numpy()[: int(inf["iterations"])]

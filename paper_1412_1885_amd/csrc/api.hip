@@ -548,6 +548,9 @@ struct FfcpPlan {
   double* W1;
   double* W2;
   double* scal;
+  double* part;
+  unsigned* bar;
+  double* nrm;
   double* Vinit[RT_MAX_MODES];
   double* Valt[RT_MAX_MODES];
   double* hgram[RT_MAX_MODES];
@@ -584,6 +587,13 @@ struct FfcpPlan {
     W1 = ar.take<double>(wsize);
     W2 = ar.take<double>(wsize);
     scal = ar.take<double>(8 + RT_MAX_SKETCH);
+    // per-workgroup partial sums of the multi-workgroup kernel: U_n^T A_n
+    // with A_n^T A_n, U_n^T U_n, column norms
+    int64_t nout = static_cast<int64_t>(Rmax) * R + static_cast<int64_t>(R) * R;
+    if (static_cast<int64_t>(Rmax) * Rmax > nout) nout = static_cast<int64_t>(Rmax) * Rmax;
+    part = ar.take<double>(ffcp_grid_part_doubles(nout));
+    bar = ar.take<unsigned>(64);
+    nrm = ar.take<double>(static_cast<int64_t>(N) * R);
     return ar.need;
   }
 };
@@ -811,6 +821,9 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
   a.W1 = P.W1;
   a.W2 = P.W2;
   a.scal = P.scal;
+  a.part = P.part;
+  a.bar = P.bar;
+  a.nrm = P.nrm;
   if (coeff) {
     // the caller's coefficient matrices (FP32 R_n x R) as the FP64 start
     for (int n = 0; n < N; ++n)

@@ -144,8 +144,13 @@ struct FfcpArgs {
   double* W1;      // prod R / min R_p * R  (MTTKRP partial)
   double* W2;      // same size
   double* scal;    // scalars
+  double* part;    // partial sums of the multi-workgroup kernel (null: one workgroup)
+  unsigned* bar;   // its grid barrier: [0] arrivals, [1] failure flag (zeroed per launch)
+  double* nrm;     // its column norms of each factor's last normalization (N x R)
 };
 int launch_ffcp(const FfcpArgs& a, hipStream_t s);
+// doubles of FfcpArgs::part for cross products of at most nout_max outputs
+int64_t ffcp_grid_part_doubles(int64_t nout_max);
 // ALS without the l1 term, run in the compressed space (one workgroup, LDS
 // resident); kErrUnsupported when the problem does not fit.
 bool ffcp_als_core_applicable(const FfcpArgs& a);
