@@ -15,11 +15,15 @@
 //
 // One workgroup runs the whole loop (the work per step is tiny and serial in
 // the modes); the core (FP32, promoted on read), the MTTKRP intermediates and
-// all R x R / R_n x R matrices live in LDS when they fit.  Wave 0 inverts T
-// by Gauss-Jordan with the working columns in registers (one per lane) and
-// the pivot column broadcast through scalar registers: a Cholesky or a
-// triangular solve in LDS serializes on LDS round trips, one per entry.
-// Vh = H T^{-1} is then a small product over all threads.
+// all R x R / R_n x R matrices live in LDS when they fit.  Per mode, wave 0
+// forms T and solves Vh T = H by Gauss-Jordan with the working columns in
+// registers (one per lane) and the pivot column broadcast through scalar
+// registers (when R + R_n > 64 it inverts T the same way and Vh = H T^{-1}
+// is a product over all threads).  Then one wave per column forms
+// P = M_n Vh, the column norm and the normalized columns, and the Gram
+// A_n^T A_n = Vh^T P follows: three barriers per mode after the MTTKRP.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -41,10 +45,12 @@ struct CoreAlsArgs {
   int64_t x1_doubles; // first MTTKRP step (shared by modes 0..N-2)
   // LDS byte offsets
   int oV[8], oVh[8], oM[8], oGram[8];
-  int oT, oL, oH, oP, oNrm, oG0, oRed, oG, oX1, oW1, oW2, oStage;
+  int oT, oL, oH, oVr, oRed, oG, oX1, oW1, oW2, oStage;
   // MTTKRP schedule: step st of mode n contracts mode sm with V_sm; the
   // operand is [sApre, R_sm, sCpost] (times RP after the first step)
   int sm[8][8], sApre[8][8], sCpost[8][8];
+  // 1: stop after the start and hand the state to the three-way kernel
+  int setup_only;
 };
 
 // 1/p from the hardware estimate refined by two Newton steps (within an ulp
@@ -63,6 +69,26 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
+}
+
+// v from the lane that the DPP control selects (within a row of 16 lanes)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same bits in every lane: butterflies within
+// each row of 16 lanes on the DPP network (quad swaps, half-row and row
+// mirrors), then the four row sums in a fixed order through scalar
+// registers.  No LDS traffic.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
 
 // Wave-level in-place Gauss-Jordan inversion of the symmetric positive
@@ -112,114 +138,67 @@ __device__ __forceinline__ bool gj_inverse_wave(const double* T, int RP, int R,
   return ok;
 }
 
-// Wave-level Gauss-Jordan solve of X (T + delta I) = H for X (Rn x R), T
-// symmetric positive definite (R x R) and H (Rn x R), all with row stride
-// RP.  The wave holds the augmented matrix [T + delta I | H^T] (R rows),
-// lane c column c (R + Rn <= 64), and eliminates two pivots per step (a
-// 2 x 2 pivot block; one at the end when R is odd), so the chain of
-// dependent steps is half as long: lanes k and k+1 publish their columns in
-// LDS, every lane reads both back as broadcasts, applies the block's
-// inverse to its rows k, k+1 and subtracts the corresponding combination of
-// the two pivot columns from its other rows.  The pivot lanes' columns
-// become e_k, e_{k+1} by the same arithmetic.  After the last step lane
-// R + i holds column i of T^{-1} H^T, i.e. row i of X.  Without pivoting the
-// pivot blocks are diagonal blocks of Schur complements of an SPD matrix: a
-// block whose leading entry or determinant is <= 0 means T + delta I is not
-// numerically positive definite (returns false).
-template <int RMAX>
-__device__ __forceinline__ bool gj_solve_wave(const double* T, int RP, int R, double delta,
-                                              const double* H, int Rn, double* X,
-                                              double* pcol) {
-  static_assert(RMAX % 2 == 0 && RMAX <= 32, "pivot columns in double2 steps");
-  // the widest form keeps one pivot per step (three columns of registers
-  // would not fit beside the rest of the kernel)
-  constexpr bool kBlocks = RMAX <= 24;
-  constexpr int kStep = kBlocks ? 2 : 1;
+// Wave-level Gauss-Jordan solve of X (T + delta I) = H for X (Rn x R), where
+// T = hadamard_{p != n} Gram_p (R x R, symmetric positive definite) is formed
+// here, each lane c < R building column c of T from the Grams (row stride
+// RP), so no separate pass writes T.  The wave holds the augmented matrix
+// [T + delta I | H^T] (R rows), lane c column c (R + Rn <= 64), and
+// eliminates one pivot per step without pivoting: the pivot column comes
+// from lane k through scalar registers (two readlanes per entry), which
+// costs less than a round trip through LDS per step.  After the last step
+// lane R + i holds column i of T^{-1} H^T, i.e. row i of X.  The pivots are
+// the Schur-complement diagonals of an SPD matrix: a pivot <= 0 means
+// T + delta I is not numerically positive definite (returns false).  *trace
+// receives tr(T) (every lane).  gram(p) returns Gram_p.
+template <int RMAX, class GramFn>
+__device__ __forceinline__ bool gj_solve_wave(GramFn gram, int N, int n, int RP,
+                                              int R, double delta, const double* H, int Rn,
+                                              double* X, double* trace) {
+  static_assert(RMAX <= 32, "two columns of RMAX rows per lane");
   const int c = threadIdx.x & 63;
   const bool isT = c < R, isH = c >= R && c < R + Rn;
   const int jt = isT ? c : 0, ih = isH ? c - R : 0;   // clamped: loads in bounds
-  double* pc1 = pcol + RMAX;
   double col[RMAX];
+#pragma unroll
+  for (int i = 0; i < RMAX; ++i) col[i] = 1.0;
+  for (int p = 0; p < N; ++p) {
+    if (p == n) continue;
+    const double* Gp = gram(p);
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+      const int ic = i < R ? i : R - 1;
+      col[i] *= Gp[ic * RP + jt];
+    }
+  }
+  double dg = 0.0;
 #pragma unroll
   for (int i = 0; i < RMAX; ++i) {
     const int ic = i < R ? i : R - 1;
     double v = 0.0;
-    if (isT)
-      v = T[ic * RP + jt] + (i == c ? delta : 0.0);
-    else if (isH)
+    if (isT) {
+      if (i == c) dg = col[i];
+      v = col[i] + (i == c ? delta : 0.0);
+    } else if (isH) {
       v = H[ih * RP + ic];
+    }
     col[i] = i < R ? v : 0.0;
   }
+  *trace = wave_sum(dg);
   bool ok = true;
 #pragma unroll
-  for (int k = 0; k < RMAX; k += kStep) {
+  for (int k = 0; k < RMAX; ++k) {
     if (k < R) {
-      const bool pair = kBlocks && k + 1 < R;
-      if (c == k || (pair && c == k + 1)) {
-        double* dst = c == k ? pcol : pc1;
+      double m[RMAX];   // the pivot column (zero below row R)
 #pragma unroll
-        for (int i = 0; i < RMAX; i += 2)
-          *reinterpret_cast<double2*>(dst + i) = make_double2(col[i], col[i + 1]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // both pivot columns (k; k+1, unused in a single-pivot step), every
-      // load issued before the first use: one LDS round trip per step
-      double m0[RMAX], m1[RMAX];   // zero below row R
+      for (int i = 0; i < RMAX; ++i) m[i] = lane_bcast(col[i], k);
+      // a failed pivot spoils the result, which the caller then discards
+      const double p = m[k];
+      ok = ok && p > 0.0;
+      const double f = col[k] * recip(p);
 #pragma unroll
-      for (int i = 0; i < RMAX; i += 2) {
-        const double2 v = *reinterpret_cast<const double2*>(pcol + i);
-        m0[i] = v.x;
-        m0[i + 1] = v.y;
-      }
-#pragma unroll
-      for (int i = 0; i < RMAX; i += 2) {
-        const double2 v = *reinterpret_cast<const double2*>(pc1 + i);
-        m1[i] = v.x;
-        m1[i + 1] = v.y;
-      }
-      // keep the second column's loads ahead of the branch (the compiler
-      // would sink them into it, behind a second wait); register-only.  The
-      // widest block form has no registers to spare for it.
-      if constexpr (RMAX <= 20) {
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i) asm volatile("" : "+v"(m1[i]));
-      }
-      if (pair) {
-        // block [[a, b], [cc, d]] = rows/columns k, k+1
-        const int k1 = (k + 1) % RMAX;   // = k + 1 here
-        const double a = m0[k], cc = m0[k1], b = m1[k], d = m1[k1];
-        double det = a * d - b * cc;
-        if (!(a > 0.0 && det > 0.0)) {
-          ok = false;
-          det = 1.0;
-        }
-        const double rd = recip(det);
-        const double x0 = col[k], x1 = col[k1];
-        const double f0 = (d * x0 - b * x1) * rd;
-        const double f1 = (a * x1 - cc * x0) * rd;
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i)
-          if (i != k && i != k1) col[i] = fma(-m1[i], f1, fma(-m0[i], f0, col[i]));
-        col[k] = f0;
-        col[k1] = f1;
-      } else {
-        double p = m0[k];
-        if (!(p > 0.0)) {
-          ok = false;
-          p = 1.0;
-        }
-        const double f = col[k] * recip(p);
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i)
-          if (i != k) col[i] = fma(-m0[i], f, col[i]);
-        col[k] = f;
-      }
-      // every lane has read the pivot columns before the next step rewrites them
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = 0; i < RMAX; ++i)
+        if (i != k) col[i] = fma(-m[i], f, col[i]);
+      col[k] = f;
     }
   }
   if (isH) {
@@ -403,8 +382,6 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
   // ---- iterations ----------------------------------------------------------
   double* T = D(c.oT);
   double* L = D(c.oL);  // T^{-1}
-  double* Pm = D(c.oP);
-  double* G0 = D(c.oG0);
   double* Hlast = D(c.oH);
 
   // H_n = G_(n) [KR_{p != n} V_p] into Hlast (returns it)
@@ -574,6 +551,27 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
     }
   }
 
+  if (c.setup_only) {
+    // the start for the three-way kernel, dense: V_n and Vh_n (R_n x R, in
+    // a.V and a.A), M_n (R_n x R_n, in a.U64), Gram_n (R x R), ||Yt||^2 and
+    // the start kept (a.scal[0], a.scal[1])
+    for (int n = 0; n < N; ++n) {
+      const int Rn = a.Rn[n];
+      for (int l = t; l < Rn * R; l += NT) {
+        const int j = l / R, r = l % R;
+        a.V[n][l] = D(c.oV[n])[j * RP + r];
+        a.A[n][l] = D(c.oVh[n])[j * RP + r];
+      }
+      for (int l = t; l < Rn * Rn; l += NT) a.U64[n][l] = D(c.oM[n])[l];
+      for (int l = t; l < R * R; l += NT) a.Gram[n][l] = D(c.oGram[n])[(l / R) * RP + l % R];
+    }
+    if (t == 0) {
+      a.scal[0] = nrm2;
+      a.scal[1] = init_used;
+    }
+    return;
+  }
+
   double fit_prev = 0.0, fit = 0.0;
   int it = 0, converged = 0, ridged = 0;
   for (it = 1; it <= a.max_it; ++it) {
@@ -581,7 +579,25 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
       const int Rn = a.Rn[n];
       const double* H = mttkrp(n);  // Rn x RP (Hlast)
 
-      // T = hadamard of the other Grams
+      // Vr = H T^{-1} with T = hadamard of the other Grams (ridge T + delta I
+      // when T is not numerically positive definite)
+      double* Vr = D(c.oVr);
+      if (RMAX <= 32 && R + Rn <= 64) {
+        // wave 0 forms T and solves
+        if constexpr (RMAX <= 32) {
+          if (t < 64) {
+            auto gram = [&](int p) __attribute__((always_inline)) { return D(c.oGram[p]); };
+            double delta = 0.0, tr = 0.0;
+            for (int attempt = 0; attempt < 2; ++attempt) {
+              if (gj_solve_wave<RMAX>(gram, N, n, RP, R, delta, H, Rn, Vr, &tr)) break;
+              delta = 1e-12 * tr / R;
+              ridged = 1;
+            }
+          }
+        }
+        __syncthreads();
+      } else {
+      // T in LDS, L <- T^{-1} by wave 0, then Vr = H L
       for (int l = t; l < R * R; l += NT) {
         const int i = l / R, j = l % R;
         double v = 1.0;
@@ -590,24 +606,6 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
         T[i * RP + j] = v;
       }
       __syncthreads();
-
-      double* Vh = D(c.oVh[n]);
-      // Vh = H T^{-1} (ridge T + delta I when T is not numerically positive
-      // definite), by wave 0
-      if (RMAX <= 32 && R + Rn <= 64) {
-        if constexpr (RMAX <= 32) {
-          if (t < 64) {
-            if (!gj_solve_wave<RMAX>(T, RP, R, 0.0, H, Rn, Vh, L)) {
-              double tr = 0.0;
-              for (int k = 0; k < R; ++k) tr += T[k * RP + k];
-              gj_solve_wave<RMAX>(T, RP, R, 1e-12 * tr / R, H, Rn, Vh, L);
-              ridged = 1;
-            }
-          }
-        }
-        __syncthreads();
-      } else {
-      // L <- T^{-1}, then Vh = H L
       if (t < 64) {
         if (!gj_inverse_wave<RMAX>(T, RP, R, 0.0, L)) {
           double tr = 0.0;
@@ -629,72 +627,67 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
           acc2 += hv * v23.x;
           acc3 += hv * v23.y;
         }
-        double* vp = Vh + i * RP + 4 * rq;
+        double* vp = Vr + i * RP + 4 * rq;
         *reinterpret_cast<double2*>(vp) = make_double2(acc0, acc1);
         *reinterpret_cast<double2*>(vp + 2) = make_double2(acc2, acc3);
       }
       __syncthreads();
       }
 
-      // P = M_n Vh;  G0 = Vh^T P (Gram of the unnormalized factor)
-      const double* M = D(c.oM[n]);
-      for (int l = t; l < Rn * R4; l += NT) {
-        const int j = l / R4, rq = l % R4;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-#pragma unroll 4
-        for (int q = 0; q < Rn; ++q) {
-          const double mv = M[j * Rn + q];
-          const double2 v01 = *reinterpret_cast<const double2*>(Vh + q * RP + 4 * rq);
-          const double2 v23 = *reinterpret_cast<const double2*>(Vh + q * RP + 4 * rq + 2);
-          acc0 += mv * v01.x;
-          acc1 += mv * v01.y;
-          acc2 += mv * v23.x;
-          acc3 += mv * v23.y;
-        }
-        double* pp = Pm + j * RP + 4 * rq;
-        *reinterpret_cast<double2*>(pp) = make_double2(acc0, acc1);
-        *reinterpret_cast<double2*>(pp + 2) = make_double2(acc2, acc3);
-      }
-      __syncthreads();
-      for (int l = t; l < R * R; l += NT) {
-        const int i = l / R, j = l % R;
-        // four partial sums: independent LDS round trips and FMA chains
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int q = 0;
-        for (; q + 4 <= Rn; q += 4) {
-          a0 += Vh[q * RP + i] * Pm[q * RP + j];
-          a1 += Vh[(q + 1) * RP + i] * Pm[(q + 1) * RP + j];
-          a2 += Vh[(q + 2) * RP + i] * Pm[(q + 2) * RP + j];
-          a3 += Vh[(q + 3) * RP + i] * Pm[(q + 3) * RP + j];
-        }
-        for (; q < Rn; ++q) a0 += Vh[q * RP + i] * Pm[q * RP + j];
-        G0[i * RP + j] = (a0 + a1) + (a2 + a3);
-      }
-      __syncthreads();
-      // columns normalized for n < N-1 (zero columns stay zero):
-      // Vh /= nr, V_n = P / nr, Gram_n = G0 / (nr nr^T)
+      // One wave per column r: P(:, r) = M_n Vr(:, r) with lane j holding row
+      // j (M_n is symmetric, so lane j reads row q of it at column j), the
+      // squared column norm of the factor ||a_r||^2 = Vr(:, r)^T P(:, r) as a
+      // wave sum, and the columns normalized for n < N-1 (zero columns stay
+      // zero): Vh_n = Vr / nr, V_n = P / nr.
+      double* Vh = D(c.oVh[n]);
       double* Vn = D(c.oV[n]);
-      double* Gn = D(c.oGram[n]);
+      const double* M = D(c.oM[n]);
       const bool normalize = n < N - 1;
-      for (int l = t; l < Rn * R; l += NT) {
-        const int j = l / R, r = l % R;
-        const double nr = normalize ? sqrt(G0[r * RP + r]) : 0.0;
-        if (nr > 0.0) {
-          Vh[j * RP + r] /= nr;
-          Vn[j * RP + r] = Pm[j * RP + r] / nr;
-        } else {
-          Vn[j * RP + r] = Pm[j * RP + r];
+      {
+        const int lane = t & 63, wave = t >> 6;
+        const int jl = lane < Rn ? lane : 0;   // clamped: loads in bounds
+        for (int r = wave; r < R; r += NT / 64) {
+          double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+          int q = 0;
+#pragma unroll 2
+          for (; q + 4 <= Rn; q += 4) {
+            const double m0 = M[q * Rn + jl], m1 = M[(q + 1) * Rn + jl];
+            const double m2 = M[(q + 2) * Rn + jl], m3 = M[(q + 3) * Rn + jl];
+            p0 = fma(m0, Vr[q * RP + r], p0);
+            p1 = fma(m1, Vr[(q + 1) * RP + r], p1);
+            p2 = fma(m2, Vr[(q + 2) * RP + r], p2);
+            p3 = fma(m3, Vr[(q + 3) * RP + r], p3);
+          }
+          for (; q < Rn; ++q) p0 = fma(M[q * Rn + jl], Vr[q * RP + r], p0);
+          const double pv = (p0 + p1) + (p2 + p3);
+          const double vr = Vr[jl * RP + r];
+          const double g = wave_sum_dpp(lane < Rn ? vr * pv : 0.0);
+          const double nr = normalize && g > 0.0 ? sqrt(g) : 0.0;
+          const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
+          if (lane < Rn) {
+            Vh[lane * RP + r] = vr * inv;
+            Vn[lane * RP + r] = pv * inv;
+          }
         }
       }
-      for (int l = t; l < R * R; l += NT) {
-        const int i = l / R, j = l % R;
-        double v = G0[i * RP + j];
-        if (normalize) {
-          const double ni = sqrt(G0[i * RP + i]), nj = sqrt(G0[j * RP + j]);
-          if (ni > 0.0) v /= ni;
-          if (nj > 0.0) v /= nj;
+      __syncthreads();
+      // Gram_n = A_n^T A_n = Vh_n^T V_n
+      {
+        double* Gn = D(c.oGram[n]);
+        for (int l = t; l < R * R; l += NT) {
+          const int i = l / R, j = l % R;
+          // four partial sums: independent LDS round trips and FMA chains
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          int q = 0;
+          for (; q + 4 <= Rn; q += 4) {
+            a0 = fma(Vh[q * RP + i], Vn[q * RP + j], a0);
+            a1 = fma(Vh[(q + 1) * RP + i], Vn[(q + 1) * RP + j], a1);
+            a2 = fma(Vh[(q + 2) * RP + i], Vn[(q + 2) * RP + j], a2);
+            a3 = fma(Vh[(q + 3) * RP + i], Vn[(q + 3) * RP + j], a3);
+          }
+          for (; q < Rn; ++q) a0 = fma(Vh[q * RP + i], Vn[q * RP + j], a0);
+          Gn[i * RP + j] = (a0 + a1) + (a2 + a3);
         }
-        Gn[i * RP + j] = v;
       }
       __syncthreads();
     }
@@ -775,9 +768,7 @@ int64_t layout(CoreAlsArgs& c, bool glds) {
   c.oT = take(8LL * R * c.RP);
   c.oL = take(8LL * (R * c.RP > 64 ? R * c.RP : 64));   // also the pivot column
   c.oH = take(8LL * Rmax * c.RP);
-  c.oP = take(8LL * Rmax * c.RP);
-  c.oNrm = take(8LL * c.RP);
-  c.oG0 = take(8LL * R * c.RP);
+  c.oVr = take(8LL * Rmax * c.RP);
   c.oRed = take(8LL * 64);
   // staging for the setup cross products: 64 rows of (p + q) <= 2 max(R, Rn);
   // with the MTTKRP buffers in LDS it shares the first-step buffer (X1 is
@@ -850,6 +841,423 @@ int launch_r(CoreAlsArgs& c, hipStream_t s) {
   return kErrUnsupported;
 }
 
+// ------------------------------------------------------------ three-way
+// The iterations of the same method for three-way cores with R and every
+// R_n at most K: the ranks are zero-padded to K, so every loop has a
+// compile-time trip count and every matrix a fixed place in LDS (rows of K
+// doubles), and no index arithmetic or schedule is read at run time.  The
+// start (M_n, the coefficient start and its Grams, ||Yt||^2, the guarded
+// choice) comes from the general kernel run with setup_only; the output
+// kernel forms A_n = U_n Vh_n.  Zero padding changes no value: the padded
+// rows and columns of V_n, Vh_n, M_n, H and the Grams stay zero, and the
+// solve eliminates only the first R pivots.
+//
+// Per iteration (the MTTKRPs of eqs. (12)-(13) through the core):
+//   mode 0: X = G x_3 V_2 (all K^2 positions (i0, i1), 4 x 4 register
+//           blocks), H_0 = X x_2 V_1;
+//   mode 1: H_1 = X x_1 V_0 (X is still current: V_2 has not changed);
+//   mode 2: Y = G x_2 V_1, H_2 = Y x_1 V_0;
+// and after each H_n the update of eq. (14) as in the general kernel: wave 0
+// solves Vh T = H with T = hadamard of the other two Grams, one wave per
+// column forms P = M_n Vh and the column norm, then the Gram.
+constexpr int kA3Threads = 512;
+
+template <int K>
+struct A3Layout {
+  static constexpr int GP = K | 1;   // core rows (last mode) padded to an odd stride
+  static constexpr int KK = K * K;
+  static constexpr int oG = 0;                                   // float [K][K][GP]
+  static constexpr int oV = (4 * KK * GP + 15) / 16 * 16;        // double [3][K][K]
+  static constexpr int oVh = oV + 3 * 8 * KK;
+  static constexpr int oM = oVh + 3 * 8 * KK;
+  static constexpr int oGram = oM + 3 * 8 * KK;
+  static constexpr int oW = oGram + 3 * 8 * KK;                  // double [K][K][K]
+  static constexpr int oH = oW + 8 * K * KK;
+  static constexpr int oVr = oH + 8 * KK;
+  static constexpr int oRed = oVr + 8 * KK;                      // 2 doubles per wave
+  static constexpr int bytes = oRed + 8 * 2 * (kA3Threads / 64);
+};
+
+template <int K>
+__global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
+  static_assert(K % 4 == 0 && K <= 32, "rows of K doubles in 4-column quads");
+  using L = A3Layout<K>;
+  constexpr int GP = L::GP, KK = L::KK, RQ = K / 4, NT = kA3Threads;
+  extern __shared__ __align__(16) char smem[];
+  (void)a_arg;
+  typedef const __attribute__((address_space(4))) FfcpArgs KArgs;
+  KArgs& a = *reinterpret_cast<KArgs*>(
+      reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr()));
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int R = a.R;
+  float* G = reinterpret_cast<float*>(smem + L::oG);
+  auto Vn = [&](int n) __attribute__((always_inline)) {
+    return reinterpret_cast<double*>(smem + L::oV + 8 * KK * n);
+  };
+  auto Vhn = [&](int n) __attribute__((always_inline)) {
+    return reinterpret_cast<double*>(smem + L::oVh + 8 * KK * n);
+  };
+  auto Mn = [&](int n) __attribute__((always_inline)) {
+    return reinterpret_cast<double*>(smem + L::oM + 8 * KK * n);
+  };
+  auto Gramn = [&](int n) __attribute__((always_inline)) {
+    return reinterpret_cast<double*>(smem + L::oGram + 8 * KK * n);
+  };
+  double* W = reinterpret_cast<double*>(smem + L::oW);
+  double* H = reinterpret_cast<double*>(smem + L::oH);
+  double* Vr = reinterpret_cast<double*>(smem + L::oVr);
+  double* red = reinterpret_cast<double*>(smem + L::oRed);
+
+  // ---- the start, zero-padded --------------------------------------------
+  {
+    double* z = reinterpret_cast<double*>(smem + L::oV);
+    for (int l = t; l < (L::oRed - L::oV) / 8; l += NT) z[l] = 0.0;
+    for (int l = t; l < KK * GP; l += NT) G[l] = 0.0f;
+  }
+  __syncthreads();
+  {
+    const int R0 = a.Rn[0], R1 = a.Rn[1], R2 = a.Rn[2];
+    for (int l = t; l < R0 * R1 * R2; l += NT) {
+      const int i0 = l / (R1 * R2), rem = l - i0 * (R1 * R2);
+      const int i1 = rem / R2, i2 = rem - i1 * R2;
+      G[(i0 * K + i1) * GP + i2] = a.G[l];
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int Rn = a.Rn[n];
+    for (int l = t; l < Rn * R; l += NT) {
+      const int j = l / R, r = l - j * R;
+      Vn(n)[j * K + r] = a.V[n][l];
+      Vhn(n)[j * K + r] = a.A[n][l];
+    }
+    for (int l = t; l < Rn * Rn; l += NT) {
+      const int j = l / Rn, q = l - j * Rn;
+      Mn(n)[j * K + q] = a.U64[n][l];
+    }
+    for (int l = t; l < R * R; l += NT) {
+      const int i = l / R, j = l - i * R;
+      Gramn(n)[i * K + j] = a.Gram[n][l];
+    }
+  }
+  const double nrm2 = a.scal[0];
+  const int init_used = static_cast<int>(a.scal[1]);
+  __syncthreads();
+
+  // W[p][r] = sum_j G(p, j) Vm[j][r] over the contracted mode j; p runs over
+  // the K^2 positions of the other two modes, four positions KK/4 apart and
+  // four columns per thread.  MID: the contracted mode is the middle one and
+  // p = (i0, i2); else the last and p = (i0, i1).
+  auto big_step = [&](auto mid, const double* Vm) __attribute__((always_inline)) {
+    constexpr bool MID = decltype(mid)::value;
+    constexpr int NQ = KK / 4, JS = MID ? GP : 1;
+    for (int item = t; item < NQ * RQ; item += NT) {
+      const int rq = item % RQ, pq = item / RQ;
+      int goff[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = pq + u * NQ;
+        const int i0 = p / K, x = p - i0 * K;
+        goff[u] = MID ? i0 * K * GP + x : p * GP;
+      }
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      const double* vp = Vm + 4 * rq;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const double2 v01 = *reinterpret_cast<const double2*>(vp + j * K);
+        const double2 v23 = *reinterpret_cast<const double2*>(vp + j * K + 2);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double g = static_cast<double>(G[goff[u] + j * JS]);
+          acc[u][0] = fma(g, v01.x, acc[u][0]);
+          acc[u][1] = fma(g, v01.y, acc[u][1]);
+          acc[u][2] = fma(g, v23.x, acc[u][2]);
+          acc[u][3] = fma(g, v23.y, acc[u][3]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double* dp = W + (pq + u * NQ) * K + 4 * rq;
+        *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
+        *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
+      }
+    }
+    __syncthreads();
+  };
+  // H[x][r] = sum_y W(x, y)[r] Vm[y][r] with W(x, y) = W[x][y] (XFIRST) or
+  // W[y][x]
+  auto small_step = [&](auto xfirst, const double* Vm) __attribute__((always_inline)) {
+    constexpr bool XF = decltype(xfirst)::value;
+    for (int item = t; item < K * RQ; item += NT) {
+      const int rq = item % RQ, x = item / RQ;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int y = 0; y < K; ++y) {
+        const double* wp = W + (XF ? x * K + y : y * K + x) * K + 4 * rq;
+        const double2 w01 = *reinterpret_cast<const double2*>(wp);
+        const double2 w23 = *reinterpret_cast<const double2*>(wp + 2);
+        const double2 v01 = *reinterpret_cast<const double2*>(Vm + y * K + 4 * rq);
+        const double2 v23 = *reinterpret_cast<const double2*>(Vm + y * K + 4 * rq + 2);
+        a0 = fma(w01.x, v01.x, a0);
+        a1 = fma(w01.y, v01.y, a1);
+        a2 = fma(w23.x, v23.x, a2);
+        a3 = fma(w23.y, v23.y, a3);
+      }
+      double* hp = H + x * K + 4 * rq;
+      *reinterpret_cast<double2*>(hp) = make_double2(a0, a1);
+      *reinterpret_cast<double2*>(hp + 2) = make_double2(a2, a3);
+    }
+    __syncthreads();
+  };
+
+  int ridged = 0;
+  // Vh_n from H: solve, column norms, Gram (mode n, the other two p < q)
+  auto update = [&](int n, const double* Gp, const double* Gq, bool normalize)
+      __attribute__((always_inline)) {
+    const int Rn = a.Rn[n];
+    if (t < 64) {
+      // wave 0: [T + delta I | H^T], lane c < R column c of T (T = Gp .* Gq),
+      // lane R + i row i of H; Gauss-Jordan without pivoting, the pivot
+      // column through scalar registers; a pivot <= 0 means T is not
+      // numerically positive definite: solve again with the ridge
+      const int c = lane;
+      const bool isT = c < R, isH = c >= R && c < R + Rn;
+      const int jt = isT ? c : 0, ih = isH ? c - R : 0;   // clamped: loads in bounds
+      double dg = 0.0;
+      double tcol[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        tcol[i] = Gp[i * K + jt] * Gq[i * K + jt];
+        if (i == c) dg = tcol[i];
+      }
+      const double tr = wave_sum_dpp(isT ? dg : 0.0);
+      double delta = 0.0;
+#pragma unroll 1
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        double col[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          double v = 0.0;
+          if (isT)
+            v = tcol[i] + (i == c ? delta : 0.0);
+          else if (isH)
+            v = H[ih * K + i];
+          col[i] = i < R ? v : 0.0;
+        }
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (k < R) {
+            double m[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) m[i] = lane_bcast(col[i], k);
+            const double piv = m[k];
+            ok = ok && piv > 0.0;
+            const double f = col[k] * recip(piv);
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+              if (i != k) col[i] = fma(-m[i], f, col[i]);
+            col[k] = f;
+          }
+        }
+        if (ok || attempt == 1) {
+          if (isH) {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+              if (i < R) Vr[ih * K + i] = col[i];
+          }
+          break;
+        }
+        delta = 1e-12 * tr / R;
+        ridged = 1;
+      }
+    }
+    __syncthreads();
+    // one wave per column r: P(:, r) = M_n Vr(:, r) (lane j row j; M_n is
+    // symmetric), ||a_r||^2 = Vr(:, r)^T P(:, r), normalized columns
+    {
+      const double* M = Mn(n);
+      double* Vh = Vhn(n);
+      double* V = Vn(n);
+      const int jl = lane < K ? lane : 0;   // clamped: loads in bounds
+      for (int r = wave; r < R; r += NT / 64) {
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; q += 4) {
+          p0 = fma(M[q * K + jl], Vr[q * K + r], p0);
+          p1 = fma(M[(q + 1) * K + jl], Vr[(q + 1) * K + r], p1);
+          p2 = fma(M[(q + 2) * K + jl], Vr[(q + 2) * K + r], p2);
+          p3 = fma(M[(q + 3) * K + jl], Vr[(q + 3) * K + r], p3);
+        }
+        const double pv = (p0 + p1) + (p2 + p3);
+        const double vr = Vr[jl * K + r];
+        const double g = wave_sum_dpp(lane < K ? vr * pv : 0.0);
+        const double nr = normalize && g > 0.0 ? sqrt(g) : 0.0;
+        const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
+        if (lane < K) {
+          Vh[lane * K + r] = vr * inv;
+          V[lane * K + r] = pv * inv;
+        }
+      }
+    }
+    __syncthreads();
+    // Gram_n = Vh_n^T V_n (all K x K entries; the padding stays zero)
+    {
+      const double* Vh = Vhn(n);
+      const double* V = Vn(n);
+      double* Gn = Gramn(n);
+      for (int l = t; l < KK; l += NT) {
+        const int i = l / K, j = l - i * K;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; q += 4) {
+          a0 = fma(Vh[q * K + i], V[q * K + j], a0);
+          a1 = fma(Vh[(q + 1) * K + i], V[(q + 1) * K + j], a1);
+          a2 = fma(Vh[(q + 2) * K + i], V[(q + 2) * K + j], a2);
+          a3 = fma(Vh[(q + 3) * K + i], V[(q + 3) * K + j], a3);
+        }
+        Gn[i * K + j] = (a0 + a1) + (a2 + a3);
+      }
+    }
+    __syncthreads();
+  };
+
+  double fit_prev = 0.0, fit = 0.0;
+  int it = 0, converged = 0;
+  for (it = 1; it <= a.max_it; ++it) {
+    // one copy of each step in the code (the loop over the modes is kept)
+#pragma unroll 1
+    for (int n = 0; n < 3; ++n) {
+      if (n != 1) {
+        if (n == 0)
+          big_step(std::false_type{}, Vn(2));   // X = G x_3 V_2
+        else
+          big_step(std::true_type{}, Vn(1));    // Y = G x_2 V_1
+      }
+      if (n == 0)
+        small_step(std::true_type{}, Vn(1));    // H_0 = X x_2 V_1
+      else
+        small_step(std::false_type{}, Vn(0));   // H_1 = X x_1 V_0, H_2 = Y x_1 V_0
+      update(n, Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n < 2);
+    }
+    // closed-form fit from H_2 and the Grams
+    {
+      const double* V2 = Vn(2);
+      const double* G0 = Gramn(0);
+      const double* G1 = Gramn(1);
+      const double* G2 = Gramn(2);
+      double pin = 0.0, pyh = 0.0;
+      for (int l = t; l < KK; l += NT) {
+        pin = fma(H[l], V2[l], pin);
+        pyh += G0[l] * G1[l] * G2[l];
+      }
+      pin = wave_sum_dpp(pin);
+      pyh = wave_sum_dpp(pyh);
+      if (lane == 0) {
+        red[2 * wave] = pin;
+        red[2 * wave + 1] = pyh;
+      }
+      __syncthreads();
+      double inner = 0.0, yh2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) {
+        inner += red[2 * w];
+        yh2 += red[2 * w + 1];
+      }
+      double res2 = nrm2 - 2.0 * inner + yh2;
+      res2 = res2 > 0.0 ? res2 : 0.0;
+      fit = 1.0 - sqrt(res2) / sqrt(nrm2);
+    }
+    if (t == 0 && a.fit_trace) a.fit_trace[it - 1] = fit;
+    if (it >= 2 && fabs(fit - fit_prev) < a.tol) {
+      converged = 1;
+      break;
+    }
+    if (it < a.max_it) fit_prev = fit;
+    __syncthreads();   // red is rewritten by the next fit
+  }
+  if (it > a.max_it) it = a.max_it;
+  // ridged is known to wave 0 only
+  __shared__ int ridged_any;
+  if (t == 0) ridged_any = ridged;
+  __syncthreads();
+  // Vh_n (dense R_n x R) and the last Gram for the output kernel
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int Rn = a.Rn[n];
+    for (int l = t; l < Rn * R; l += NT) {
+      const int j = l / R, r = l - j * R;
+      a.A[n][l] = Vhn(n)[j * K + r];
+    }
+  }
+  for (int l = t; l < R * R; l += NT) {
+    const int i = l / R, j = l - i * R;
+    a.Gram[2][l] = Gramn(2)[i * K + j];
+  }
+  if (t == 0 && a.info) {
+    InfoDev* info = static_cast<InfoDev*>(a.info);
+    info->iterations = it;
+    info->converged = converged;
+    info->ridged = ridged_any;
+    info->init_used = init_used;
+    info->fit = fit;
+    info->fit_prev = fit_prev;
+  }
+}
+
+// A_n = U_n Vh_n (rows of the FP32 U_n, Vh_n dense R_n x R in a.A[n]); the
+// last factor normalized, lambda = its column norms (from its Gram).
+__global__ __launch_bounds__(256) void als_output_kernel(FfcpArgs a_arg) {
+  (void)a_arg;
+  typedef const __attribute__((address_space(4))) FfcpArgs KArgs;
+  KArgs& a = *reinterpret_cast<KArgs*>(
+      reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr()));
+  const int n = blockIdx.y, R = a.R, Rn = a.Rn[n], last = a.N - 1;
+  const int64_t cnt = a.I[n] * R;
+  const double* Vh = a.A[n];
+  const double* Gl = a.Gram[last];
+  const float* Un = a.U[n];
+  float* out = a.A_out[n];
+  for (int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; l < cnt;
+       l += static_cast<int64_t>(gridDim.x) * 256) {
+    const int64_t i = l / R;
+    const int r = static_cast<int>(l - i * R);
+    double acc = 0.0;
+    for (int j = 0; j < Rn; ++j) acc += static_cast<double>(Un[i * Rn + j]) * Vh[j * R + r];
+    if (n == last) {
+      const double nr = sqrt(Gl[r * R + r]);
+      if (nr > 0.0) acc /= nr;
+    }
+    out[l] = static_cast<float>(acc);
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int r = threadIdx.x; r < R; r += 256) a.lambda[r] = static_cast<float>(sqrt(Gl[r * R + r]));
+}
+
+template <int K>
+int launch_als3(const FfcpArgs& a, hipStream_t s) {
+  constexpr int lds = A3Layout<K>::bytes;
+  static_assert(lds + 64 <= kLdsMax, "three-way state in LDS");
+  auto k = ffcp_als3_kernel<K>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return hip_fail(e, "ffcp three-way LDS attribute");
+  hipLaunchKernelGGL(k, dim3(1), dim3(kA3Threads), static_cast<size_t>(lds), s, a);
+  RT_LAUNCH_CHECK("ffcp three-way ALS");
+  int64_t imax = 1;
+  for (int n = 0; n < a.N; ++n) imax = a.I[n] > imax ? a.I[n] : imax;
+  int64_t blocks = (imax * a.R + 255) / 256;
+  blocks = blocks < 1024 ? blocks : 1024;
+  hipLaunchKernelGGL(als_output_kernel, dim3(static_cast<unsigned>(blocks), a.N), dim3(256),
+                     0, s, a);
+  RT_LAUNCH_CHECK("ffcp ALS output");
+  return kOk;
+}
+
 }  // namespace
 
 bool ffcp_als_core_applicable(const FfcpArgs& a) {
@@ -859,6 +1267,17 @@ bool ffcp_als_core_applicable(const FfcpArgs& a) {
 int launch_ffcp_als_core(const FfcpArgs& a, hipStream_t s) {
   CoreAlsArgs c{};
   c.a = a;
+  int kmax = a.R;
+  for (int n = 0; n < a.N; ++n) kmax = a.Rn[n] > kmax ? a.Rn[n] : kmax;
+  if (a.N == 3 && kmax <= 20) {
+    // the start by the general kernel, the iterations by the three-way one
+    c.setup_only = 1;
+    const int rc = a.R <= 16 ? launch_r<16, 512>(c, s) : launch_r<20, 512>(c, s);
+    if (rc != kOk) return rc;
+    if (kmax <= 8) return launch_als3<8>(a, s);
+    if (kmax <= 16) return launch_als3<16>(a, s);
+    return launch_als3<20>(a, s);
+  }
   if (a.R <= 16) return launch_r<16, 512>(c, s);
   if (a.R <= 20) return launch_r<20, 512>(c, s);
   if (a.R <= 24) return launch_r<24, 512>(c, s);
