@@ -850,16 +850,20 @@ int launch_r(CoreAlsArgs& c, hipStream_t s) {
 // choice) comes from the general kernel run with setup_only; the output
 // kernel forms A_n = U_n Vh_n.  Zero padding changes no value: the padded
 // rows and columns of V_n, Vh_n, M_n, H and the Grams stay zero, and the
-// solve eliminates only the first R pivots.
+// inversion eliminates only the first R pivots.
 //
-// Per iteration (the MTTKRPs of eqs. (12)-(13) through the core):
-//   mode 0: X = G x_3 V_2 (all K^2 positions (i0, i1), 4 x 4 register
-//           blocks), H_0 = X x_2 V_1;
+// Per mode, T_n = hadamard of the other two Grams is known before H_n, so
+// the two run side by side: wave 0 inverts T_n (Gauss-Jordan in registers)
+// while waves 1-3 and 5-7 form the MTTKRP of eqs. (12)-(13) through the core
+//   mode 0: X = G x_3 V_2 (all K^2 positions (i0, i1) in register blocks),
+//           H_0 = X x_2 V_1;
 //   mode 1: H_1 = X x_1 V_0 (X is still current: V_2 has not changed);
 //   mode 2: Y = G x_2 V_1, H_2 = Y x_1 V_0;
-// and after each H_n the update of eq. (14) as in the general kernel: wave 0
-// solves Vh T = H with T = hadamard of the other two Grams, one wave per
-// column forms P = M_n Vh and the column norm, then the Gram.
+// and M_n H_n.  Then the update of eq. (14): Vh_n = H_n T_n^{-1} and
+// V_n = U_n^T A_n = (M_n H_n) T_n^{-1}, normalized by the column norms
+// ||a_r||^2 = Vh_n(:, r)^T V_n(:, r) (one wave per four columns), and the
+// Gram A_n^T A_n = Vh_n^T V_n.  Eight barriers per mode, none waiting on a
+// serial chain other than the inversion.
 constexpr int kA3Threads = 512;
 
 template <int K>
@@ -873,8 +877,9 @@ struct A3Layout {
   static constexpr int oGram = oM + 3 * 8 * KK;
   static constexpr int oW = oGram + 3 * 8 * KK;                  // double [K][K][K]
   static constexpr int oH = oW + 8 * K * KK;
-  static constexpr int oVr = oH + 8 * KK;
-  static constexpr int oRed = oVr + 8 * KK;                      // 2 doubles per wave
+  static constexpr int oTi = oH + 8 * KK;                        // T^{-1}
+  static constexpr int oMH = oTi + 8 * KK;                       // M_n H
+  static constexpr int oRed = oMH + 8 * KK;                      // 2 doubles per wave
   static constexpr int bytes = oRed + 8 * 2 * (kA3Threads / 64);
 };
 
@@ -905,7 +910,6 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   };
   double* W = reinterpret_cast<double*>(smem + L::oW);
   double* H = reinterpret_cast<double*>(smem + L::oH);
-  double* Vr = reinterpret_cast<double*>(smem + L::oVr);
   double* red = reinterpret_cast<double*>(smem + L::oRed);
 
   // ---- the start, zero-padded --------------------------------------------
@@ -944,46 +948,55 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   const int init_used = static_cast<int>(a.scal[1]);
   __syncthreads();
 
+  double* Ti = reinterpret_cast<double*>(smem + L::oTi);
+  double* MH = reinterpret_cast<double*>(smem + L::oMH);
+  // The MTTKRP steps run on waves 1-3 and 5-7 (worker u of NW = 384) while
+  // wave 0 inverts T; wave 4, which shares wave 0's SIMD when the waves are
+  // placed round-robin, only meets the barriers.  Each step ends with a
+  // barrier that wave 0 matches.
+  constexpr int NW = NT - 128;
+  const int u_w = wave == 4 ? (1 << 20) : (wave < 4 ? t - 64 : t - 128);
   // W[p][r] = sum_j G(p, j) Vm[j][r] over the contracted mode j; p runs over
-  // the K^2 positions of the other two modes, four positions KK/4 apart and
-  // four columns per thread.  MID: the contracted mode is the middle one and
+  // the K^2 positions of the other two modes, PG positions KK/PG apart and
+  // RG columns per item (5 x 5 when K = 20, so that the items fit the
+  // workers once).  MID: the contracted mode is the middle one and
   // p = (i0, i2); else the last and p = (i0, i1).
   auto big_step = [&](auto mid, const double* Vm) __attribute__((always_inline)) {
     constexpr bool MID = decltype(mid)::value;
-    constexpr int NQ = KK / 4, JS = MID ? GP : 1;
-    for (int item = t; item < NQ * RQ; item += NT) {
-      const int rq = item % RQ, pq = item / RQ;
-      int goff[4];
+    constexpr int RG = K % 5 == 0 ? 5 : 4, NG = K / RG, PG = RG;
+    constexpr int NQ = KK / PG, JS = MID ? GP : 1;
+    for (int item = u_w; item < NQ * NG; item += NW) {
+      const int rg = item % NG, pq = item / NG;
+      int goff[PG];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < PG; ++u) {
         const int p = pq + u * NQ;
         const int i0 = p / K, x = p - i0 * K;
         goff[u] = MID ? i0 * K * GP + x : p * GP;
       }
-      double acc[4][4];
+      double acc[PG][RG];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < PG; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-      const double* vp = Vm + 4 * rq;
+        for (int v = 0; v < RG; ++v) acc[u][v] = 0.0;
+      const double* vp = Vm + RG * rg;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const double2 v01 = *reinterpret_cast<const double2*>(vp + j * K);
-        const double2 v23 = *reinterpret_cast<const double2*>(vp + j * K + 2);
+        double vv[RG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int v = 0; v < RG; ++v) vv[v] = vp[j * K + v];
+#pragma unroll
+        for (int u = 0; u < PG; ++u) {
           const double g = static_cast<double>(G[goff[u] + j * JS]);
-          acc[u][0] = fma(g, v01.x, acc[u][0]);
-          acc[u][1] = fma(g, v01.y, acc[u][1]);
-          acc[u][2] = fma(g, v23.x, acc[u][2]);
-          acc[u][3] = fma(g, v23.y, acc[u][3]);
+#pragma unroll
+          for (int v = 0; v < RG; ++v) acc[u][v] = fma(g, vv[v], acc[u][v]);
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        double* dp = W + (pq + u * NQ) * K + 4 * rq;
-        *reinterpret_cast<double2*>(dp) = make_double2(acc[u][0], acc[u][1]);
-        *reinterpret_cast<double2*>(dp + 2) = make_double2(acc[u][2], acc[u][3]);
+      for (int u = 0; u < PG; ++u) {
+        double* dp = W + (pq + u * NQ) * K + RG * rg;
+#pragma unroll
+        for (int v = 0; v < RG; ++v) dp[v] = acc[u][v];
       }
     }
     __syncthreads();
@@ -992,7 +1005,7 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   // W[y][x]
   auto small_step = [&](auto xfirst, const double* Vm) __attribute__((always_inline)) {
     constexpr bool XF = decltype(xfirst)::value;
-    for (int item = t; item < K * RQ; item += NT) {
+    for (int item = u_w; item < K * RQ; item += NW) {
       const int rq = item % RQ, x = item / RQ;
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
@@ -1014,93 +1027,119 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
     __syncthreads();
   };
 
-  int ridged = 0;
-  // Vh_n from H: solve, column norms, Gram (mode n, the other two p < q)
-  auto update = [&](int n, const double* Gp, const double* Gq, bool normalize)
-      __attribute__((always_inline)) {
-    const int Rn = a.Rn[n];
-    if (t < 64) {
-      // wave 0: [T + delta I | H^T], lane c < R column c of T (T = Gp .* Gq),
-      // lane R + i row i of H; Gauss-Jordan without pivoting, the pivot
-      // column through scalar registers; a pivot <= 0 means T is not
-      // numerically positive definite: solve again with the ridge
-      const int c = lane;
-      const bool isT = c < R, isH = c >= R && c < R + Rn;
-      const int jt = isT ? c : 0, ih = isH ? c - R : 0;   // clamped: loads in bounds
-      double dg = 0.0;
-      double tcol[K];
+  // MH = M_n H (M_n symmetric, zero-padded)
+  auto mh_step = [&](const double* M) __attribute__((always_inline)) {
+    for (int item = u_w; item < K * RQ; item += NW) {
+      const int rq = item % RQ, x = item / RQ;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-      for (int i = 0; i < K; ++i) {
-        tcol[i] = Gp[i * K + jt] * Gq[i * K + jt];
-        if (i == c) dg = tcol[i];
+      for (int y = 0; y < K; ++y) {
+        const double mv = M[x * K + y];
+        const double2 h01 = *reinterpret_cast<const double2*>(H + y * K + 4 * rq);
+        const double2 h23 = *reinterpret_cast<const double2*>(H + y * K + 4 * rq + 2);
+        a0 = fma(mv, h01.x, a0);
+        a1 = fma(mv, h01.y, a1);
+        a2 = fma(mv, h23.x, a2);
+        a3 = fma(mv, h23.y, a3);
       }
-      const double tr = wave_sum_dpp(isT ? dg : 0.0);
-      double delta = 0.0;
-#pragma unroll 1
-      for (int attempt = 0; attempt < 2; ++attempt) {
-        double col[K];
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-          double v = 0.0;
-          if (isT)
-            v = tcol[i] + (i == c ? delta : 0.0);
-          else if (isH)
-            v = H[ih * K + i];
-          col[i] = i < R ? v : 0.0;
-        }
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          if (k < R) {
-            double m[K];
-#pragma unroll
-            for (int i = 0; i < K; ++i) m[i] = lane_bcast(col[i], k);
-            const double piv = m[k];
-            ok = ok && piv > 0.0;
-            const double f = col[k] * recip(piv);
-#pragma unroll
-            for (int i = 0; i < K; ++i)
-              if (i != k) col[i] = fma(-m[i], f, col[i]);
-            col[k] = f;
-          }
-        }
-        if (ok || attempt == 1) {
-          if (isH) {
-#pragma unroll
-            for (int i = 0; i < K; ++i)
-              if (i < R) Vr[ih * K + i] = col[i];
-          }
-          break;
-        }
-        delta = 1e-12 * tr / R;
-        ridged = 1;
-      }
+      double* dp = MH + x * K + 4 * rq;
+      *reinterpret_cast<double2*>(dp) = make_double2(a0, a1);
+      *reinterpret_cast<double2*>(dp + 2) = make_double2(a2, a3);
     }
     __syncthreads();
-    // one wave per column r: P(:, r) = M_n Vr(:, r) (lane j row j; M_n is
-    // symmetric), ||a_r||^2 = Vr(:, r)^T P(:, r), normalized columns
-    {
-      const double* M = Mn(n);
+  };
+
+  int ridged = 0;
+  // Wave 0: Ti = (T + delta I)^{-1} for T = Gp .* Gq (R x R) by Gauss-Jordan
+  // on [T | I] without pivoting: lane c < R holds column c of T, lane R + c
+  // column c of I; the pivot column comes from lane k through scalar
+  // registers.  A pivot <= 0 means T is not numerically positive definite:
+  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.
+  auto invert_T = [&](const double* Gp, const double* Gq) __attribute__((always_inline)) {
+    const int c = lane;
+    const bool isT = c < R, isI = c >= R && c < 2 * R;
+    const int jt = isT ? c : 0;   // clamped: loads in bounds
+    double dg = 0.0;
+    double tcol[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      tcol[i] = Gp[i * K + jt] * Gq[i * K + jt];
+      if (i == c) dg = tcol[i];
+    }
+    const double tr = wave_sum_dpp(isT ? dg : 0.0);
+    double delta = 0.0;
+#pragma unroll 1
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      double col[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        double v = 0.0;
+        if (isT)
+          v = tcol[i] + (i == c ? delta : 0.0);
+        else if (isI)
+          v = i == c - R ? 1.0 : 0.0;
+        col[i] = i < R ? v : 0.0;
+      }
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < R) {
+          double m[K];
+#pragma unroll
+          for (int i = 0; i < K; ++i) m[i] = lane_bcast(col[i], k);
+          const double piv = m[k];
+          ok = ok && piv > 0.0;
+          const double f = col[k] * recip(piv);
+#pragma unroll
+          for (int i = 0; i < K; ++i)
+            if (i != k) col[i] = fma(-m[i], f, col[i]);
+          col[k] = f;
+        }
+      }
+      if (ok || attempt == 1) {
+        if (isI) {
+#pragma unroll
+          for (int i = 0; i < K; ++i) Ti[i * K + (c - R)] = i < R ? col[i] : 0.0;
+        }
+        break;
+      }
+      delta = 1e-12 * tr / R;
+      ridged = 1;
+    }
+  };
+  // Mode n after H_n, MH and Ti: wave w < K/4 takes the columns 4w..4w+3,
+  // lane x row x: Vr = H Ti (the unnormalized Vh_n), P = MH Ti (= M_n Vr,
+  // the unnormalized V_n = U_n^T A_n), the squared column norms ||a_r||^2 =
+  // Vr(:, r)^T P(:, r) as wave sums, and the normalized columns; then
+  // Gram_n = Vh_n^T V_n.
+  auto finish_mode = [&](int n, bool normalize) __attribute__((always_inline)) {
+    if (wave < RQ) {
+      const int x = lane < K ? lane : 0;   // clamped: loads in bounds
+      double vr[4] = {0.0, 0.0, 0.0, 0.0}, pr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int y = 0; y < K; ++y) {
+        const double hv = H[x * K + y], mv = MH[x * K + y];
+        const double2 t01 = *reinterpret_cast<const double2*>(Ti + y * K + 4 * wave);
+        const double2 t23 = *reinterpret_cast<const double2*>(Ti + y * K + 4 * wave + 2);
+        vr[0] = fma(hv, t01.x, vr[0]);
+        vr[1] = fma(hv, t01.y, vr[1]);
+        vr[2] = fma(hv, t23.x, vr[2]);
+        vr[3] = fma(hv, t23.y, vr[3]);
+        pr[0] = fma(mv, t01.x, pr[0]);
+        pr[1] = fma(mv, t01.y, pr[1]);
+        pr[2] = fma(mv, t23.x, pr[2]);
+        pr[3] = fma(mv, t23.y, pr[3]);
+      }
       double* Vh = Vhn(n);
       double* V = Vn(n);
-      const int jl = lane < K ? lane : 0;   // clamped: loads in bounds
-      for (int r = wave; r < R; r += NT / 64) {
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-        for (int q = 0; q < K; q += 4) {
-          p0 = fma(M[q * K + jl], Vr[q * K + r], p0);
-          p1 = fma(M[(q + 1) * K + jl], Vr[(q + 1) * K + r], p1);
-          p2 = fma(M[(q + 2) * K + jl], Vr[(q + 2) * K + r], p2);
-          p3 = fma(M[(q + 3) * K + jl], Vr[(q + 3) * K + r], p3);
-        }
-        const double pv = (p0 + p1) + (p2 + p3);
-        const double vr = Vr[jl * K + r];
-        const double g = wave_sum_dpp(lane < K ? vr * pv : 0.0);
+      for (int c = 0; c < 4; ++c) {
+        const double g = wave_sum_dpp(lane < K ? vr[c] * pr[c] : 0.0);
         const double nr = normalize && g > 0.0 ? sqrt(g) : 0.0;
         const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
         if (lane < K) {
-          Vh[lane * K + r] = vr * inv;
-          V[lane * K + r] = pv * inv;
+          Vh[lane * K + 4 * wave + c] = vr[c] * inv;
+          V[lane * K + 4 * wave + c] = pr[c] * inv;
         }
       }
     }
@@ -1129,20 +1168,29 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   double fit_prev = 0.0, fit = 0.0;
   int it = 0, converged = 0;
   for (it = 1; it <= a.max_it; ++it) {
-    // one copy of each step in the code (the loop over the modes is kept)
+    // one copy of each step in the code (the loop over the modes is kept).
+    // T_n needs only the other Grams, so wave 0 inverts it while waves
+    // 1..7 form H_n; the barriers of the two sides pair up (the branch is
+    // uniform per wave).
 #pragma unroll 1
     for (int n = 0; n < 3; ++n) {
-      if (n != 1) {
+      if (__builtin_amdgcn_readfirstlane(wave) == 0) {
+        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2));
+        if (n != 1) __syncthreads();   // the big step's barrier
+        __syncthreads();               // the small step's barrier
+        __syncthreads();               // the M_n H step's barrier
+      } else {
         if (n == 0)
           big_step(std::false_type{}, Vn(2));   // X = G x_3 V_2
-        else
+        else if (n == 2)
           big_step(std::true_type{}, Vn(1));    // Y = G x_2 V_1
+        if (n == 0)
+          small_step(std::true_type{}, Vn(1));  // H_0 = X x_2 V_1
+        else
+          small_step(std::false_type{}, Vn(0)); // H_1 = X x_1 V_0, H_2 = Y x_1 V_0
+        mh_step(Mn(n));
       }
-      if (n == 0)
-        small_step(std::true_type{}, Vn(1));    // H_0 = X x_2 V_1
-      else
-        small_step(std::false_type{}, Vn(0));   // H_1 = X x_1 V_0, H_2 = Y x_1 V_0
-      update(n, Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n < 2);
+      finish_mode(n, n < 2);
     }
     // closed-form fit from H_2 and the Grams
     {
