@@ -49,8 +49,6 @@ struct CoreAlsArgs {
   // MTTKRP schedule: step st of mode n contracts mode sm with V_sm; the
   // operand is [sApre, R_sm, sCpost] (times RP after the first step)
   int sm[8][8], sApre[8][8], sCpost[8][8];
-  // 1: stop after the start and hand the state to the three-way kernel
-  int setup_only;
 };
 
 // 1/p from the hardware estimate refined by two Newton steps (within an ulp
@@ -551,27 +549,6 @@ __global__ __launch_bounds__(NT) void ffcp_als_core_kernel(CoreAlsArgs c_arg) {
     }
   }
 
-  if (c.setup_only) {
-    // the start for the three-way kernel, dense: V_n and Vh_n (R_n x R, in
-    // a.V and a.A), M_n (R_n x R_n, in a.U64), Gram_n (R x R), ||Yt||^2 and
-    // the start kept (a.scal[0], a.scal[1])
-    for (int n = 0; n < N; ++n) {
-      const int Rn = a.Rn[n];
-      for (int l = t; l < Rn * R; l += NT) {
-        const int j = l / R, r = l % R;
-        a.V[n][l] = D(c.oV[n])[j * RP + r];
-        a.A[n][l] = D(c.oVh[n])[j * RP + r];
-      }
-      for (int l = t; l < Rn * Rn; l += NT) a.U64[n][l] = D(c.oM[n])[l];
-      for (int l = t; l < R * R; l += NT) a.Gram[n][l] = D(c.oGram[n])[(l / R) * RP + l % R];
-    }
-    if (t == 0) {
-      a.scal[0] = nrm2;
-      a.scal[1] = init_used;
-    }
-    return;
-  }
-
   double fit_prev = 0.0, fit = 0.0;
   int it = 0, converged = 0, ridged = 0;
   for (it = 1; it <= a.max_it; ++it) {
@@ -846,11 +823,12 @@ int launch_r(CoreAlsArgs& c, hipStream_t s) {
 // R_n at most K: the ranks are zero-padded to K, so every loop has a
 // compile-time trip count and every matrix a fixed place in LDS (rows of K
 // doubles), and no index arithmetic or schedule is read at run time.  The
-// start (M_n, the coefficient start and its Grams, ||Yt||^2, the guarded
-// choice) comes from the general kernel run with setup_only; the output
-// kernel forms A_n = U_n Vh_n.  Zero padding changes no value: the padded
-// rows and columns of V_n, Vh_n, M_n, H and the Grams stay zero, and the
-// inversion eliminates only the first R pivots.
+// tall cross products of the start (M_n = U_n^T U_n; U_n^T A_n and A_n^T A_n
+// for a start given as factors) come from the batched cross-product kernel;
+// the kernel itself forms the coefficient start, ||Yt||^2 and the guarded
+// choice, and the output kernel forms A_n = U_n Vh_n.  Zero padding changes
+// no value: the padded rows and columns of V_n, Vh_n, M_n, H and the Grams
+// stay zero, and the inversion eliminates only the first R pivots.
 //
 // Per mode, T_n = hadamard of the other two Grams is known before H_n, so
 // the two run side by side: wave 0 inverts T_n (Gauss-Jordan in registers)
@@ -927,25 +905,27 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
       G[(i0 * K + i1) * GP + i2] = a.G[l];
     }
   }
+  // M_n = U_n^T U_n (dense R_n x R_n in a.U64); a start given as I_n x R
+  // factors comes as V_n = U_n^T A_n (a.V) and Gram_n = A_n^T A_n (a.Gram)
+  const bool user = a.A_init[0] != nullptr;
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
     const int Rn = a.Rn[n];
-    for (int l = t; l < Rn * R; l += NT) {
-      const int j = l / R, r = l - j * R;
-      Vn(n)[j * K + r] = a.V[n][l];
-      Vhn(n)[j * K + r] = a.A[n][l];
-    }
     for (int l = t; l < Rn * Rn; l += NT) {
       const int j = l / Rn, q = l - j * Rn;
       Mn(n)[j * K + q] = a.U64[n][l];
     }
-    for (int l = t; l < R * R; l += NT) {
-      const int i = l / R, j = l - i * R;
-      Gramn(n)[i * K + j] = a.Gram[n][l];
+    if (user) {
+      for (int l = t; l < Rn * R; l += NT) {
+        const int j = l / R, r = l - j * R;
+        Vn(n)[j * K + r] = a.V[n][l];
+      }
+      for (int l = t; l < R * R; l += NT) {
+        const int i = l / R, j = l - i * R;
+        Gramn(n)[i * K + j] = a.Gram[n][l];
+      }
     }
   }
-  const double nrm2 = a.scal[0];
-  const int init_used = static_cast<int>(a.scal[1]);
   __syncthreads();
 
   double* Ti = reinterpret_cast<double*>(smem + L::oTi);
@@ -953,9 +933,10 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   // The MTTKRP steps run on waves 1-3 and 5-7 (worker u of NW = 384) while
   // wave 0 inverts T; wave 4, which shares wave 0's SIMD when the waves are
   // placed round-robin, only meets the barriers.  Each step ends with a
-  // barrier that wave 0 matches.
+  // barrier that wave 0 matches (or takes part in with no items, at the
+  // start).
   constexpr int NW = NT - 128;
-  const int u_w = wave == 4 ? (1 << 20) : (wave < 4 ? t - 64 : t - 128);
+  const int u_w = (wave == 0 || wave == 4) ? (1 << 20) : (wave < 4 ? t - 64 : t - 128);
   // W[p][r] = sum_j G(p, j) Vm[j][r] over the contracted mode j; p runs over
   // the K^2 positions of the other two modes, PG positions KK/PG apart and
   // RG columns per item (5 x 5 when K = 20, so that the items fit the
@@ -1165,6 +1146,155 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
     __syncthreads();
   };
 
+  // closed-form fit from H_2 (in H) and the Grams; the same value in every
+  // thread
+  auto fit_now = [&](double nrm2) __attribute__((always_inline)) -> double {
+    const double* V2 = Vn(2);
+    const double* G0 = Gramn(0);
+    const double* G1 = Gramn(1);
+    const double* G2 = Gramn(2);
+    double pin = 0.0, pyh = 0.0;
+    for (int l = t; l < KK; l += NT) {
+      pin = fma(H[l], V2[l], pin);
+      pyh += G0[l] * G1[l] * G2[l];
+    }
+    pin = wave_sum_dpp(pin);
+    pyh = wave_sum_dpp(pyh);
+    if (lane == 0) {
+      red[2 * wave] = pin;
+      red[2 * wave + 1] = pyh;
+    }
+    __syncthreads();
+    double inner = 0.0, yh2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      inner += red[2 * w];
+      yh2 += red[2 * w + 1];
+    }
+    __syncthreads();   // red is rewritten by the next call
+    double res2 = nrm2 - 2.0 * inner + yh2;
+    res2 = res2 > 0.0 ? res2 : 0.0;
+    return 1.0 - sqrt(res2) / sqrt(nrm2);
+  };
+  // coefficient start: Vh_n = src[n] (dense R_n x R, FP64), V_n = M_n Vh_n,
+  // Gram_n = Vh_n^T V_n
+  auto coeff_start = [&](bool alt) __attribute__((always_inline)) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int Rn = a.Rn[n];
+      const double* src = alt ? a.V_alt[n] : a.V_init[n];
+      for (int l = t; l < Rn * R; l += NT) {
+        const int j = l / R, r = l - j * R;
+        Vhn(n)[j * K + r] = src[l];
+      }
+    }
+    __syncthreads();
+    for (int item = t; item < 3 * K * RQ; item += NT) {
+      const int n = item / (K * RQ), rem = item - n * (K * RQ);
+      const int rq = rem % RQ, x = rem / RQ;
+      const double* M = Mn(n);
+      const double* Vh = Vhn(n);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+      for (int y = 0; y < K; ++y) {
+        const double mv = M[x * K + y];
+        const double2 v01 = *reinterpret_cast<const double2*>(Vh + y * K + 4 * rq);
+        const double2 v23 = *reinterpret_cast<const double2*>(Vh + y * K + 4 * rq + 2);
+        a0 = fma(mv, v01.x, a0);
+        a1 = fma(mv, v01.y, a1);
+        a2 = fma(mv, v23.x, a2);
+        a3 = fma(mv, v23.y, a3);
+      }
+      double* vp = Vn(n) + x * K + 4 * rq;
+      *reinterpret_cast<double2*>(vp) = make_double2(a0, a1);
+      *reinterpret_cast<double2*>(vp + 2) = make_double2(a2, a3);
+    }
+    __syncthreads();
+    for (int l = t; l < 3 * KK; l += NT) {
+      const int n = l / KK, e = l - n * KK;
+      const int i = e / K, j = e - i * K;
+      const double* Vh = Vhn(n);
+      const double* V = Vn(n);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int q = 0; q < K; q += 4) {
+        a0 = fma(Vh[q * K + i], V[q * K + j], a0);
+        a1 = fma(Vh[(q + 1) * K + i], V[(q + 1) * K + j], a1);
+        a2 = fma(Vh[(q + 2) * K + i], V[(q + 2) * K + j], a2);
+        a3 = fma(Vh[(q + 3) * K + i], V[(q + 3) * K + j], a3);
+      }
+      Gramn(n)[i * K + j] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+  };
+  // H_2 = G x_1 V_0 x_2 V_1 (the last mode's MTTKRP)
+  auto mttkrp_last = [&]() __attribute__((always_inline)) {
+    big_step(std::true_type{}, Vn(1));
+    small_step(std::false_type{}, Vn(0));
+  };
+
+  // ||Yt||^2 = <G, G x_1 M_0 x_2 M_1 x_3 M_2> unless given: W = G x_3 M_2,
+  // then the other two modes in place (a thread keeps its whole fibre in
+  // registers), then the inner product with G
+  double nrm2 = a.normY2;
+  if (!(nrm2 >= 0.0)) {
+    big_step(std::false_type{}, Mn(2));
+#pragma unroll 1
+    for (int md = 1; md >= 0; --md) {
+      const double* M = Mn(md);
+      // fibre along mode md through W[i0][i1][c]: the other position index
+      // o and c fixed
+      const int step = md == 0 ? KK : K;
+      for (int l = t; l < KK; l += NT) {
+        const int o = l / K, c = l - o * K;
+        const int base = (md == 0 ? o * K : o * KK) + c;
+        double f[K];
+#pragma unroll
+        for (int x = 0; x < K; ++x) f[x] = W[base + x * step];
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          double acc = 0.0;
+#pragma unroll
+          for (int y = 0; y < K; ++y) acc = fma(M[x * K + y], f[y], acc);
+          W[base + x * step] = acc;
+        }
+      }
+      __syncthreads();
+    }
+    double pl = 0.0;
+    for (int l = t; l < K * KK; l += NT) {
+      const int i0 = l / KK, rem = l - i0 * KK;
+      const int i1 = rem / K, i2 = rem - i1 * K;
+      pl = fma(static_cast<double>(G[(i0 * K + i1) * GP + i2]), W[l], pl);
+    }
+    pl = wave_sum_dpp(pl);
+    if (lane == 0) red[2 * wave] = pl;
+    __syncthreads();
+    nrm2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) nrm2 += red[2 * w];
+    __syncthreads();
+  }
+
+  // the start: the caller's factors, or the coefficient start (guarded by
+  // the HOSVD start when one is given: the caller's is kept only if its fit
+  // is at least the HOSVD start's)
+  int init_used = 0;
+  if (!user) {
+    coeff_start(false);
+    if (a.V_alt[0]) {
+      mttkrp_last();
+      const double f_user = fit_now(nrm2);
+      coeff_start(true);
+      mttkrp_last();
+      const double f_hosvd = fit_now(nrm2);
+      if (f_user >= f_hosvd) {
+        coeff_start(false);
+        init_used = 1;
+      }
+    }
+  }
+
   double fit_prev = 0.0, fit = 0.0;
   int it = 0, converged = 0;
   for (it = 1; it <= a.max_it; ++it) {
@@ -1192,41 +1322,13 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
       }
       finish_mode(n, n < 2);
     }
-    // closed-form fit from H_2 and the Grams
-    {
-      const double* V2 = Vn(2);
-      const double* G0 = Gramn(0);
-      const double* G1 = Gramn(1);
-      const double* G2 = Gramn(2);
-      double pin = 0.0, pyh = 0.0;
-      for (int l = t; l < KK; l += NT) {
-        pin = fma(H[l], V2[l], pin);
-        pyh += G0[l] * G1[l] * G2[l];
-      }
-      pin = wave_sum_dpp(pin);
-      pyh = wave_sum_dpp(pyh);
-      if (lane == 0) {
-        red[2 * wave] = pin;
-        red[2 * wave + 1] = pyh;
-      }
-      __syncthreads();
-      double inner = 0.0, yh2 = 0.0;
-#pragma unroll
-      for (int w = 0; w < NT / 64; ++w) {
-        inner += red[2 * w];
-        yh2 += red[2 * w + 1];
-      }
-      double res2 = nrm2 - 2.0 * inner + yh2;
-      res2 = res2 > 0.0 ? res2 : 0.0;
-      fit = 1.0 - sqrt(res2) / sqrt(nrm2);
-    }
+    fit = fit_now(nrm2);
     if (t == 0 && a.fit_trace) a.fit_trace[it - 1] = fit;
     if (it >= 2 && fabs(fit - fit_prev) < a.tol) {
       converged = 1;
       break;
     }
     if (it < a.max_it) fit_prev = fit;
-    __syncthreads();   // red is rewritten by the next fit
   }
   if (it > a.max_it) it = a.max_it;
   // ridged is known to wave 0 only
@@ -1318,10 +1420,36 @@ int launch_ffcp_als_core(const FfcpArgs& a, hipStream_t s) {
   int kmax = a.R;
   for (int n = 0; n < a.N; ++n) kmax = a.Rn[n] > kmax ? a.Rn[n] : kmax;
   if (a.N == 3 && kmax <= 20) {
-    // the start by the general kernel, the iterations by the three-way one
-    c.setup_only = 1;
-    const int rc = a.R <= 16 ? launch_r<16, 512>(c, s) : launch_r<20, 512>(c, s);
-    if (rc != kOk) return rc;
+    // the tall cross products of the start (M_n = U_n^T U_n, and for a
+    // start given as factors U_n^T A_n and A_n^T A_n), then the three-way
+    // kernel and the output kernel
+    CrossBatch cb{};
+    int nb = 0;
+    for (int n = 0; n < 3; ++n) {
+      cb.X[nb] = a.U[n];
+      cb.Y[nb] = a.U[n];
+      cb.out[nb] = a.U64[n];
+      cb.I[nb] = a.I[n];
+      cb.p[nb] = cb.q[nb] = a.Rn[n];
+      ++nb;
+      if (a.A_init[0]) {
+        cb.X[nb] = a.U[n];
+        cb.Y[nb] = a.A_init[n];
+        cb.out[nb] = a.V[n];
+        cb.I[nb] = a.I[n];
+        cb.p[nb] = a.Rn[n];
+        cb.q[nb] = a.R;
+        ++nb;
+        cb.X[nb] = a.A_init[n];
+        cb.Y[nb] = a.A_init[n];
+        cb.out[nb] = a.Gram[n];
+        cb.I[nb] = a.I[n];
+        cb.p[nb] = cb.q[nb] = a.R;
+        ++nb;
+      }
+    }
+    cb.nb = nb;
+    RT_TRY(launch_cross_tall(cb, s));
     if (kmax <= 8) return launch_als3<8>(a, s);
     if (kmax <= 16) return launch_als3<16>(a, s);
     return launch_als3<20>(a, s);

@@ -117,6 +117,19 @@ struct EigBatch {
 };
 int launch_eig(const EigBatch& b, hipStream_t s);
 
+// out_m = X_m^T Y_m in FP64 (p_m x q_m, dense row-major) for row-major FP32
+// X_m (I_m x p_m) and Y_m (I_m x q_m), p_m, q_m <= 32: one workgroup per
+// product, FP64 matrix cores, a fixed summation order.
+struct CrossBatch {
+  const float* X[16];
+  const float* Y[16];
+  double* out[16];
+  int64_t I[16];
+  int p[16], q[16];
+  int nb;
+};
+int launch_cross_tall(const CrossBatch& b, hipStream_t s);
+
 // ---- FFCP (ffcp.hip) ------------------------------------------------------
 struct FfcpArgs {
   int N, R, update, max_it;

@@ -853,6 +853,73 @@ __global__ __launch_bounds__(kQfThreads) void qr_fused_kernel(QrBatch b) {
   if (t == 0) b.need[m] = 0;
 }
 
+// ------------------------------------------------- tall cross products
+// out = X^T Y for tall FP32 X (I x p) and Y (I x q), p, q <= 32, by the
+// FP64 MFMA of the fused CholeskyQR2's first Gram: waves take 4-row groups
+// in turn (a batch of NG groups' loads in flight), each holds the 2 x 2
+// tiles of 16 x 16 of its partial product, and the waves' tiles are summed
+// in wave order.  Operand lane layout as there: lane l holds row
+// 4g + l/16, column l%16 (+16 for the second tile) of X and of Y.
+__global__ __launch_bounds__(kQfThreads) void cross_tall_kernel(CrossBatch b) {
+  __shared__ double red[kQfWaves * 4 * 256];
+  const int m = blockIdx.x;
+  const int64_t I = b.I[m];
+  const int p = b.p[m], q = b.q[m];
+  const float* X = b.X[m];
+  const float* Y = b.Y[m];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  constexpr int NG = 16;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t ng = (I + 3) / 4;
+  const int c0 = l & 15, c1 = 16 + (l & 15);
+  for (int64_t gb = w; gb < ng; gb += NG * kQfWaves) {
+    float x0[NG], x1[NG], y0[NG], y1[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {   // clamped loads, zeroed afterwards
+      const int64_t r = 4 * (gb + j * kQfWaves) + (l >> 4);
+      const bool in = r < I;
+      const float a0 = X[in && c0 < p ? r * p + c0 : 0];
+      const float a1 = X[in && c1 < p ? r * p + c1 : 0];
+      const float b0 = Y[in && c0 < q ? r * q + c0 : 0];
+      const float b1 = Y[in && c1 < q ? r * q + c1 : 0];
+      x0[j] = in && c0 < p ? a0 : 0.0f;
+      x1[j] = in && c1 < p ? a1 : 0.0f;
+      y0[j] = in && c0 < q ? b0 : 0.0f;
+      y1[j] = in && c1 < q ? b1 : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const double a0 = x0[j], a1 = x1[j], b0 = y0[j], b1 = y1[j];
+      acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+      if (q > 16) acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+      if (p > 16) {
+        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+        if (q > 16) acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[((w * 4 + 2 * a + c) * 64 + l) * 4 + e] = acc[a][c][e];
+  __syncthreads();
+  double* out = b.out[m];
+  for (int o = t; o < 4 * 256; o += kQfThreads) {
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kQfWaves; ++ww) v += red[ww * 1024 + o];
+    const int tile = o / 256, ln = (o % 256) / 4, e = o % 4;
+    const int i = 16 * (tile >> 1) + 4 * e + ln / 16, j = 16 * (tile & 1) + ln % 16;
+    if (i < p && j < q) out[i * q + j] = v;
+  }
+}
+
 template <typename T, int KMAX>
 int qr_dispatch(const QrBatch& b, int32_t* flag, hipStream_t s) {
   const dim3 rows_grid(kQrChunks, b.nb);
@@ -905,6 +972,18 @@ int launch_qr(const QrBatch& b, int32_t* flag, hipStream_t s) {
 
 template int launch_qr<float>(const QrBatch&, int32_t*, hipStream_t);
 template int launch_qr<double>(const QrBatch&, int32_t*, hipStream_t);
+
+int launch_cross_tall(const CrossBatch& b, hipStream_t s) {
+  for (int i = 0; i < b.nb; ++i) {
+    if (b.p[i] < 1 || b.p[i] > 32 || b.q[i] < 1 || b.q[i] > 32 || b.I[i] < 1) {
+      set_error("cross product: widths %d x %d unsupported", b.p[i], b.q[i]);
+      return kErrUnsupported;
+    }
+  }
+  hipLaunchKernelGGL(cross_tall_kernel, dim3(b.nb), dim3(kQfThreads), 0, s, b);
+  RT_LAUNCH_CHECK("cross products");
+  return kOk;
+}
 
 int launch_eig(const EigBatch& b, hipStream_t s) {
   for (int i = 0; i < b.nb; ++i) {
