@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--tucker-only", action="store_true",
                     help="time only the Tucker stage of the chosen form (short "
                          "runs under a profiler) and print its stage times")
+    ap.add_argument("--ffcp-only", action="store_true",
+                    help="the 1000^3 workload's Tucker stage once, then only the "
+                         "timed FFCP-ALS calls from the HOSVD start (for the profiler)")
     ap.add_argument("--hals-only", action="store_true",
                     help="run only the FFCP-HALS fits on the 10^4-per-mode workload (short "
                          "runs under a profiler) and print their record")
@@ -401,6 +404,29 @@ def tucker_only(args, P, torch, Y, om_d, omt_d, ranks, ybf16):
                                     for k, v in prof.items() if v[1] > 0}}), flush=True)
 
 
+def ffcp_only(args, P, torch, Y, om_d, omt_d, ranks, R, ybf16):
+    """The precision form's Tucker stage once, then `steps` FFCP-ALS calls
+    on its core from the HOSVD start: the command the FFCP-ALS kernel-trace
+    profile under profiles/ was taken with."""
+    out = P.tucker_rand(Y, om_d, omt_d, ranks=ranks, sweeps=2, precision="bf16",
+                        ybf16=ybf16)
+    kw = dict(update="als", max_it=args.max_it, tol=args.tol, init="hosvd")
+    f = P.ffcp(out["U"], out["G"], R, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        f = P.ffcp(out["U"], out["G"], R, workspace=f["workspace"], sync=False, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    info = np.frombuffer(f["info_dev"].cpu().numpy().tobytes(), P.FFCP_INFO_DTYPE)[0]
+    print(json.dumps({"ffcp_only": "als", "steps": args.steps, "ms": round(ms, 4),
+                      "iterations": int(info["iterations"]),
+                      "us_per_iteration_incl_start": round(1e3 * ms / int(info["iterations"]), 2),
+                      "fit": float(info["fit"])}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -438,6 +464,9 @@ def main():
 
     if args.tucker_only:
         tucker_only(args, P, torch, Y, om_d, omt_d, ranks, ybf16)
+        return
+    if args.ffcp_only:
+        ffcp_only(args, P, torch, Y, om_d, omt_d, ranks, R, ybf16)
         return
 
     net, learned = None, None
