@@ -640,10 +640,34 @@ constexpr int kStPitch = 144;                   // bytes per row of a staged BF1
 constexpr int kStBytes = 32 * kStPitch;
 static_assert(kYtBytes % 16 == 0 && kStPitch % 16 == 0, "16-byte LDS accesses");
 
-// per-wave LDS of the column-split pass: the transposed tile (TB), then the
-// staged copy tile (FIRST)
+// per-wave LDS of the column-split pass: one 32 x 64 BF16 tile, row-major
+// (rows of kStPitch bytes).  FIRST stages the copy through it; TB reads it
+// back transposed.
 constexpr int cs_wave_bytes(bool first, bool doq) {
-  return (doq ? kYtBytes : 0) + (first ? kStBytes : 0);
+  return (first || doq) ? kStBytes : 0;
+}
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+// TB's B operand of the 32x32x16 BF16 product from the wave's row-major
+// tile (rows = the K of the product): lane l = 16 G + i gets rows
+// k0 + 8 (G / 2) + 0..7 of column n0 + 16 (G % 2) + i.  ds_read_b64_tr_b16
+// hands lane j of a 16-lane group element j % 4 of the four halfwords that
+// lanes 4 k + j / 4 address (k = 0..3); so each of the two loads points
+// lane i at row (i / 4) of its 4-row half and columns 4 (i % 4) .. + 3, and
+// lane i receives four consecutive rows of column i.
+__device__ __forceinline__ v8bf tile_b_operand(const char* tile, int k0, int n0, int lane) {
+  const int G = lane >> 4, i = lane & 15;
+  const int row = k0 + 8 * (G >> 1) + (i >> 2);
+  const int col = n0 + 16 * (G & 1) + 4 * (i & 3);
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_v4s*)(tile + row * kStPitch + 2 * col));
+  const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_v4s*)(tile + (row + 4) * kStPitch + 2 * col));
+  const v8s v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(v8bf, v);
 }
 
 template <bool F>
@@ -692,8 +716,7 @@ __global__ __launch_bounds__(kBThreads) void bf16_cs_kernel(CsArgs a) {
   // LDS: per-wave regions (transposed tile for TB, staged copy tile), two
   // TA-partial buffers, two reduced TA blocks, statistics
   constexpr int kWave = cs_wave_bytes(FIRST, DOQ);
-  uint16_t* yt = reinterpret_cast<uint16_t*>(smem + w * kWave);
-  char* stg = smem + w * kWave + (DOQ ? kYtBytes : 0);
+  char* stg = smem + w * kWave;   // the wave's row-major tile
   float* red = reinterpret_cast<float*>(smem + kBW * kWave);
   float* tab = red + 2 * kCsRed;
   double* sred = reinterpret_cast<double*>(tab + 2 * 1024);
@@ -853,26 +876,24 @@ __global__ __launch_bounds__(kBThreads) void bf16_cs_kernel(CsArgs a) {
           yb[q] = make_uint4(cur.v[q].x, cur.v[q].y, cur.v[q].z, cur.v[q].w);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 4; ++q)
         accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(yb[q]), b2[j][q], accA, 0, 0, 0);
-        if constexpr (DOQ) {
-          const uint32_t wds[4] = {yb[q].x, yb[q].y, yb[q].z, yb[q].w};
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            yt[(16 * q + 8 * g + k) * kYtStride + lr] =
-                static_cast<uint16_t>(wds[k >> 1] >> (16 * (k & 1)));
-        }
-      }
       if constexpr (DOQ) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // TB += B1_block^T M_tile: the tile row-major in the wave's LDS
+        // (FIRST staged it there for the copy already), read back transposed
+        if constexpr (!FIRST) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint4*>(stg + lr * kStPitch + 32 * q + 16 * g) = yb[q];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int sh = 0; sh < 2; ++sh) {
-            const v8bf yc = as_v8bf(*reinterpret_cast<const uint4*>(
-                yt + (32 * sh + lr) * kYtStride + 16 * h + 8 * g));
+            const v8bf yc = tile_b_operand(stg, 16 * h, 32 * sh, lane);
             accB[j][sh] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(b1r[par][h]), yc,
                                                                 accB[j][sh], 0, 0, 0);
           }

@@ -341,9 +341,11 @@ def _tucker_format(seed, dims, ranks, nonneg=False, with_factors=False):
 
 # Cases for the iterate parity.  Small R runs the per-group cross products of
 # the general kernel; R = R_n = 15 its per-thread branch (R_n R + R^2 >= 256);
-# R = 20 and 40 the 32- and 64-column instantiations; ALS at R = 24 the 2x2
-# pivot Gauss-Jordan with the core in LDS, at 32 and 48 the single-pivot solve
-# (the 48^3 core read from global memory).  Every case was checked on the CPU
+# R = 20 and 40 the 32- and 64-column instantiations.  ALS on three-way cores
+# with R and R_n <= 20 runs the three-way kernel, zero-padded to 8, 16 or 20
+# (ranks that differ from each other and from R pad differently); ALS in four
+# modes and at R = 24, 32 and 48 runs the general kernel (the 48^3 core read
+# from global memory).  Every case was checked on the CPU
 # to be well posed for 12 iterations: a 1e-13 relative change of the start
 # moves the oracle's fits by < 1e-13 and its factors by < 1e-11.  For HALS at
 # R = 40 that needs a start near the solution (the true factors times
@@ -352,6 +354,8 @@ def _tucker_format(seed, dims, ranks, nonneg=False, with_factors=False):
 ITERATE_CASES = [
     ("als", (50, 60, 70), (6, 7, 8), 5, "random"),
     ("als", (30, 31, 32, 33), (4, 5, 4, 5), 3, "random"),
+    ("als", (40, 44, 48), (12, 14, 16), 13, "random"),
+    ("als", (40, 44, 48), (20, 18, 19), 17, "random"),
     ("als", (40, 44, 48), (24, 24, 24), 24, "random"),
     ("als", (40, 44, 48), (32, 32, 32), 32, "random"),
     ("als", (56, 60, 64), (48, 48, 48), 48, "random"),
