@@ -598,8 +598,9 @@ int launch_bf_half(const BfArgs& a, int grid, hipStream_t s) {
 // at a time.  For each 32 x 64 tile:
 //   TA partial += M_tile B2_tile       (K = the tile's columns; the wave's
 //                                      B2^T operands stay in registers)
-//   TB_j       += B1_block^T M_tile    (K = the block's rows, B operand from
-//                                      the transposed copy in the wave's LDS)
+//   TB_j       += B1_block^T M_tile    (K = the block's rows, B operand read
+//                                      transposed from the wave's row-major
+//                                      copy of the tile in LDS)
 // After its tiles of a row block a wave parks its TA partial in LDS; one
 // barrier per row block, then the partials are summed over the 8 waves in a
 // fixed order into the block's TA rows, which are stored and kept in LDS for
