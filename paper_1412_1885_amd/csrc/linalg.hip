@@ -661,9 +661,10 @@ __global__ __launch_bounds__(kEigThreads) void eig32_kernel(EigBatch b) {
 // ONE workgroup per matrix, so that no step waits on a global round trip or
 // a kernel boundary (the multi-kernel form spends most of its time there):
 //   G1 = Z^T Z  (FP64 MFMA over 4-row groups read straight from Z)
-//   R1 = chol(G1), R1^{-1}                     (one wavefront, registers)
+//   R1^{-1} for R1 = chol(G1), by Gaussian elimination on [G1 | I]
+//                                               (one wavefront, registers)
 //   Q1 = Z R1^{-1} tile by tile, G2 = Q1^T Q1   (Q1 never leaves registers)
-//   R2 = chol(G2), M = R1^{-1} R2^{-1}
+//   R2^{-1} likewise, M = R1^{-1} R2^{-1}
 //   Q  = Z M     (= Q1 R2^{-1} up to FP64 rounding; M is upper triangular)
 // v_mfma_f64_16x16x4_f64 lane layout (checked on the device): A (16 x 4)
 // lane l holds A[l%16][l/16], B (4 x 16) lane l holds B[l/16][l%16], D
@@ -682,74 +683,61 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// R^{-1} for the upper Cholesky factor R of the K x K matrix S (S = R^T R),
-// by one wavefront: lane c keeps column c of the trailing matrix in
-// registers (right-looking; row j of R is published in LDS each step),
-// then computes column c of R^{-1} by right-looking back substitution with
-// the columns of R read from LDS (Rt, row k = column k of R).  1/R[j][j]
-// comes from the hardware reciprocal square root refined by two Newton
-// steps, R[j][j] = S'[j][j] / sqrt(S'[j][j]).  Pivots at or below 1e-11 of
-// the mean diagonal of S fail (returns false, wave-uniform).  Writes R^{-1}
-// to Ri ([32][kQfLd], zero outside the upper K x K part).
-__device__ __forceinline__ bool chol_inv_wave(const double* S, int K, double* Ri,
-                                              double* Rt /*32 x 32*/, double* rowbuf /*2 x 32*/,
-                                              double* rdiag /*32*/) {
+// R^{-1} for the upper Cholesky factor R of the K x K SPD matrix S, by one
+// wavefront, through Gaussian elimination without pivoting on [S | I]:
+// lane c < K holds column c of S, lane K + c column c of I, all in
+// registers.  Step k broadcasts the pivot and the multipliers of column k
+// (rows below k) from lane k through scalar registers and subtracts the
+// row multiples in every lane.  With S = L D L^T the pivots are D (= the
+// squared diagonal of R) and the right half becomes E = L^{-1}; since
+// R = D^{1/2} L^T, R^{-1} = E^T D^{-1/2}, upper triangular with a positive
+// diagonal: lane K + i writes row i.  A pivot at or below 1e-11 of the mean
+// diagonal of S fails (returns false, wave-uniform).  Writes R^{-1} to Ri
+// ([32][kQfLd], zero outside the upper K x K part).
+__device__ __forceinline__ bool chol_inv_ge_wave(const double* S, int K, double* Ri) {
   const int c = threadIdx.x & 63;
-  const int cc = c < 32 ? c : 31;
-  const double floor_ = 1e-11 * wave_sum(c < K ? S[cc * kQfLd + cc] : 0.0) / K;
+  const bool isS = c < K, isI = c >= K && c < 2 * K;
+  const int cs = isS ? c : 0;   // clamped: loads in bounds
+  const double floor_ = 1e-11 * wave_sum(isS ? S[cs * kQfLd + cs] : 0.0) / K;
   double col[32];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) col[r] = (r <= c && c < K && r < K) ? S[r * kQfLd + cc] : 0.0;
+  for (int r = 0; r < 32; ++r) {
+    double v = 0.0;
+    if (isS)
+      v = S[r * kQfLd + cs];
+    else if (isI)
+      v = (r == c - K) ? 1.0 : 0.0;
+    col[r] = r < K ? v : 0.0;
+  }
+  double dinv[32];   // 1 / sqrt(pivot k), uniform
   bool ok = true;
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    if (j < K) {
-      double d = wave_read(col[j], j);
-      if (!(d > floor_)) {
-        ok = false;
-        d = 1.0;
-      }
-      const double y = rsqrt_nr(d);
-      col[j] = (c == j) ? d * y : (c > j ? col[j] * y : 0.0);
-      if (c == j) rdiag[j] = y;
-      double* rb = rowbuf + 32 * (j & 1);
-      if (c < 32) rb[c] = col[j];          // row j of R (zero left of j)
-      wave_sync_lds();
-      // all of the row's loads first, one wait, then the updates
-      double rv[32];
-#pragma unroll
-      for (int r = j + 1; r < 32; ++r) rv[r] = rb[r];
-#pragma unroll
-      for (int r = j + 1; r < 32; ++r)
-        if (r <= c) col[r] -= rv[r] * col[j];
-    }
-  }
-  if (c < 32) {
-#pragma unroll
-    for (int r = 0; r < 32; ++r) Rt[c * 32 + r] = col[r];   // zero below the diagonal
-  }
-  wave_sync_lds();
-  // column c of R^{-1}: x_k = (delta_kc + s_k) / R[k][k], then s_i -= R[i][k] x_k
-  double x[32], sacc[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) sacc[i] = 0.0;
-#pragma unroll
-  for (int k = 31; k >= 0; --k) {
+  for (int k = 0; k < 32; ++k) {
+    dinv[k] = 0.0;
     if (k < K) {
-      double rk[32];   // column k of R: loads issued together
+      const double p = wave_read(col[k], k);
+      ok = ok && p > floor_;
+      dinv[k] = rsqrt_nr(p);
+      const double rp = dinv[k] * dinv[k];   // 1 / p
+      const double ck = col[k];
+      // rows at or past K are zero in every lane: no guard, straight-line code
+      double mv[32];
 #pragma unroll
-      for (int i = 0; i < k; ++i) rk[i] = Rt[k * 32 + i];
-      x[k] = ((k == c) ? 1.0 : 0.0) + sacc[k];
-      x[k] *= rdiag[k];
+      for (int i = k + 1; i < 32; ++i) mv[i] = wave_read(col[i], k);
 #pragma unroll
-      for (int i = 0; i < k; ++i) sacc[i] -= rk[i] * x[k];
-    } else {
-      x[k] = 0.0;
+      for (int i = k + 1; i < 32; ++i) col[i] = fma(-(mv[i] * rp), ck, col[i]);
     }
   }
-  if (c < 32) {
+  // rows of R^{-1}: lane K + i holds column i of E, R^{-1}[i][j] = E[j][i] / sqrt(d_j)
+  if (isI) {
+    const int i = c - K;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) Ri[i * kQfLd + c] = (c < K) ? x[i] : 0.0;
+    for (int j = 0; j < 32; ++j) Ri[i * kQfLd + j] = j < K ? col[j] * dinv[j] : 0.0;
+  }
+  // rows K .. 31 of R^{-1} are zero
+  if (c >= K && c < 32) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) Ri[c * kQfLd + j] = 0.0;
   }
   return ok;
 }
@@ -838,9 +826,6 @@ __global__ __launch_bounds__(kQfThreads) void qr_fused_kernel(QrBatch b) {
   __shared__ double S[32 * kQfLd];
   __shared__ double Ri1[32 * kQfLd];
   __shared__ double Ri2[32 * kQfLd];
-  __shared__ double rowbuf[64];
-  __shared__ double rdiag[32];
-  __shared__ double Rt[32 * 32];
   __shared__ double scal[2];
   const int m = blockIdx.x;
   const int64_t I = b.I[m];
@@ -886,7 +871,7 @@ __global__ __launch_bounds__(kQfThreads) void qr_fused_kernel(QrBatch b) {
   gram_reduce(red, S);
   __syncthreads();
   if (w == 0) {
-    const bool ok = chol_inv_wave(S, K, Ri1, Rt, rowbuf, rdiag);
+    const bool ok = chol_inv_ge_wave(S, K, Ri1);
     if (l == 0) scal[0] = ok ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -929,7 +914,7 @@ __global__ __launch_bounds__(kQfThreads) void qr_fused_kernel(QrBatch b) {
   gram_reduce(red, S);
   __syncthreads();
   if (w == 0) {
-    const bool ok = chol_inv_wave(S, K, Ri2, Rt, rowbuf, rdiag);
+    const bool ok = chol_inv_ge_wave(S, K, Ri2);
     if (l == 0) scal[0] = ok ? 1.0 : 0.0;
   }
   __syncthreads();
