@@ -44,6 +44,11 @@ struct GemmArgs {
   uint16_t* Cb;      // BF16 result (same layout), or null
   const float* bias;  // per column n
   const float* Zin;   // pre-activation (ldc layout) for the GELU derivative
+  // split-K: workgroup z of the grid takes k in [z kper, (z + 1) kper) and
+  // writes its FP32 partial product to part[z][M][N] (the epilogue follows
+  // in gemm_finish_kernel); part == null: one range, epilogue in place
+  int kper;
+  float* part;
 };
 
 __device__ __forceinline__ float gelu_f(float z) {
@@ -90,52 +95,77 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float 
   }
 }
 
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+constexpr int kKp = 72;   // halfwords per k-row of a tile staged with k along rows
+
+// MFMA operand (lane l: index c0 + l % 32, k = k0 + 8 (l / 32) + 0..7) from
+// a tile staged with k along rows (kKp halfwords per row), by two
+// ds_read_b64_tr_b16: lane j of a 16-lane group receives element j % 4 of
+// the four halfwords lanes 4 q + j / 4 address (q = 0..3), so lane i of the
+// group points at row i / 4 of a 4-row half and columns 4 (i % 4) .. + 3.
+__device__ __forceinline__ v8bf kmajor_operand(const uint16_t* tile, int k0, int c0, int lane) {
+  const int G = lane >> 4, i = lane & 15;
+  const int row = k0 + 8 * (G >> 1) + (i >> 2);
+  const int col = c0 + 16 * (G & 1) + 4 * (i & 3);
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(tile + row * kKp + col));
+  const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(tile + (row + 4) * kKp + col));
+  const v8s v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(v8bf, v);
+}
+
 // C (M x N) = op(A) op(B); op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k],
 // op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64 x 64 tiles staged in
-// LDS with K contiguous; four wavefronts, one 32 x 32 MFMA block each.
+// LDS as they are read (K contiguous, or k along rows: then the MFMA operand
+// comes through the LDS transpose read); four wavefronts, one 32 x 32 MFMA
+// block each.
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[kTM * kLdsK];
-  __shared__ __align__(16) uint16_t Bs[kTM * kLdsK];
+  constexpr int kTile = kTM * kLdsK > kTK * kKp ? kTM * kLdsK : kTK * kKp;
+  __shared__ __align__(16) uint16_t As[kTile];
+  __shared__ __align__(16) uint16_t Bs[kTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1, lr = lane & 31, gq = lane >> 5;
   const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTM;
+  const int kb = g.part ? blockIdx.z * g.kper : 0;
+  const int ke = g.part && kb + g.kper < g.K ? kb + g.kper : g.K;   // this range's end
   v16f acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
     __syncthreads();
     if (!TA) {  // A rows are m: 64 rows x 32 k, 16 bytes per thread
       const int m = t >> 2, k8 = (t & 3) * 8;
-      const uint4 u = load8(g.A + static_cast<int64_t>(m0 + m) * g.lda, k0 + k8, g.K,
+      const uint4 u = load8(g.A + static_cast<int64_t>(m0 + m) * g.lda, k0 + k8, ke,
                             m0 + m < g.M);
       *reinterpret_cast<uint4*>(As + m * kLdsK + k8) = u;
-    } else {    // A rows are k: 32 rows x 64 m, transposed into As
+    } else {    // A rows are k: 32 rows x 64 m, kept with k along rows
       const int k = t >> 3, m8 = (t & 7) * 8;
       const uint4 u = load8(g.A + static_cast<int64_t>(k0 + k) * g.lda, m0 + m8, g.M,
-                            k0 + k < g.K);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) As[(m8 + j) * kLdsK + k] = half_of(u, j);
+                            k0 + k < ke);
+      *reinterpret_cast<uint4*>(As + k * kKp + m8) = u;
     }
     if (TB) {   // B rows are n
       const int n = t >> 2, k8 = (t & 3) * 8;
-      const uint4 u = load8(g.B + static_cast<int64_t>(n0 + n) * g.ldb, k0 + k8, g.K,
+      const uint4 u = load8(g.B + static_cast<int64_t>(n0 + n) * g.ldb, k0 + k8, ke,
                             n0 + n < g.N);
       *reinterpret_cast<uint4*>(Bs + n * kLdsK + k8) = u;
-    } else {    // B rows are k
+    } else {    // B rows are k, kept with k along rows
       const int k = t >> 3, n8 = (t & 7) * 8;
       const uint4 u = load8(g.B + static_cast<int64_t>(k0 + k) * g.ldb, n0 + n8, g.N,
-                            k0 + k < g.K);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) Bs[(n8 + j) * kLdsK + k] = half_of(u, j);
+                            k0 + k < ke);
+      *reinterpret_cast<uint4*>(Bs + k * kKp + n8) = u;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 16) {
-      const v8bf a = __builtin_bit_cast(
-          v8bf, *reinterpret_cast<const uint4*>(As + (wm * 32 + lr) * kLdsK + kk + 8 * gq));
-      const v8bf b = __builtin_bit_cast(
-          v8bf, *reinterpret_cast<const uint4*>(Bs + (wn * 32 + lr) * kLdsK + kk + 8 * gq));
+      const v8bf a = TA ? kmajor_operand(As, kk, wm * 32, lane)
+                        : __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(
+                                                       As + (wm * 32 + lr) * kLdsK + kk + 8 * gq));
+      const v8bf b = !TB ? kmajor_operand(Bs, kk, wn * 32, lane)
+                         : __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(
+                                                        Bs + (wn * 32 + lr) * kLdsK + kk + 8 * gq));
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
   }
@@ -143,15 +173,58 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int m = m0 + wm * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
-    if (m < g.M && n < g.N) epilogue<EPI>(g, m, n, acc[v]);
+    if (m < g.M && n < g.N) {
+      if (g.part)
+        g.part[(static_cast<int64_t>(blockIdx.z) * g.M + m) * g.N + n] = acc[v];
+      else
+        epilogue<EPI>(g, m, n, acc[v]);
+    }
   }
 }
 
+// The split-K ranges' partial products summed in range order, then the
+// epilogue.
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_finish_kernel(GemmArgs g, int splits) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t mn = static_cast<int64_t>(g.M) * g.N;
+  if (o >= mn) return;
+  float x = 0.0f;
+  for (int z = 0; z < splits; ++z) x += g.part[z * mn + o];
+  epilogue<EPI>(g, static_cast<int>(o / g.N), static_cast<int>(o % g.N), x);
+}
+
+// K ranges for a product whose 64 x 64 tiles alone would leave most of the
+// 256 compute units idle (the products with M = batch rows): enough ranges
+// for about 256 workgroups, each at least 512 deep, at most kSplitMax.
+constexpr int kSplitMax = 8;
+int gemm_splits(int M, int N, int K) {
+  const int tiles = ((N + kTM - 1) / kTM) * ((M + kTM - 1) / kTM);
+  if (tiles >= 192 || K < 1024) return 1;
+  int sp = (256 + tiles - 1) / tiles;
+  sp = sp < K / 512 ? sp : K / 512;
+  return sp < kSplitMax ? sp : kSplitMax;
+}
+
+// kpart: FP32 scratch of kSplitMax M N floats for the split-K form, or null
+// (one range per tile)
 template <bool TA, bool TB, int EPI>
-int gemm(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid((g.N + kTM - 1) / kTM, (g.M + kTM - 1) / kTM);
+int gemm(GemmArgs g, hipStream_t s, float* kpart = nullptr) {
+  const int splits = kpart ? gemm_splits(g.M, g.N, g.K) : 1;
+  if (splits > 1) {
+    g.kper = ((g.K + splits - 1) / splits + kTK - 1) / kTK * kTK;
+    g.part = kpart;
+  }
+  const int used = splits > 1 ? (g.K + g.kper - 1) / g.kper : 1;
+  const dim3 grid((g.N + kTM - 1) / kTM, (g.M + kTM - 1) / kTM, used);
   hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
   RT_LAUNCH_CHECK("mlp gemm");
+  if (splits > 1) {
+    const int64_t mn = static_cast<int64_t>(g.M) * g.N;
+    hipLaunchKernelGGL(gemm_finish_kernel<EPI>, dim3(static_cast<unsigned>((mn + 255) / 256)),
+                       dim3(256), 0, s, g, used);
+    RT_LAUNCH_CHECK("mlp gemm finish");
+  }
   return kOk;
 }
 
@@ -466,6 +539,7 @@ struct MlpPlan {
   float *Z1, *Z2, *Yo, *dY, *dZ1, *dZ2, *loss;
   uint16_t *H1, *H2, *dYb, *dZ1b, *dZ2b;
   float* part;    // split-K partial sums (few cores)
+  float* kpart;   // split-K partial sums of the batch-row products
   float* gW[3];
   float* gb[3];
   size_t plan(const MlpDims& m, void* ws, bool grads) {
@@ -494,6 +568,12 @@ struct MlpPlan {
         most = e > most ? e : most;
       }
       part = ar.take<float>(most);
+    }
+    kpart = nullptr;
+    if (part == nullptr) {
+      int64_t wmax = m.d1 > m.d2 ? m.d1 : m.d2;
+      wmax = wmax > m.d3 ? wmax : m.d3;
+      kpart = ar.take<float>(static_cast<int64_t>(kSplitMax) * m.B * wmax);
     }
     for (int l = 0; l < 3; ++l) {
       gW[l] = grads ? ar.take<float>(static_cast<int64_t>(dims[l]) * dims[l + 1]) : nullptr;
@@ -529,13 +609,15 @@ int forward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& P
   g.M = m.B; g.N = m.d1; g.K = m.d0;
   g.A = P.X; g.lda = m.d0; g.B = p->Wb[0]; g.ldb = m.d1;
   g.C = P.Z1; g.ldc = m.d1; g.Cb = P.H1; g.bias = p->b[0];
-  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s) : gemm<false, false, kEpiBiasGelu>(g, s)));
+  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s)
+              : gemm<false, false, kEpiBiasGelu>(g, s, P.kpart)));
   g.N = m.d2; g.K = m.d1; g.A = P.H1; g.lda = m.d1; g.B = p->Wb[1]; g.ldb = m.d2;
   g.C = P.Z2; g.ldc = m.d2; g.Cb = P.H2; g.bias = p->b[1];
-  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s) : gemm<false, false, kEpiBiasGelu>(g, s)));
+  RT_TRY((few ? gemv<kEpiBiasGelu>(g, P.part, s)
+              : gemm<false, false, kEpiBiasGelu>(g, s, P.kpart)));
   g.N = m.d3; g.K = m.d2; g.A = P.H2; g.lda = m.d2; g.B = p->Wb[2]; g.ldb = m.d3;
   g.C = P.Yo; g.ldc = m.d3; g.Cb = nullptr; g.bias = p->b[2];
-  RT_TRY((few ? gemv<kEpiBias>(g, P.part, s) : gemm<false, false, kEpiBias>(g, s)));
+  RT_TRY((few ? gemv<kEpiBias>(g, P.part, s) : gemm<false, false, kEpiBias>(g, s, P.kpart)));
   return kOk;
 }
 
@@ -567,7 +649,7 @@ int backward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& 
   g.M = m.B; g.N = m.d2; g.K = m.d3;
   g.A = P.dYb; g.lda = m.d3; g.B = p->Wb[2]; g.ldb = m.d3; g.C = P.dZ2; g.ldc = m.d2;
   g.Cb = P.dZ2b; g.Zin = P.Z2;
-  RT_TRY((gemm<false, true, kEpiDGelu>(g, s)));
+  RT_TRY((gemm<false, true, kEpiDGelu>(g, s, P.kpart)));
   // layer 2
   g = GemmArgs{};
   g.M = m.d1; g.N = m.d2; g.K = m.B;
@@ -580,7 +662,7 @@ int backward(const MlpDims& m, const rt_mlp_params* p, const float* G, MlpPlan& 
   g.M = m.B; g.N = m.d1; g.K = m.d2;
   g.A = P.dZ2b; g.lda = m.d2; g.B = p->Wb[1]; g.ldb = m.d2; g.C = P.dZ1; g.ldc = m.d1;
   g.Cb = P.dZ1b; g.Zin = P.Z1;
-  RT_TRY((gemm<false, true, kEpiDGelu>(g, s)));
+  RT_TRY((gemm<false, true, kEpiDGelu>(g, s, P.kpart)));
   // layer 1
   g = GemmArgs{};
   g.M = m.d0; g.N = m.d1; g.K = m.B;
