@@ -50,7 +50,18 @@ __global__ __launch_bounds__(kThreads) void expand_kernel(
       T acc[kExpRows];
 #pragma unroll
       for (int u = 0; u < kExpRows; ++u) acc[u] = T(0);
-      for (int j = 0; j < J; ++j) {
+      // eight X loads in flight at a time, then their products (j in order)
+      int j = 0;
+      for (; j + 8 <= J; j += 8) {
+        T x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = xp[static_cast<int64_t>(j + q) * C];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int u = 0; u < kExpRows; ++u) acc[u] += bs[u][j + q] * x[q];
+      }
+      for (; j < J; ++j) {
         const T x = xp[static_cast<int64_t>(j) * C];
 #pragma unroll
         for (int u = 0; u < kExpRows; ++u) acc[u] += bs[u][j] * x;
