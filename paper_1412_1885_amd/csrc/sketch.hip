@@ -354,10 +354,21 @@ __global__ __launch_bounds__(kThreads) void gram_waves_kernel(
   const int c2 = r + o;
   double acc = 0.0;
   const int64_t n = A * C;
-  for (int64_t l = lane; l < n; l += 64) {
-    const int64_t a = l / C, c = l % C;
-    acc += static_cast<double>(X[(a * I + r) * C + c]) *
-           static_cast<double>(X[(a * I + c2) * C + c]);
+  if (n <= 0x7fffffff && C <= 0x7fffffff) {
+    // 32-bit index arithmetic (the usual core-sized case); l in order
+    const int n32 = static_cast<int>(n), C32 = static_cast<int>(C);
+#pragma unroll 4
+    for (int l = lane; l < n32; l += 64) {
+      const int a = l / C32, c = l - a * C32;
+      acc += static_cast<double>(X[(static_cast<int64_t>(a) * I + r) * C32 + c]) *
+             static_cast<double>(X[(static_cast<int64_t>(a) * I + c2) * C32 + c]);
+    }
+  } else {
+    for (int64_t l = lane; l < n; l += 64) {
+      const int64_t a = l / C, c = l % C;
+      acc += static_cast<double>(X[(a * I + r) * C + c]) *
+             static_cast<double>(X[(a * I + c2) * C + c]);
+    }
   }
   acc = wave_sum(acc);
   if (lane == 0) {

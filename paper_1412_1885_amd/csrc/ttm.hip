@@ -159,6 +159,8 @@ __global__ __launch_bounds__(kThreads) void matmul_w_kernel(
   const int64_t i = idx / J;
   const int j = static_cast<int>(idx % J);
   double acc = 0.0;
+  // k in order; the unrolled loads of a chunk are in flight together
+#pragma unroll 8
   for (int k = 0; k < K; ++k) acc += static_cast<double>(Q[i * K + k]) * W[k * J + j];
   out[idx] = static_cast<T>(acc);
 }
