@@ -257,6 +257,8 @@ __global__ __launch_bounds__(256) void gemv_partial_kernel(GemmArgs g, int kchun
   for (int m = 0; m < kGvMaxM; ++m)
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[m][j] = 0.0f;
+  // k in order per wave; the unrolled rows' loads are in flight together
+#pragma unroll 8
   for (int k = k0 + w; k < k1; k += 4) {
     const uint4 u = colok ? *reinterpret_cast<const uint4*>(
                                 g.B + static_cast<int64_t>(k) * g.ldb + n)
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(256) void gemv_finish_kernel(GemmArgs g, int splits
   if (l >= g.M * g.N) return;
   const int m = l / g.N, n = l % g.N;
   float x = 0.0f;
+#pragma unroll 8
   for (int sp = 0; sp < splits; ++sp) x += part[(static_cast<int64_t>(sp) * g.M + m) * g.N + n];
   epilogue<EPI>(g, m, n, x);
 }
