@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kThreads) void ttm_rows_kernel(
   for (int k = 0; k < KMAX; ++k) acc[k] = T(0);
   for (int64_t i0 = 0; i0 < I; i0 += ICH) {
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 16
     for (int e = 0; e < ICH; ++e) {
       int l = e * kThreads + t;
       int row = l / ICH, col = l % ICH;
@@ -82,6 +82,8 @@ __global__ __launch_bounds__(kThreads) void ttm_cols_kernel(
     __syncthreads();
     if (live) {
       const int n = static_cast<int>((I - i0) < ICH ? (I - i0) : ICH);
+      // ii in order; the unrolled loads are in flight together
+#pragma unroll 8
       for (int ii = 0; ii < n; ++ii) {
         T x = xp[(i0 + ii) * C];
 #pragma unroll
