@@ -857,12 +857,15 @@ struct A3Layout {
   static constexpr int oH = oW + 8 * K * KK;
   static constexpr int oTi = oH + 8 * KK;                        // T^{-1}
   static constexpr int oMH = oTi + 8 * KK;                       // M_n H
-  static constexpr int oRed = oMH + 8 * KK;                      // 2 doubles per wave
+  static constexpr int SP = K + 2;                               // pitch of the transposed pair
+  static constexpr int oS = oMH + 8 * KK;                        // Vr^T, P^T [K][SP] doubles each
+  static constexpr int oRed = oS + 2 * 8 * K * SP;               // 2 doubles per wave
   static constexpr int bytes = oRed + 8 * 2 * (kA3Threads / 64);
 };
 
 template <int K>
-__global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
+__global__ __launch_bounds__(kA3Threads) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void ffcp_als3_kernel(FfcpArgs a_arg) {
   static_assert(K % 4 == 0 && K <= 32, "rows of K doubles in 4-column quads");
   using L = A3Layout<K>;
   constexpr int GP = L::GP, KK = L::KK, RQ = K / 4, NT = kA3Threads;
@@ -961,16 +964,27 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
 #pragma unroll
         for (int v = 0; v < RG; ++v) acc[u][v] = 0.0;
       const double* vp = Vm + RG * rg;
+      // operands of step j + 2 are fetched while step j's products run
+      // (three register sets), so the LDS latency is covered
+      float gq[3][PG];
+      double vq[3][RG];
+      auto fetch = [&](int j, int b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < RG; ++v) vq[b][v] = vp[j * K + v];
+#pragma unroll
+        for (int u = 0; u < PG; ++u) gq[b][u] = G[goff[u] + j * JS];
+      };
+      fetch(0, 0);
+      fetch(1, 1);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        double vv[RG];
-#pragma unroll
-        for (int v = 0; v < RG; ++v) vv[v] = vp[j * K + v];
+        if (j + 2 < K) fetch(j + 2, (j + 2) % 3);
+        const int b = j % 3;
 #pragma unroll
         for (int u = 0; u < PG; ++u) {
-          const double g = static_cast<double>(G[goff[u] + j * JS]);
+          const double g = static_cast<double>(gq[b][u]);
 #pragma unroll
-          for (int v = 0; v < RG; ++v) acc[u][v] = fma(g, vv[v], acc[u][v]);
+          for (int v = 0; v < RG; ++v) acc[u][v] = fma(g, vq[b][v], acc[u][v]);
         }
       }
 #pragma unroll
@@ -1035,8 +1049,12 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
   // on [T | I] without pivoting: lane c < R holds column c of T, lane R + c
   // column c of I; the pivot column comes from lane k through scalar
   // registers.  A pivot <= 0 means T is not numerically positive definite:
-  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.
-  auto invert_T = [&](const double* Gp, const double* Gq) __attribute__((always_inline)) {
+  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.  With
+  // SPLIT the first attempt meets one barrier after its first K/2 pivot
+  // steps (the big step's, so that the small step runs beside the second
+  // half).
+  auto invert_T = [&](const double* Gp, const double* Gq, bool split) __attribute__((always_inline)) {
+    constexpr int KH = K / 2;
     const int c = lane;
     const bool isT = c < R, isI = c >= R && c < 2 * R;
     const int jt = isT ? c : 0;   // clamped: loads in bounds
@@ -1064,6 +1082,7 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
       bool ok = true;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
+        if (k == KH && split && attempt == 0) __syncthreads();
         if (k < R) {
           double m[K];
 #pragma unroll
@@ -1088,60 +1107,62 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
       ridged = 1;
     }
   };
-  // Mode n after H_n, MH and Ti: wave w < K/4 takes the columns 4w..4w+3,
-  // lane x row x: Vr = H Ti (the unnormalized Vh_n), P = MH Ti (= M_n Vr,
-  // the unnormalized V_n = U_n^T A_n), the squared column norms ||a_r||^2 =
-  // Vr(:, r)^T P(:, r) as wave sums, and the normalized columns; then
-  // Gram_n = Vh_n^T V_n.
+  // Mode n after H_n, MH and Ti, in two passes over all waves.  First the
+  // unnormalized Vr = H Ti (the coefficients Vh_n) and P = MH Ti (= M_n Vr,
+  // the products U_n^T A_n), stored transposed.  Then thread (i, j) forms
+  // (Vr^T P)(i, j) and the squared column norms ||a_i||^2 = (Vr^T P)(i, i),
+  // ||a_j||^2, and writes Gram_n(i, j) = (Vr^T P)(i, j) / (||a_i|| ||a_j||)
+  // and entry (i, j) of the normalized Vh_n and V_n.
   auto finish_mode = [&](int n, bool normalize) __attribute__((always_inline)) {
-    if (wave < RQ) {
-      const int x = lane < K ? lane : 0;   // clamped: loads in bounds
-      double vr[4] = {0.0, 0.0, 0.0, 0.0}, pr[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int y = 0; y < K; ++y) {
-        const double hv = H[x * K + y], mv = MH[x * K + y];
-        const double2 t01 = *reinterpret_cast<const double2*>(Ti + y * K + 4 * wave);
-        const double2 t23 = *reinterpret_cast<const double2*>(Ti + y * K + 4 * wave + 2);
-        vr[0] = fma(hv, t01.x, vr[0]);
-        vr[1] = fma(hv, t01.y, vr[1]);
-        vr[2] = fma(hv, t23.x, vr[2]);
-        vr[3] = fma(hv, t23.y, vr[3]);
-        pr[0] = fma(mv, t01.x, pr[0]);
-        pr[1] = fma(mv, t01.y, pr[1]);
-        pr[2] = fma(mv, t23.x, pr[2]);
-        pr[3] = fma(mv, t23.y, pr[3]);
-      }
-      double* Vh = Vhn(n);
-      double* V = Vn(n);
+    constexpr int SP = L::SP;
+    double* S1 = reinterpret_cast<double*>(smem + L::oS);
+    double* S2 = S1 + K * SP;
+    for (int l = t; l < KK; l += NT) {
+      const int x = l / K, c = l - x * K;
+      double v0 = 0.0, v1 = 0.0, p0 = 0.0, p1 = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double g = wave_sum_dpp(lane < K ? vr[c] * pr[c] : 0.0);
-        const double nr = normalize && g > 0.0 ? sqrt(g) : 0.0;
-        const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
-        if (lane < K) {
-          Vh[lane * K + 4 * wave + c] = vr[c] * inv;
-          V[lane * K + 4 * wave + c] = pr[c] * inv;
-        }
+      for (int y = 0; y < K; y += 2) {
+        const double2 h = *reinterpret_cast<const double2*>(H + x * K + y);
+        const double2 m = *reinterpret_cast<const double2*>(MH + x * K + y);
+        const double t0 = Ti[y * K + c], t1 = Ti[(y + 1) * K + c];
+        v0 = fma(h.x, t0, v0);
+        v1 = fma(h.y, t1, v1);
+        p0 = fma(m.x, t0, p0);
+        p1 = fma(m.y, t1, p1);
       }
+      S1[c * SP + x] = v0 + v1;
+      S2[c * SP + x] = p0 + p1;
     }
     __syncthreads();
-    // Gram_n = Vh_n^T V_n (all K x K entries; the padding stays zero)
-    {
-      const double* Vh = Vhn(n);
-      const double* V = Vn(n);
-      double* Gn = Gramn(n);
-      for (int l = t; l < KK; l += NT) {
-        const int i = l / K, j = l - i * K;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double* Vh = Vhn(n);
+    double* V = Vn(n);
+    double* Gn = Gramn(n);
+    for (int l = t; l < KK; l += NT) {
+      const int i = l / K, j = l - i * K;
+      const double* ri = S1 + i * SP;
+      const double* pi = S2 + i * SP;
+      const double* rj = S1 + j * SP;
+      const double* pj = S2 + j * SP;
+      double g0 = 0.0, g1 = 0.0, di0 = 0.0, di1 = 0.0, dj0 = 0.0, dj1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < K; q += 4) {
-          a0 = fma(Vh[q * K + i], V[q * K + j], a0);
-          a1 = fma(Vh[(q + 1) * K + i], V[(q + 1) * K + j], a1);
-          a2 = fma(Vh[(q + 2) * K + i], V[(q + 2) * K + j], a2);
-          a3 = fma(Vh[(q + 3) * K + i], V[(q + 3) * K + j], a3);
-        }
-        Gn[i * K + j] = (a0 + a1) + (a2 + a3);
+      for (int x = 0; x < K; x += 2) {
+        const double2 a = *reinterpret_cast<const double2*>(ri + x);
+        const double2 b = *reinterpret_cast<const double2*>(pj + x);
+        const double2 e = *reinterpret_cast<const double2*>(pi + x);
+        const double2 d = *reinterpret_cast<const double2*>(rj + x);
+        g0 = fma(a.x, b.x, g0);
+        g1 = fma(a.y, b.y, g1);
+        di0 = fma(a.x, e.x, di0);
+        di1 = fma(a.y, e.y, di1);
+        dj0 = fma(d.x, b.x, dj0);
+        dj1 = fma(d.y, b.y, dj1);
       }
+      const double di = di0 + di1, dj = dj0 + dj1;
+      const double si = normalize && di > 0.0 ? 1.0 / sqrt(di) : 1.0;
+      const double sj = normalize && dj > 0.0 ? 1.0 / sqrt(dj) : 1.0;
+      Gn[i * K + j] = (g0 + g1) * si * sj;
+      Vh[i * K + j] = S1[j * SP + i] * sj;
+      V[i * K + j] = S2[j * SP + i] * sj;
     }
     __syncthreads();
   };
@@ -1305,8 +1326,8 @@ __global__ __launch_bounds__(kA3Threads) void ffcp_als3_kernel(FfcpArgs a_arg) {
 #pragma unroll 1
     for (int n = 0; n < 3; ++n) {
       if (__builtin_amdgcn_readfirstlane(wave) == 0) {
-        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2));
-        if (n != 1) __syncthreads();   // the big step's barrier
+        // with a big step, its barrier is met halfway through the pivots
+        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n != 1);
         __syncthreads();               // the small step's barrier
         __syncthreads();               // the M_n H step's barrier
       } else {
