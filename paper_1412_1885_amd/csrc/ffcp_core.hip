@@ -77,15 +77,21 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes, the same bits in every lane: butterflies within
-// each row of 16 lanes on the DPP network (quad swaps, half-row and row
-// mirrors), then the four row sums in a fixed order through scalar
-// registers.  No LDS traffic.
-__device__ __forceinline__ double wave_sum_dpp(double v) {
+// Sum over a row of 16 lanes (all active), the same bits in every lane of
+// the row: butterflies on the DPP network (quad swaps, half-row and row
+// mirrors).  No LDS traffic.
+__device__ __forceinline__ double row_sum16(double v) {
   v += dpp_f64<0xb1>(v);    // quad_perm [1, 0, 3, 2]
   v += dpp_f64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
   v += dpp_f64<0x141>(v);   // row_half_mirror
   v += dpp_f64<0x140>(v);   // row_mirror
+  return v;
+}
+
+// Sum over the 64 lanes, the same bits in every lane: the row sums, then
+// the four of them in a fixed order through scalar registers.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = row_sum16(v);
   return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
 
@@ -855,9 +861,9 @@ struct A3Layout {
   static constexpr int oGram = oM + 3 * 8 * KK;
   static constexpr int oW = oGram + 3 * 8 * KK;                  // double [K][K][K]
   static constexpr int oH = oW + 8 * K * KK;
-  static constexpr int oTi = oH + 8 * KK;                        // T^{-1}
-  static constexpr int oMH = oTi + 8 * KK;                       // M_n H
-  static constexpr int SP = K + 2;                               // pitch of the transposed pair
+  static constexpr int SP = K + 2;                               // pitch of the transposed arrays
+  static constexpr int oTi = oH + 8 * KK;                        // T^{-1} by columns [K][SP]
+  static constexpr int oMH = oTi + 8 * K * SP;                   // M_n H
   static constexpr int oS = oMH + 8 * KK;                        // Vr^T, P^T [K][SP] doubles each
   static constexpr int oRed = oS + 2 * 8 * K * SP;               // 2 doubles per wave
   static constexpr int bytes = oRed + 8 * 2 * (kA3Threads / 64);
@@ -997,49 +1003,49 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
     __syncthreads();
   };
   // H[x][r] = sum_y W(x, y)[r] Vm[y][r] with W(x, y) = W[x][y] (XFIRST) or
-  // W[y][x]
+  // W[y][x]; an item is one row x and a column pair, with the even and odd
+  // y summed apart
   auto small_step = [&](auto xfirst, const double* Vm) __attribute__((always_inline)) {
     constexpr bool XF = decltype(xfirst)::value;
-    for (int item = u_w; item < K * RQ; item += NW) {
-      const int rq = item % RQ, x = item / RQ;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    constexpr int RP = K / 2;
+    for (int item = u_w; item < K * RP; item += NW) {
+      const int rp = item % RP, x = item / RP;
+      double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-      for (int y = 0; y < K; ++y) {
-        const double* wp = W + (XF ? x * K + y : y * K + x) * K + 4 * rq;
-        const double2 w01 = *reinterpret_cast<const double2*>(wp);
-        const double2 w23 = *reinterpret_cast<const double2*>(wp + 2);
-        const double2 v01 = *reinterpret_cast<const double2*>(Vm + y * K + 4 * rq);
-        const double2 v23 = *reinterpret_cast<const double2*>(Vm + y * K + 4 * rq + 2);
-        a0 = fma(w01.x, v01.x, a0);
-        a1 = fma(w01.y, v01.y, a1);
-        a2 = fma(w23.x, v23.x, a2);
-        a3 = fma(w23.y, v23.y, a3);
+      for (int y = 0; y < K; y += 2) {
+        const double2 w0 = *reinterpret_cast<const double2*>(
+            W + (XF ? x * K + y : y * K + x) * K + 2 * rp);
+        const double2 w1 = *reinterpret_cast<const double2*>(
+            W + (XF ? x * K + y + 1 : (y + 1) * K + x) * K + 2 * rp);
+        const double2 v0 = *reinterpret_cast<const double2*>(Vm + y * K + 2 * rp);
+        const double2 v1 = *reinterpret_cast<const double2*>(Vm + (y + 1) * K + 2 * rp);
+        a0 = fma(w0.x, v0.x, a0);
+        a1 = fma(w0.y, v0.y, a1);
+        b0 = fma(w1.x, v1.x, b0);
+        b1 = fma(w1.y, v1.y, b1);
       }
-      double* hp = H + x * K + 4 * rq;
-      *reinterpret_cast<double2*>(hp) = make_double2(a0, a1);
-      *reinterpret_cast<double2*>(hp + 2) = make_double2(a2, a3);
+      *reinterpret_cast<double2*>(H + x * K + 2 * rp) = make_double2(a0 + b0, a1 + b1);
     }
     __syncthreads();
   };
 
-  // MH = M_n H (M_n symmetric, zero-padded)
+  // MH = M_n H (M_n symmetric, zero-padded), items as in the small step
   auto mh_step = [&](const double* M) __attribute__((always_inline)) {
-    for (int item = u_w; item < K * RQ; item += NW) {
-      const int rq = item % RQ, x = item / RQ;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    constexpr int RP = K / 2;
+    for (int item = u_w; item < K * RP; item += NW) {
+      const int rp = item % RP, x = item / RP;
+      double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-      for (int y = 0; y < K; ++y) {
-        const double mv = M[x * K + y];
-        const double2 h01 = *reinterpret_cast<const double2*>(H + y * K + 4 * rq);
-        const double2 h23 = *reinterpret_cast<const double2*>(H + y * K + 4 * rq + 2);
-        a0 = fma(mv, h01.x, a0);
-        a1 = fma(mv, h01.y, a1);
-        a2 = fma(mv, h23.x, a2);
-        a3 = fma(mv, h23.y, a3);
+      for (int y = 0; y < K; y += 2) {
+        const double2 m = *reinterpret_cast<const double2*>(M + x * K + y);
+        const double2 h0 = *reinterpret_cast<const double2*>(H + y * K + 2 * rp);
+        const double2 h1 = *reinterpret_cast<const double2*>(H + (y + 1) * K + 2 * rp);
+        a0 = fma(m.x, h0.x, a0);
+        a1 = fma(m.x, h0.y, a1);
+        b0 = fma(m.y, h1.x, b0);
+        b1 = fma(m.y, h1.y, b1);
       }
-      double* dp = MH + x * K + 4 * rq;
-      *reinterpret_cast<double2*>(dp) = make_double2(a0, a1);
-      *reinterpret_cast<double2*>(dp + 2) = make_double2(a2, a3);
+      *reinterpret_cast<double2*>(MH + x * K + 2 * rp) = make_double2(a0 + b0, a1 + b1);
     }
     __syncthreads();
   };
@@ -1049,11 +1055,11 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
   // on [T | I] without pivoting: lane c < R holds column c of T, lane R + c
   // column c of I; the pivot column comes from lane k through scalar
   // registers.  A pivot <= 0 means T is not numerically positive definite:
-  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.  With
-  // SPLIT the first attempt meets one barrier after its first K/2 pivot
-  // steps (the big step's, so that the small step runs beside the second
-  // half).
-  auto invert_T = [&](const double* Gp, const double* Gq, bool split) __attribute__((always_inline)) {
+  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.  The
+  // first attempt meets one barrier after its first K/2 pivot steps: the big
+  // step's (the small step then runs beside the second half) or, in a mode
+  // without one, the small step's (the M_n H step runs beside it).
+  auto invert_T = [&](const double* Gp, const double* Gq) __attribute__((always_inline)) {
     constexpr int KH = K / 2;
     const int c = lane;
     const bool isT = c < R, isI = c >= R && c < 2 * R;
@@ -1082,7 +1088,7 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       bool ok = true;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (k == KH && split && attempt == 0) __syncthreads();
+        if (k == KH && attempt == 0) __syncthreads();
         if (k < R) {
           double m[K];
 #pragma unroll
@@ -1099,7 +1105,9 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       if (ok || attempt == 1) {
         if (isI) {
 #pragma unroll
-          for (int i = 0; i < K; ++i) Ti[i * K + (c - R)] = i < R ? col[i] : 0.0;
+          for (int i = 0; i < K; i += 2)
+            *reinterpret_cast<double2*>(Ti + (c - R) * L::SP + i) =
+                make_double2(i < R ? col[i] : 0.0, i + 1 < R ? col[i + 1] : 0.0);
         }
         break;
       }
@@ -1124,7 +1132,8 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       for (int y = 0; y < K; y += 2) {
         const double2 h = *reinterpret_cast<const double2*>(H + x * K + y);
         const double2 m = *reinterpret_cast<const double2*>(MH + x * K + y);
-        const double t0 = Ti[y * K + c], t1 = Ti[(y + 1) * K + c];
+        const double2 tc = *reinterpret_cast<const double2*>(Ti + c * L::SP + y);
+        const double t0 = tc.x, t1 = tc.y;
         v0 = fma(h.x, t0, v0);
         v1 = fma(h.y, t1, v1);
         p0 = fma(m.x, t0, p0);
@@ -1326,9 +1335,9 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
 #pragma unroll 1
     for (int n = 0; n < 3; ++n) {
       if (__builtin_amdgcn_readfirstlane(wave) == 0) {
-        // with a big step, its barrier is met halfway through the pivots
-        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n != 1);
-        __syncthreads();               // the small step's barrier
+        // the first step's barrier is met halfway through the pivots
+        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2));
+        if (n != 1) __syncthreads();   // the small step's barrier
         __syncthreads();               // the M_n H step's barrier
       } else {
         if (n == 0)
