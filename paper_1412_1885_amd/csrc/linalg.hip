@@ -535,10 +535,11 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigBatch b) {
   }
 }
 
-// The same cyclic Jacobi for n <= 32: the matrix is zero-padded to 32 (a
-// zero row and column is never rotated, since its off-diagonal entries stay
-// 0 and fail the threshold), so 16 pairs, 31 rounds per sweep and exactly
-// one 2 x 2 block per thread, with no dummy player.  The rotation angles
+// The same cyclic Jacobi for n <= 32: the matrix is zero-padded to the even
+// size np = n or n + 1 (a zero row and column is never rotated, since its
+// off-diagonal entries stay 0 and fail the threshold), so np/2 pairs,
+// np - 1 rounds per sweep and one 2 x 2 block per thread of the first
+// (np/2)^2, with no dummy player.  The rotation angles
 // come from the hardware reciprocal and reciprocal square root refined by
 // Newton steps (c^2 + s^2 = 1 to working precision) instead of an IEEE
 // division and square root, and the LDS addresses from 24-bit products:
@@ -588,15 +589,24 @@ __global__ __launch_bounds__(kEigThreads) void eig32_kernel(EigBatch b) {
   }
   const double thresh = 1e-14 * sqrt(block_sum(fro, red)) + 1e-300;
   const int pa = t >> 4, pb = t & 15;   // the thread's block: pairs pa x pb
+  // the round-robin schedule runs over the even size np >= n (np - 1
+  // rounds per sweep); entries beyond np are never read
+  const int np = n + (n & 1);
+  const bool on = pa < np / 2 && pb < np / 2;
   int cur = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rotated = 0;
-    for (int r = 0; r < NP - 1; ++r) {
+    for (int r = 0; r < np - 1; ++r) {
       const double* Sc = S2[cur];
       double* Sn = S2[cur ^ 1];
+      if (!on) {
+        cur ^= 1;
+        __syncthreads();
+        continue;
+      }
       int i0, i1, j0, j1;
-      jacobi_pair(pa, r, NP, i0, i1);
-      jacobi_pair(pb, r, NP, j0, j1);
+      jacobi_pair(pa, r, np, i0, i1);
+      jacobi_pair(pb, r, np, j0, j1);
       const int ri0 = __mul24(i0, L), ri1 = __mul24(i1, L);
       const int rj0 = __mul24(j0, L), rj1 = __mul24(j1, L);
       const double b00 = Sc[ri0 + j0], b01 = Sc[ri0 + j1];
