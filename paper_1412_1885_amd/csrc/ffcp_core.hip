@@ -1051,16 +1051,22 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
   };
 
   int ridged = 0;
-  // Wave 0: Ti = (T + delta I)^{-1} for T = Gp .* Gq (R x R) by Gauss-Jordan
-  // on [T | I] without pivoting: lane c < R holds column c of T, lane R + c
-  // column c of I; the pivot column comes from lane k through scalar
-  // registers.  A pivot <= 0 means T is not numerically positive definite:
-  // the inversion is repeated with the ridge delta = 1e-12 tr(T) / R.  The
-  // first attempt meets one barrier after its first K/2 pivot steps: the big
-  // step's (the small step then runs beside the second half) or, in a mode
-  // without one, the small step's (the M_n H step runs beside it).
-  auto invert_T = [&](const double* Gp, const double* Gq) __attribute__((always_inline)) {
-    constexpr int KH = K / 2;
+  // Wave 0: forward Gaussian elimination without pivoting on [T + delta I |
+  // I] for T = Gp .* Gq (R x R): lane c < R holds column c of T, lane R + c
+  // column c of I; step k takes the pivot column's rows k.. from lane k
+  // through scalar registers and clears the rows below k.  With T = L D L^T
+  // the pivots are D and the right half becomes E = L^{-1}, so that
+  // T^{-1} = E^T D^{-1} E (formed by all waves in ti_step).  Lane R + c
+  // stores column c of E and of D^{-1} E transposed (rows of pitch SP, in
+  // the pair S1, S2, free until the finishing passes).  A pivot <= 0 means
+  // T is not numerically positive definite: the elimination is repeated
+  // with the ridge delta = 1e-12 tr(T) / R.  With SPLIT the first attempt
+  // meets one barrier after its first K/5 steps (the small step's, in the
+  // mode without a big step: the M_n H step then runs beside the rest).
+  auto eliminate_T = [&](const double* Gp, const double* Gq, bool split) __attribute__((always_inline)) {
+    constexpr int KS = K / 5, SP = L::SP;
+    double* Et = reinterpret_cast<double*>(smem + L::oS);
+    double* EtD = Et + K * SP;
     const int c = lane;
     const bool isT = c < R, isI = c >= R && c < 2 * R;
     const int jt = isT ? c : 0;   // clamped: loads in bounds
@@ -1075,7 +1081,7 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
     double delta = 0.0;
 #pragma unroll 1
     for (int attempt = 0; attempt < 2; ++attempt) {
-      double col[K];
+      double col[K], rps[K];
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         double v = 0.0;
@@ -1088,32 +1094,55 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       bool ok = true;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (k == KH && attempt == 0) __syncthreads();
+        if (k == KS && split && attempt == 0) __syncthreads();
+        rps[k] = 0.0;
         if (k < R) {
           double m[K];
 #pragma unroll
-          for (int i = 0; i < K; ++i) m[i] = lane_bcast(col[i], k);
+          for (int i = k; i < K; ++i) m[i] = lane_bcast(col[i], k);
           const double piv = m[k];
           ok = ok && piv > 0.0;
-          const double f = col[k] * recip(piv);
+          rps[k] = recip(piv);
+          const double f = col[k] * rps[k];
 #pragma unroll
-          for (int i = 0; i < K; ++i)
-            if (i != k) col[i] = fma(-m[i], f, col[i]);
-          col[k] = f;
+          for (int i = k + 1; i < K; ++i) col[i] = fma(-m[i], f, col[i]);
         }
       }
       if (ok || attempt == 1) {
         if (isI) {
 #pragma unroll
-          for (int i = 0; i < K; i += 2)
-            *reinterpret_cast<double2*>(Ti + (c - R) * L::SP + i) =
-                make_double2(i < R ? col[i] : 0.0, i + 1 < R ? col[i + 1] : 0.0);
+          for (int i = 0; i < K; i += 2) {
+            *reinterpret_cast<double2*>(Et + (c - R) * SP + i) = make_double2(col[i], col[i + 1]);
+            *reinterpret_cast<double2*>(EtD + (c - R) * SP + i) =
+                make_double2(col[i] * rps[i], col[i + 1] * rps[i + 1]);
+          }
         }
         break;
       }
       delta = 1e-12 * tr / R;
       ridged = 1;
     }
+  };
+  // All waves: T^{-1} = E^T D^{-1} E, stored by columns: Ti[c][y] =
+  // sum_i E(i, y) E(i, c) / D_i.  Rows of the pair beyond R hold the last
+  // finishing pass's values, so the padding of Ti is written as zero.
+  auto ti_step = [&]() __attribute__((always_inline)) {
+    constexpr int SP = L::SP;
+    const double* Et = reinterpret_cast<const double*>(smem + L::oS);
+    const double* EtD = Et + K * SP;
+    for (int l = t; l < KK; l += NT) {
+      const int y = l / K, c = l - y * K;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < K; i += 2) {
+        const double2 e = *reinterpret_cast<const double2*>(Et + y * SP + i);
+        const double2 d = *reinterpret_cast<const double2*>(EtD + c * SP + i);
+        a0 = fma(e.x, d.x, a0);
+        a1 = fma(e.y, d.y, a1);
+      }
+      Ti[c * SP + y] = y < R && c < R ? a0 + a1 : 0.0;
+    }
+    __syncthreads();
   };
   // Mode n after H_n, MH and Ti, in two passes over all waves.  First the
   // unnormalized Vr = H Ti (the coefficients Vh_n) and P = MH Ti (= M_n Vr,
@@ -1335,9 +1364,13 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
 #pragma unroll 1
     for (int n = 0; n < 3; ++n) {
       if (__builtin_amdgcn_readfirstlane(wave) == 0) {
-        // the first step's barrier is met halfway through the pivots
-        invert_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2));
-        if (n != 1) __syncthreads();   // the small step's barrier
+        // in the mode without a big step the small step's barrier is met
+        // inside the elimination
+        eliminate_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n == 1);
+        if (n != 1) {
+          __syncthreads();             // the big step's barrier
+          __syncthreads();             // the small step's barrier
+        }
         __syncthreads();               // the M_n H step's barrier
       } else {
         if (n == 0)
@@ -1350,6 +1383,7 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
           small_step(std::false_type{}, Vn(0)); // H_1 = X x_1 V_0, H_2 = Y x_1 V_0
         mh_step(Mn(n));
       }
+      ti_step();
       finish_mode(n, n < 2);
     }
     fit = fit_now(nrm2);
