@@ -865,7 +865,8 @@ struct A3Layout {
   static constexpr int oTi = oH + 8 * KK;                        // T^{-1} by columns [K][SP]
   static constexpr int oMH = oTi + 8 * K * SP;                   // M_n H
   static constexpr int oS = oMH + 8 * KK;                        // Vr^T, P^T [K][SP] doubles each
-  static constexpr int oRed = oS + 2 * 8 * K * SP;               // 2 doubles per wave
+  static constexpr int oSv = oS + 2 * 8 * K * SP;                // column scales, K doubles
+  static constexpr int oRed = oSv + 8 * K;                       // 2 doubles per wave
   static constexpr int bytes = oRed + 8 * 2 * (kA3Threads / 64);
 };
 
@@ -1144,12 +1145,13 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
     }
     __syncthreads();
   };
-  // Mode n after H_n, MH and Ti, in two passes over all waves.  First the
+  // Mode n after H_n, MH and Ti, in three passes over all waves.  First the
   // unnormalized Vr = H Ti (the coefficients Vh_n) and P = MH Ti (= M_n Vr,
-  // the products U_n^T A_n), stored transposed.  Then thread (i, j) forms
-  // (Vr^T P)(i, j) and the squared column norms ||a_i||^2 = (Vr^T P)(i, i),
-  // ||a_j||^2, and writes Gram_n(i, j) = (Vr^T P)(i, j) / (||a_i|| ||a_j||)
-  // and entry (i, j) of the normalized Vh_n and V_n.
+  // the products U_n^T A_n), stored transposed.  Then the column scales
+  // 1 / ||a_c|| with ||a_c||^2 = Vr(:, c)^T P(:, c): row c of 16 lanes sums
+  // the products of its row pairs on the DPP network.  Then thread (i, j)
+  // writes Gram_n(i, j) = (Vr^T P)(i, j) / (||a_i|| ||a_j||) and entry
+  // (i, j) of the normalized Vh_n and V_n.
   auto finish_mode = [&](int n, bool normalize) __attribute__((always_inline)) {
     constexpr int SP = L::SP;
     double* S1 = reinterpret_cast<double*>(smem + L::oS);
@@ -1172,32 +1174,35 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       S2[c * SP + x] = p0 + p1;
     }
     __syncthreads();
+    double* sv = reinterpret_cast<double*>(smem + L::oSv);
+    {
+      const int c = t >> 4, xp = t & 15;
+      if (c < K) {   // whole 16-lane rows
+        const bool on = xp < K / 2;
+        const int x0 = on ? 2 * xp : 0;   // clamped: loads in bounds
+        const double2 a = *reinterpret_cast<const double2*>(S1 + c * SP + x0);
+        const double2 b = *reinterpret_cast<const double2*>(S2 + c * SP + x0);
+        const double d = row_sum16(on ? fma(a.y, b.y, a.x * b.x) : 0.0);
+        if (xp == 0) sv[c] = normalize && d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+      }
+    }
+    __syncthreads();
     double* Vh = Vhn(n);
     double* V = Vn(n);
     double* Gn = Gramn(n);
     for (int l = t; l < KK; l += NT) {
       const int i = l / K, j = l - i * K;
       const double* ri = S1 + i * SP;
-      const double* pi = S2 + i * SP;
-      const double* rj = S1 + j * SP;
       const double* pj = S2 + j * SP;
-      double g0 = 0.0, g1 = 0.0, di0 = 0.0, di1 = 0.0, dj0 = 0.0, dj1 = 0.0;
+      double g0 = 0.0, g1 = 0.0;
 #pragma unroll
       for (int x = 0; x < K; x += 2) {
         const double2 a = *reinterpret_cast<const double2*>(ri + x);
         const double2 b = *reinterpret_cast<const double2*>(pj + x);
-        const double2 e = *reinterpret_cast<const double2*>(pi + x);
-        const double2 d = *reinterpret_cast<const double2*>(rj + x);
         g0 = fma(a.x, b.x, g0);
         g1 = fma(a.y, b.y, g1);
-        di0 = fma(a.x, e.x, di0);
-        di1 = fma(a.y, e.y, di1);
-        dj0 = fma(d.x, b.x, dj0);
-        dj1 = fma(d.y, b.y, dj1);
       }
-      const double di = di0 + di1, dj = dj0 + dj1;
-      const double si = normalize && di > 0.0 ? 1.0 / sqrt(di) : 1.0;
-      const double sj = normalize && dj > 0.0 ? 1.0 / sqrt(dj) : 1.0;
+      const double si = sv[i], sj = sv[j];
       Gn[i * K + j] = (g0 + g1) * si * sj;
       Vh[i * K + j] = S1[j * SP + i] * sj;
       V[i * K + j] = S2[j * SP + i] * sj;
