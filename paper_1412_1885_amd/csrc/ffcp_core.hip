@@ -834,20 +834,21 @@ int launch_r(CoreAlsArgs& c, hipStream_t s) {
 // the kernel itself forms the coefficient start, ||Yt||^2 and the guarded
 // choice, and the output kernel forms A_n = U_n Vh_n.  Zero padding changes
 // no value: the padded rows and columns of V_n, Vh_n, M_n, H and the Grams
-// stay zero, and the inversion eliminates only the first R pivots.
+// stay zero, and the elimination takes only the first R pivots.
 //
 // Per mode, T_n = hadamard of the other two Grams is known before H_n, so
-// the two run side by side: wave 0 inverts T_n (Gauss-Jordan in registers)
-// while waves 1-3 and 5-7 form the MTTKRP of eqs. (12)-(13) through the core
+// the two run side by side: wave 0 factors T_n = L D L^T by forward
+// elimination in registers (keeping E = L^{-1} and D) while waves 1-3 and
+// 5-7 form the MTTKRP of eqs. (12)-(13) through the core
 //   mode 0: X = G x_3 V_2 (all K^2 positions (i0, i1) in register blocks),
 //           H_0 = X x_2 V_1;
 //   mode 1: H_1 = X x_1 V_0 (X is still current: V_2 has not changed);
 //   mode 2: Y = G x_2 V_1, H_2 = Y x_1 V_0;
-// and M_n H_n.  Then the update of eq. (14): Vh_n = H_n T_n^{-1} and
-// V_n = U_n^T A_n = (M_n H_n) T_n^{-1}, normalized by the column norms
-// ||a_r||^2 = Vh_n(:, r)^T V_n(:, r) (one wave per four columns), and the
-// Gram A_n^T A_n = Vh_n^T V_n.  Eight barriers per mode, none waiting on a
-// serial chain other than the inversion.
+// and M_n H_n.  Then T_n^{-1} = E^T D^{-1} E and the update of eq. (14):
+// Vh_n = H_n T_n^{-1} and V_n = U_n^T A_n = (M_n H_n) T_n^{-1}, normalized
+// by the column norms ||a_r||^2 = Vh_n(:, r)^T V_n(:, r) (16-lane DPP row
+// sums), and the Gram A_n^T A_n = Vh_n^T V_n.  Six or seven barriers per
+// mode, none waiting on a serial chain other than the elimination.
 constexpr int kA3Threads = 512;
 
 template <int K>
@@ -941,7 +942,7 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
   double* Ti = reinterpret_cast<double*>(smem + L::oTi);
   double* MH = reinterpret_cast<double*>(smem + L::oMH);
   // The MTTKRP steps run on waves 1-3 and 5-7 (worker u of NW = 384) while
-  // wave 0 inverts T; wave 4, which shares wave 0's SIMD when the waves are
+  // wave 0 factors T; wave 4, which shares wave 0's SIMD when the waves are
   // placed round-robin, only meets the barriers.  Each step ends with a
   // barrier that wave 0 matches (or takes part in with no items, at the
   // start).
@@ -1363,7 +1364,7 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
   int it = 0, converged = 0;
   for (it = 1; it <= a.max_it; ++it) {
     // one copy of each step in the code (the loop over the modes is kept).
-    // T_n needs only the other Grams, so wave 0 inverts it while waves
+    // T_n needs only the other Grams, so wave 0 factors it while waves
     // 1..7 form H_n; the barriers of the two sides pair up (the branch is
     // uniform per wave).
 #pragma unroll 1
