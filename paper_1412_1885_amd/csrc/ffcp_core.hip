@@ -1125,26 +1125,41 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
       ridged = 1;
     }
   };
-  // All waves: T^{-1} = E^T D^{-1} E, stored by columns: Ti[c][y] =
-  // sum_i E(i, y) E(i, c) / D_i.  Rows of the pair beyond R hold the last
-  // finishing pass's values, so the padding of Ti is written as zero.
-  auto ti_step = [&]() __attribute__((always_inline)) {
+  // T^{-1} = E^T D^{-1} E, stored by columns: Ti[c][y] = sum_i E(i, y)
+  // E(i, c) / D_i.  Rows of the pair beyond R hold the last finishing pass's
+  // values, so the padding of Ti is written as zero.
+  auto ti_entry = [&](int l) __attribute__((always_inline)) {
     constexpr int SP = L::SP;
     const double* Et = reinterpret_cast<const double*>(smem + L::oS);
     const double* EtD = Et + K * SP;
-    for (int l = t; l < KK; l += NT) {
-      const int y = l / K, c = l - y * K;
-      double a0 = 0.0, a1 = 0.0;
+    const int y = l / K, c = l - y * K;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < K; i += 2) {
-        const double2 e = *reinterpret_cast<const double2*>(Et + y * SP + i);
-        const double2 d = *reinterpret_cast<const double2*>(EtD + c * SP + i);
-        a0 = fma(e.x, d.x, a0);
-        a1 = fma(e.y, d.y, a1);
-      }
-      Ti[c * SP + y] = y < R && c < R ? a0 + a1 : 0.0;
+    for (int i = 0; i < K; i += 2) {
+      const double2 e = *reinterpret_cast<const double2*>(Et + y * SP + i);
+      const double2 d = *reinterpret_cast<const double2*>(EtD + c * SP + i);
+      a0 = fma(e.x, d.x, a0);
+      a1 = fma(e.y, d.y, a1);
     }
+    Ti[c * SP + y] = y < R && c < R ? a0 + a1 : 0.0;
+  };
+  // by all waves (the mode without a big step, where the elimination ends
+  // last)
+  auto ti_step = [&]() __attribute__((always_inline)) {
+    for (int l = t; l < KK; l += NT) ti_entry(l);
     __syncthreads();
+  };
+  // by waves 0 and 4 beside the small step (H = 0) and the M_n H step
+  // (H = 1), in a mode with a big step: wave 0's elimination ends before the
+  // big step does, and the two waves share a SIMD that the steps leave idle
+  static_assert(K * K <= 512, "two halves of 256 entries");
+  auto ti_half = [&](int h) __attribute__((always_inline)) {
+    const int u = (wave == 0 ? 0 : 64) + lane;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int l = 256 * h + 128 * r + u;
+      if (l < KK) ti_entry(l);
+    }
   };
   // Mode n after H_n, MH and Ti, in three passes over all waves.  First the
   // unnormalized Vr = H Ti (the coefficients Vh_n) and P = MH Ti (= M_n Vr,
@@ -1375,7 +1390,9 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
         eliminate_T(Gramn(n == 0 ? 1 : 0), Gramn(n == 2 ? 1 : 2), n == 1);
         if (n != 1) {
           __syncthreads();             // the big step's barrier
+          ti_half(0);
           __syncthreads();             // the small step's barrier
+          ti_half(1);
         }
         __syncthreads();               // the M_n H step's barrier
       } else {
@@ -1383,13 +1400,15 @@ void ffcp_als3_kernel(FfcpArgs a_arg) {
           big_step(std::false_type{}, Vn(2));   // X = G x_3 V_2
         else if (n == 2)
           big_step(std::true_type{}, Vn(1));    // Y = G x_2 V_1
+        if (n != 1 && wave == 4) ti_half(0);
         if (n == 0)
           small_step(std::true_type{}, Vn(1));  // H_0 = X x_2 V_1
         else
           small_step(std::false_type{}, Vn(0)); // H_1 = X x_1 V_0, H_2 = Y x_1 V_0
+        if (n != 1 && wave == 4) ti_half(1);
         mh_step(Mn(n));
       }
-      ti_step();
+      if (n == 1) ti_step();
       finish_mode(n, n < 2);
     }
     fit = fit_now(nrm2);
