@@ -438,10 +438,16 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
     ProfScope ps(kStageTruncate, s);
     EigBatch eb{};
     eb.nb = N;
+    static_assert(kBatchModes >= RT_MAX_MODES, "a batch holds every mode");
+    GramWavesBatch gb{};
+    gb.nb = N;
     int64_t Apre = 1;
     for (int n = 0; n < N; ++n) {
-      const int64_t Cpost = P.core / (Apre * P.K[n]);
-      RT_TRY(launch_gram_waves<T>(P.Gt, P.gram[n], Apre, P.K[n], Cpost, s));
+      gb.S[n] = P.gram[n];
+      gb.A[n] = Apre;
+      gb.I[n] = P.K[n];
+      gb.C[n] = P.core / (Apre * P.K[n]);
+      gb.first[n + 1] = gb.first[n] + P.K[n] * (P.K[n] + 1) / 2;
       Apre *= P.K[n];
       eb.S[n] = P.gram[n];
       eb.W[n] = P.W[n];
@@ -449,20 +455,31 @@ int tucker_run(const rt_tucker_desc* d, const void* Yv, const void* const* Om,
       eb.n[n] = P.K[n];
       eb.k[n] = P.Rn[n];
     }
+    RT_TRY(launch_gram_waves_batch<T>(P.Gt, gb, s));
     RT_TRY(launch_eig(eb, s));
+    // U_n = Q_n W_n for every mode, and the FP32 copies of W_n, in one launch
     const T* WT[RT_MAX_MODES];
+    MatWBatch<T> mb{};
+    mb.nb = N;
     for (int n = 0; n < N; ++n) {
-      RT_TRY(launch_matmul_w<T>(P.Q[n], P.W[n], static_cast<T*>(Uout[n]),
-                                P.I[n], P.K[n], P.Rn[n], s));
+      mb.Q[n] = P.Q[n];
+      mb.W[n] = P.W[n];
+      mb.out[n] = static_cast<T*>(Uout[n]);
+      mb.I[n] = P.I[n];
+      mb.K[n] = P.K[n];
+      mb.J[n] = P.Rn[n];
+      mb.first[n + 1] = mb.first[n] + P.I[n] * P.Rn[n];
       if (sizeof(T) == sizeof(double)) {
+        mb.WT[n] = nullptr;
+        mb.wfirst[n + 1] = mb.wfirst[n];
         WT[n] = reinterpret_cast<const T*>(P.W[n]);
       } else {
-        RT_TRY((launch_convert<double, float>(
-            P.W[n], reinterpret_cast<float*>(P.WT[n]),
-            static_cast<int64_t>(P.K[n]) * P.Rn[n], s)));
+        mb.WT[n] = reinterpret_cast<float*>(P.WT[n]);
+        mb.wfirst[n + 1] = mb.wfirst[n] + static_cast<int64_t>(P.K[n]) * P.Rn[n];
         WT[n] = P.WT[n];
       }
     }
+    RT_TRY(launch_matmul_w_batch<T>(mb, s));
     int64_t D[RT_MAX_MODES];
     for (int p = 0; p < N; ++p) D[p] = P.K[p];
     int modes[RT_MAX_MODES];
@@ -843,10 +860,15 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
     int64_t Apre = 1;
     EigBatch eb{};
     eb.nb = N;
+    GramWavesBatch gb{};
+    gb.nb = N;
     for (int n = 0; n < N; ++n) {
       const int Rn = desc->ranks[n];
-      const int64_t Cpost = core / (Apre * Rn);
-      RT_TRY(launch_gram_waves<float>(G, P.hgram[n], Apre, Rn, Cpost, s));
+      gb.S[n] = P.hgram[n];
+      gb.A[n] = Apre;
+      gb.I[n] = Rn;
+      gb.C[n] = core / (Apre * Rn);
+      gb.first[n + 1] = gb.first[n] + Rn * (Rn + 1) / 2;
       Apre *= Rn;
       eb.S[n] = P.hgram[n];
       eb.W[n] = P.hgram[n];
@@ -854,6 +876,7 @@ int rt_ffcp(const rt_ffcp_desc* desc, const float* const* U, const float* G,
       eb.n[n] = Rn;
       eb.k[n] = R < Rn ? R : Rn;
     }
+    RT_TRY(launch_gram_waves_batch<float>(G, gb, s));
     RT_TRY(launch_eig(eb, s));
     for (int n = 0; n < N; ++n) {
       const int Rn = desc->ranks[n];

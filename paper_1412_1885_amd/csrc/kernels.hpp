@@ -7,6 +7,9 @@
 
 namespace rt {
 
+// modes per batched launch (at least the library's largest N)
+constexpr int kBatchModes = 8;
+
 // ---- generic mode-n product (ttm.hip) ------------------------------------
 // out[a, k, c] = sum_i X[a, i, c] * M[i, k];  X: [A, I, C], M: I x K.
 template <typename T>
@@ -40,6 +43,18 @@ int launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t s);
 template <typename T>
 int launch_gram_waves(const T* X, double* S, int64_t A, int I, int64_t C,
                       hipStream_t s);
+// The same for several views of one X in one launch: S[m] for the view
+// [A[m], I[m], C[m]]; first[m] numbers mode m's upper-triangle entries
+// (first[nb] is the total).
+struct GramWavesBatch {
+  double* S[kBatchModes];
+  int64_t A[kBatchModes], C[kBatchModes];
+  int I[kBatchModes];
+  int first[kBatchModes + 1];
+  int nb;
+};
+template <typename T>
+int launch_gram_waves_batch(const T* X, const GramWavesBatch& b, hipStream_t s);
 // out[a, k, c] = sum_i X[a, i, c] M[i, k] for C <= 64, K <= 64.
 template <typename T>
 int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
@@ -54,6 +69,24 @@ int launch_gram_unfold(const T* X, double* S, int64_t A, int I, int64_t C,
 template <typename T>
 int launch_matmul_w(const T* Q, const double* W, T* out, int64_t I, int K,
                     int J, hipStream_t s);
+
+// Several modes in one launch: out[m] = Q[m] W[m] as in launch_matmul_w,
+// then WT[m] = float(W[m]) (K[m] x J[m]) where WT[m] is set.  first[m] and
+// wfirst[m] number the elements of each mode's product and copy (first[nb]
+// and wfirst[nb] are the totals).
+template <typename T>
+struct MatWBatch {
+  const T* Q[kBatchModes];
+  const double* W[kBatchModes];
+  T* out[kBatchModes];
+  float* WT[kBatchModes];
+  int64_t I[kBatchModes];
+  int K[kBatchModes], J[kBatchModes];
+  int64_t first[kBatchModes + 1], wfirst[kBatchModes + 1];
+  int nb;
+};
+template <typename T>
+int launch_matmul_w_batch(const MatWBatch<T>& b, hipStream_t s);
 
 // partial[b] = sum of squares (FP64) over a grid-stride slice; flag |= !finite.
 // Then out[0] = sum partials (fixed order).  n elements of T.

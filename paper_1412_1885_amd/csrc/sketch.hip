@@ -341,11 +341,9 @@ __global__ void transpose_kernel(const T* __restrict__ in, T* __restrict__ out,
 // S = X_(n) X_(n)^T in FP64 for X viewed [A, I, C]; one wavefront per
 // entry of the upper triangle (lanes stride the (a, c) pairs).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void gram_waves_kernel(
-    const T* __restrict__ X, double* __restrict__ S, int64_t A, int I, int64_t C) {
-  const int lane = threadIdx.x & 63;
-  const int pair = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (pair >= I * (I + 1) / 2) return;
+__device__ __forceinline__ void gram_wave_entry(const T* __restrict__ X,
+                                                double* __restrict__ S, int64_t A,
+                                                int I, int64_t C, int pair, int lane) {
   int o = pair, r = 0;
   while (o >= I - r) {
     o -= I - r;
@@ -375,6 +373,25 @@ __global__ __launch_bounds__(kThreads) void gram_waves_kernel(
     S[r * I + c2] = acc;
     S[c2 * I + r] = acc;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gram_waves_kernel(
+    const T* __restrict__ X, double* __restrict__ S, int64_t A, int I, int64_t C) {
+  const int pair = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (pair >= I * (I + 1) / 2) return;
+  gram_wave_entry(X, S, A, I, C, pair, threadIdx.x & 63);
+}
+
+// the batch: the wave's entry picks its mode (uniform per wave)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gram_waves_batch_kernel(const T* __restrict__ X,
+                                                                    GramWavesBatch b) {
+  const int q = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (q >= b.first[b.nb]) return;
+  int m = 0;
+  while (m + 1 < b.nb && q >= b.first[m + 1]) ++m;
+  gram_wave_entry(X, b.S[m], b.A[m], b.I[m], b.C[m], q - b.first[m], threadIdx.x & 63);
 }
 
 }  // namespace
@@ -506,6 +523,20 @@ int launch_gram_waves(const T* X, double* S, int64_t A, int I, int64_t C,
 }
 
 template <typename T>
+int launch_gram_waves_batch(const T* X, const GramWavesBatch& b, hipStream_t s) {
+  if (b.nb < 1 || b.nb > kBatchModes) {
+    set_error("gram batch of %d views", b.nb);
+    return kErrUnsupported;
+  }
+  const int total = b.first[b.nb];
+  if (total <= 0) return kOk;
+  hipLaunchKernelGGL(gram_waves_batch_kernel<T>, dim3((total + 3) / 4), dim3(kThreads),
+                     0, s, X, b);
+  RT_LAUNCH_CHECK("gram_waves_batch");
+  return kOk;
+}
+
+template <typename T>
 int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
                        int C, int K, hipStream_t s) {
   if (C > 64 || K > 64) {
@@ -533,7 +564,9 @@ int launch_ttm_small_c(const T* X, const T* M, T* out, int64_t A, int64_t I,
                                      int, int, hipStream_t);                    \
   template int launch_transpose<T>(const T*, T*, int64_t, int64_t, hipStream_t); \
   template int launch_gram_waves<T>(const T*, double*, int64_t, int, int64_t,   \
-                                    hipStream_t);
+                                    hipStream_t);                               \
+  template int launch_gram_waves_batch<T>(const T*, const GramWavesBatch&,      \
+                                          hipStream_t);
 RT_INST(float)
 RT_INST(double)
 #undef RT_INST

@@ -167,6 +167,33 @@ __global__ __launch_bounds__(kThreads) void matmul_w_kernel(
   out[idx] = static_cast<T>(acc);
 }
 
+// the batch: products first, then the FP32 copies of W
+template <typename T>
+__global__ __launch_bounds__(kThreads) void matmul_w_batch_kernel(MatWBatch<T> b) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < b.first[b.nb]) {
+    int m = 0;
+    while (m + 1 < b.nb && idx >= b.first[m + 1]) ++m;
+    const int64_t e = idx - b.first[m];
+    const int J = b.J[m], K = b.K[m];
+    const int64_t i = e / J;
+    const int j = static_cast<int>(e % J);
+    const T* __restrict__ Q = b.Q[m];
+    const double* __restrict__ W = b.W[m];
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) acc += static_cast<double>(Q[i * K + k]) * W[k * J + j];
+    b.out[m][e] = static_cast<T>(acc);
+    return;
+  }
+  const int64_t w = idx - b.first[b.nb];
+  if (w >= b.wfirst[b.nb]) return;
+  int m = 0;
+  while (m + 1 < b.nb && w >= b.wfirst[m + 1]) ++m;
+  const int64_t e = w - b.wfirst[m];
+  b.WT[m][e] = static_cast<float>(b.W[m][e]);
+}
+
 template <typename T>
 __device__ __forceinline__ double sq_val(T x) {
   double d = static_cast<double>(x);
@@ -353,6 +380,21 @@ int launch_matmul_w(const T* Q, const double* W, T* out, int64_t I, int K,
   return kOk;
 }
 
+template <typename T>
+int launch_matmul_w_batch(const MatWBatch<T>& b, hipStream_t s) {
+  if (b.nb < 1 || b.nb > kBatchModes) {
+    set_error("matmul_w batch of %d modes", b.nb);
+    return kErrUnsupported;
+  }
+  const int64_t total = b.first[b.nb] + b.wfirst[b.nb];
+  if (total <= 0) return kOk;
+  hipLaunchKernelGGL(matmul_w_batch_kernel<T>,
+                     dim3(static_cast<unsigned>(ceil_div(total, kThreads))), dim3(kThreads),
+                     0, s, b);
+  RT_LAUNCH_CHECK("matmul_w_batch");
+  return kOk;
+}
+
 int norm2_blocks() { return 1024; }
 
 template <typename T>
@@ -398,6 +440,7 @@ int launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s) {
                                      hipStream_t);                              \
   template int launch_matmul_w<T>(const T*, const double*, T*, int64_t, int,   \
                                   int, hipStream_t);                            \
+  template int launch_matmul_w_batch<T>(const MatWBatch<T>&, hipStream_t);      \
   template int launch_norm2<T>(const T*, int64_t, double*, int, double*,       \
                                int32_t*, hipStream_t);
 RT_INST(float)
